@@ -1,0 +1,69 @@
+"""Input generator: geometry of the node cloud and stencil selection (CPU)."""
+import numpy as np
+import pytest
+
+import nodecloud as nc
+
+
+def test_boundary_nodes_on_sphere(small_cloud):
+    c = small_cloud
+    b = c.pos[c.n_int:]
+    assert np.abs(nc.sphere_sdf(b, c.r)).max() < 1e-12
+    d = nc.min_image(b - 0.5)
+    # unit normals, radial, pointing out of the solid
+    assert np.allclose(np.linalg.norm(c.nrm, axis=1), 1.0, atol=1e-12)
+    assert np.allclose(c.nrm, d / c.r, atol=1e-12)
+
+
+def test_interior_in_fluid_and_spacing(small_cloud):
+    c = small_cloud
+    assert (nc.sphere_sdf(c.pos[:c.n_int], c.r) > 0).all()
+    from scipy.spatial import cKDTree
+    d, _ = cKDTree(c.pos, boxsize=1.0).query(c.pos, k=2)
+    # exclusion radius 0.999 min(h) with h >= 0.02 everywhere; boundary spacing ~1.07 h
+    assert d[:, 1].min() > 0.8 * 0.02
+
+
+def test_deterministic_under_seed():
+    a = nc.sphere_cloud(0.25, 0.04, 0.3, 0.1, seed=11)
+    b = nc.sphere_cloud(0.25, 0.04, 0.3, 0.1, seed=11)
+    c = nc.sphere_cloud(0.25, 0.04, 0.3, 0.1, seed=12)
+    assert np.array_equal(a.pos, b.pos) and a.n_int == b.n_int
+    assert a.n != c.n or not np.array_equal(a.pos, c.pos)
+
+
+def test_knn_matches_brute_force():
+    c = nc.sphere_cloud(0.3, 0.05, 0.3, 0.12, seed=3)
+    assert 500 < c.n < 5000
+    S = nc.stencils(c.pos, 30)
+    d = nc.min_image(c.pos[:, None, :] - c.pos[None, :, :])
+    dist = np.sqrt((d * d).sum(-1))
+    for i in range(0, c.n, 7):
+        order = np.lexsort((np.arange(c.n), dist[i]))
+        assert S[i, 0] == i
+        # same set and same sorted distances as brute force
+        assert np.allclose(np.sort(dist[i][S[i]]), dist[i][order[:30]], rtol=0, atol=1e-15)
+
+
+def test_neumann_stencils_interior_only(small_cloud):
+    Sn = nc.neumann_stencils(small_cloud, 30)
+    assert Sn.shape == (small_cloud.n_bnd, 30)
+    assert np.array_equal(Sn[:, 0], np.arange(small_cloud.n_int, small_cloud.n))
+    assert (Sn[:, 1:] < small_cloud.n_int).all()
+
+
+def test_workload_node_counts():
+    c = nc.config_cloud("acm_small")
+    assert 6000 < c.n < 10000
+    # porosity-weighted count: the fill is denser near the grain
+    assert c.n_bnd > 0.2 * c.n
+
+
+def test_plane_plan(small_cloud):
+    pp = nc.plane_plan(small_cloud, 32, 30)
+    assert (nc.sphere_sdf(pp.pts, small_cloud.r) > 0).all()
+    assert np.allclose(nc.min_image(pp.pts - small_cloud.pos[pp.idx[:, 0]]), pp.shift)
+    # the first stencil column is the nearest node of the sample
+    d = nc.min_image(pp.pts[:, None, :] - small_cloud.pos[pp.idx])
+    dist = np.sqrt((d * d).sum(-1))
+    assert (np.diff(dist, axis=1) >= -1e-15).all()

@@ -1,0 +1,107 @@
+"""Oracle ACM Navier-Stokes step (Sec. 2.3) pinned by closed forms."""
+import numpy as np
+import pytest
+
+import nodecloud as nc
+import oracle as O
+from oracle.steady import steady_solve
+
+
+@pytest.fixture(scope="module")
+def channel():
+    c = nc.channel_cloud(0.1, 0.5, seed=0)
+    S = nc.stencils(c.pos, 30)
+    Sn = nc.neumann_stencils(c, 30)
+    return c, S, Sn
+
+
+def poiseuille(c, H=0.5, g=1.0, nu=1.0):
+    z = c.pos[:, 2]
+    u = g * z * (H - z) / (2.0 * nu)
+    u[c.n_int:] = 0.0
+    return u
+
+
+def test_poiseuille_is_a_fixed_point(channel):
+    """Weights are exact on quadratics, so the plane Poiseuille profile, with
+    constant pressure, is reproduced exactly by every term of the step."""
+    c, S, Sn = channel
+    a = O.ACM(c.pos, c.n_int, S, c.nrm, sten_n=Sn, h_min=0.05, v_ref=1e-3)
+    u = poiseuille(c)
+    a.v[:, 0] = u
+    a.run(50)
+    assert np.abs(a.v[:, 0] - u).max() < 1e-12 * u.max()
+    assert np.abs(a.v[:, 1:]).max() < 1e-12 * u.max()
+    assert np.ptp(a.p) < 1e-10
+
+
+def test_direct_steady_solve_gives_poiseuille(channel):
+    c, S, Sn = channel
+    w, _ = O.weights(c.pos, S, [("dx",), ("dy",), ("dz",), ("lap",)])
+    wn, _ = O.weights(c.pos, Sn, [("dn",)], rowvec=c.nrm)
+    v, p, kappa = steady_solve(c.n_int, S, w, Sn, wn[:, 0, :])
+    u = poiseuille(c)
+    assert np.abs(v[:, 0] - u).max() < 1e-11 * u.max()
+    assert abs(kappa) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def box():
+    """Periodic fill without a grain, and the nodes whose whole stencil sits
+    away from the periodic seam (there a polynomial field is single-valued)."""
+    c = nc.sphere_cloud(0.0, 0.05, 0.0, 0.05, seed=5)
+    S = nc.stencils(c.pos, 30)
+    d_raw = c.pos[S] - c.pos[S[:, :1]]
+    safe = np.all(np.abs(d_raw - nc.min_image(d_raw)) < 1e-12, axis=(1, 2))
+    return c, S, safe
+
+
+def test_predictor_terms_exact_on_quadratics(box):
+    """With beta = 0 the coupling is inert and one step is the intermediate
+    velocity of Eq. MNS_intermediate; for v = (Y^2, Z^2, X^2) the Laplacian
+    and the gradients are exact, so v' has a closed form."""
+    c, S, safe = box
+    X, Y, Z = (c.pos - 0.5).T
+    g = np.array([0.7, -0.2, 0.1])
+    a = O.ACM(c.pos, c.n, S, np.zeros((0, 3)), dt=1e-4, nu=0.9, beta=0.0, v_ref=1.0, g=g, n_p=1)
+    a.v[:] = np.stack([Y * Y, Z * Z, X * X], 1)
+    v0 = a.v.copy()
+    a.run(1)
+    lap = np.array([2.0, 2.0, 2.0])
+    adv = np.stack([Z * Z * 2 * Y, X * X * 2 * Z, Y * Y * 2 * X], 1)  # (v . grad) v
+    expect = v0 + 1e-4 * (0.9 * lap - adv + g)
+    assert safe.sum() > 100
+    assert np.abs(a.v[safe] - expect[safe]).max() < 1e-13
+
+
+def test_pressure_gradient_exact_on_quadratics(box):
+    """From rest, without forcing, one coupling iteration turns a quadratic
+    pressure q into v = -(dt/rho) grad q (Eq. MNS_velocity) and leaves p
+    unchanged (Eq. MNS_pressure with div v' = 0)."""
+    c, S, safe = box
+    X, Y, Z = (c.pos - 0.5).T
+    a = O.ACM(c.pos, c.n, S, np.zeros((0, 3)), dt=2e-4, rho=1.3, g=(0, 0, 0), n_p=1)
+    q = X * X + X * Y - 0.5 * Z * Z
+    a.p[:] = q
+    a.run(1)
+    gq = np.stack([2 * X + Y, X, -Z], 1)
+    assert np.abs(a.v[safe] + 2e-4 / 1.3 * gq[safe]).max() < 1e-14
+    assert np.array_equal(a.p, q)
+    # Eq. MNS_C from the new velocity
+    assert a.C[0] == pytest.approx(10.0 * max(np.linalg.norm(a.v, axis=1).max(), 1.0), rel=1e-15)
+
+
+def test_rest_without_force_stays_at_rest(small_cloud, small_stencils):
+    c, S = small_cloud, small_stencils
+    a = O.ACM(c.pos, c.n_int, S, c.nrm, sten_n=nc.neumann_stencils(c, 30), h_min=0.02, g=(0, 0, 0))
+    a.run(5)
+    assert not a.v.any() and not a.p.any()
+
+
+def test_time_steps_match_paper_footnotes():
+    rows = [l.split() for l in open(__file__.replace("test_oracle_acm.py", "golden/timestep_paper.txt"))
+            if l.strip() and not l.startswith("#")]
+    for solver, h, dt, tol in rows:
+        h, dt, tol = float(h), float(dt), float(tol)
+        got = O.acm_dt(h, 1.0) if solver == "acm" else O.lbm_units(h, 1.0, 1.0, (0, 0, 0), 1.0)["dt"]
+        assert abs(got - dt) <= tol * dt, (solver, h, got, dt)

@@ -1,0 +1,111 @@
+"""Oracle geometry, permeability and drag reductions pinned by closed forms,
+the divergence theorem and brute force."""
+import os
+
+import numpy as np
+import pytest
+
+import nodecloud as nc
+import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_porosity_matches_paper_pairs():
+    for line in open(os.path.join(GOLD, "porosity_paper.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        r, phi, tol = map(float, line.split())
+        assert abs(O.porosity(r) - phi) <= tol, (r, O.porosity(r), phi)
+
+
+@pytest.mark.parametrize("r", [0.3, 0.55, 0.65])
+def test_porosity_and_area_brute_force(r):
+    rng = np.random.default_rng(7)
+    x = rng.uniform(size=(2_000_000, 3))
+    phi_mc = (nc.sphere_sdf(x, r) > 0).mean()
+    assert O.porosity(r) == pytest.approx(phi_mc, abs=2e-3)
+    # area: uniform points on the sphere, fraction that is not covered by an image
+    u = rng.normal(size=(1_000_000, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    p = 0.5 + r * u
+    inside = np.all((p >= 0) & (p < 1), axis=1)
+    assert O.area(r) == pytest.approx(4 * np.pi * r * r * inside.mean(), rel=3e-3)
+
+
+@pytest.fixture(scope="module")
+def plan_small(small_cloud):
+    pp = nc.plane_plan(small_cloud, 64, 30)
+    pw = O.plane_weights(small_cloud.pos, pp.idx, pp.shift)
+    return pp, pw
+
+
+def test_flux_of_uniform_field(small_cloud, plan_small):
+    """v_x = 1 in the fluid: interpolation reproduces constants, so q is the
+    fraction of fluid samples, and that tends to the mean open fraction of the
+    five planes: (1 + 1 + (1 - pi(r^2 - 0.01))*2 + 1)/5 for r = 0.3."""
+    pp, pw = plan_small
+    q = O.flux(pp.idx, pw, np.ones(small_cloud.n), 5 * 64 * 64)
+    assert q == pytest.approx(pp.n_samples / (5 * 64 * 64), rel=1e-13)
+    r = small_cloud.r
+    open_frac = [1.0 if abs(x - 0.5) >= r else 1.0 - np.pi * (r * r - (x - 0.5) ** 2) for x in pp.planes]
+    assert q == pytest.approx(np.mean(open_frac), abs=2e-3)
+
+
+def test_flux_of_linear_field(small_cloud, plan_small):
+    """A field linear in y and z is interpolated exactly; its plane integral is
+    the sum over the fluid samples of the field at the sample points."""
+    pp, pw = plan_small
+    a, b, c0 = 0.3, -0.7, 1.1
+    X = small_cloud.pos - 0.5
+    vx = c0 + a * X[:, 1] + b * X[:, 2]
+    # only linear fields that are single-valued across the seam: none are, so
+    # compare sample by sample using the minimum-image offsets of each stencil
+    num = 0.0
+    for s in range(pp.n_samples):
+        d = nc.min_image(small_cloud.pos[pp.idx[s]] - pp.pts[s])
+        vals = c0 + a * (pp.pts[s, 1] - 0.5 + d[:, 1]) + b * (pp.pts[s, 2] - 0.5 + d[:, 2])
+        num += pw[s] @ vals
+    expect = (c0 + a * (pp.pts[:, 1] - 0.5) + b * (pp.pts[:, 2] - 0.5)).sum() / (5 * 64 * 64)
+    assert num / (5 * 64 * 64) == pytest.approx(expect, rel=1e-12)
+
+
+@pytest.fixture(scope="module")
+def grad_bnd(small_cloud, small_stencils):
+    c, S = small_cloud, small_stencils
+    w, _ = O.weights(c.pos, S[c.n_int:], [("dx",), ("dy",), ("dz",)])
+    return w
+
+
+def test_drag_of_linear_pressure(small_cloud, small_stencils, grad_bnd):
+    """p = -G x, v = 0: F = -oint p n dA = G V_sphere (divergence theorem)."""
+    c, S = small_cloud, small_stencils
+    X = nc.min_image(c.pos - 0.5)
+    G = 2.5
+    F = O.drag(S[c.n_int:], grad_bnd, c.nrm, np.zeros((c.n, 3)), -G * X[:, 0], 1.0, 1.0, O.area(c.r) / c.n_bnd)
+    V = 4.0 / 3.0 * np.pi * c.r ** 3
+    assert F[0] == pytest.approx(G * V, rel=2e-4)
+    assert abs(F[1]) < 1e-4 * G * V and abs(F[2]) < 1e-4 * G * V
+
+
+def test_drag_of_shear_field(small_cloud, small_stencils, grad_bnd):
+    """v = (z^2, 0, 0), p = 0: sigma_xz = sigma_zx = 2 rho nu z, so
+    F_x = oint 2 rho nu z n_z dA = 2 rho nu V (divergence theorem)."""
+    c, S = small_cloud, small_stencils
+    X = nc.min_image(c.pos - 0.5)
+    v = np.zeros((c.n, 3))
+    v[:, 0] = X[:, 2] ** 2
+    rho, nu = 1.2, 0.7
+    F = O.drag(S[c.n_int:], grad_bnd, c.nrm, v, np.zeros(c.n), rho, nu, O.area(c.r) / c.n_bnd)
+    V = 4.0 / 3.0 * np.pi * c.r ** 3
+    assert F[0] == pytest.approx(2 * rho * nu * V, rel=5e-4)
+
+
+def test_drag_ignores_pressure_gauge(small_cloud, small_stencils, grad_bnd):
+    c, S = small_cloud, small_stencils
+    rng = np.random.default_rng(0)
+    p = rng.normal(size=c.n)
+    dA = O.area(c.r) / c.n_bnd
+    F1 = O.drag(S[c.n_int:], grad_bnd, c.nrm, np.zeros((c.n, 3)), p, 1.0, 1.0, dA)
+    F2 = O.drag(S[c.n_int:], grad_bnd, c.nrm, np.zeros((c.n, 3)), p + 123.0, 1.0, 1.0, dA)
+    assert np.abs(F1 - F2).max() < 1e-9
