@@ -1,0 +1,155 @@
+"""Throughput of the meshless LBM time loop on one MI355X.
+
+Workload: the meshless D3Q19 TRT lattice-Boltzmann cell -- one sphere of
+radius 0.3 centred in the unit periodic simple-cubic cell, about 71k nodes
+with spacing h(d) = min(0.008 + 0.16 d, 0.04), 30-node RBF-FD interpolation
+stencils, Lambda = 1/4 with tau+ = 1, unit body force along x.  A step is one
+time step of the solver (stream by interpolation, bounce-back, TRT collision)
+with the permeability reduction every 100 steps, all on the GPU; weights are
+set-up work and are timed separately.
+
+Prints one JSON line: FP32 (shifted populations, FP64 reductions) node-steps/s
+as the value, the FP64 path beside it, the roofline of the step kernel and the
+CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RBF-FD node-steps/s (FP64 vs FP32); time-to-steady permeability at 1e-3 rel"
+HBM_PEAK_GBS = 8000.0
+CHECK_EVERY = 100
+
+
+def bytes_per_node_step(q, nl, s_w, s_f, s_i=4):
+    """Algorithmic HBM bytes of one MLBM node-step: the q-1 interpolation
+    weight rows and the stencil indices streamed once, the q populations read
+    once (gathers of neighbours hit the caches) and written once."""
+    return (q - 1) * s_w * nl + s_i * nl + 2 * q * s_f
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
+                                   "note only)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import nodecloud as nc
+    from paper_2404_14195_amd import MPF_F32, MPF_F64, api
+    from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    cloud = nc.config_cloud("lbm_mid")
+    disc = Discretization(cloud, nl=30, M=64)
+    print(f"[bench] cloud {cloud.n} nodes ({cloud.n_bnd} on the grain), setup {time.perf_counter() - t_setup:.1f}s",
+          file=sys.stderr, flush=True)
+
+    res = {}
+    for name, prec in (("f32", MPF_F32), ("f64", MPF_F64)):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        s = MLBMSolver(disc, q=19, precision=prec)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_weights = ev0.elapsed_time(ev1)
+        v = torch.empty((3, disc.n), dtype=torch.float64, device="cuda")
+        p = torch.empty(disc.n, dtype=torch.float64, device="cuda")
+        qd = torch.empty(1, dtype=torch.float64, device="cuda")
+
+        def loop(n_steps):
+            done = 0
+            while done < n_steps:
+                k = min(CHECK_EVERY, n_steps - done)
+                s.run(k)
+                done += k
+                if done % CHECK_EVERY == 0:
+                    api.lbm_moments(s.prm, s.f, s.units["vel_scale"], v, p)
+                    api.flux_planes(disc.s_idx, disc.s_w, v[0], disc.n_all, q_out=qd, ws=disc.red_ws)
+
+        loop(args.warmup)
+        torch.cuda.synchronize()
+        ev0.record()
+        t0 = time.perf_counter()
+        loop(args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        # the step kernel alone: one run() of CHECK_EVERY steps launches one
+        # collide, CHECK_EVERY - 1 fused step kernels and one stream kernel
+        reps = max(1, min(10, args.steps // CHECK_EVERY))
+        ev0.record()
+        for _ in range(reps):
+            s.run(CHECK_EVERY)
+        ev1.record()
+        torch.cuda.synchronize()
+        step_ms = ev0.elapsed_time(ev1) / (reps * CHECK_EVERY)
+        k_perm = s.permeability()
+        res[name] = dict(ms_per_step=ms / args.steps, wall_s=wall, value=disc.n * args.steps / (ms * 1e-3),
+                         step_kernel_ms=step_ms, weights_ms=t_weights, k=k_perm, steps_total=s.steps)
+        print(f"[bench] {name}: {ms / args.steps * 1e3:.2f} us/step, {res[name]['value']:.3e} node-steps/s, "
+              f"k={k_perm:.6e}", file=sys.stderr, flush=True)
+        del s
+        torch.cuda.empty_cache()
+
+    f32 = res["f32"]
+    bpn = bytes_per_node_step(19, 30, 4, 4)
+    achieved = bpn * disc.n / (f32["step_kernel_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "lbm_step<float,19,true>", "bytes_per_node_step": bpn,
+            "launch_ms": f32["step_kernel_ms"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        o = O.MLBM(cloud.pos, cloud.n_int, disc.sten_host, cloud.nrm, q=19, h_min=cloud.h_min)
+        t0 = time.perf_counter()
+        o.run(2)
+        per = (time.perf_counter() - t0) / 2
+        n_cpu = max(2, int(args.cpu_seconds / per))
+        t0 = time.perf_counter()
+        o.run(n_cpu)
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": cloud.n * n_cpu / dt_cpu, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_cpu} FP64 steps of the full {cloud.n}-node cell (weights precomputed, not timed), "
+                         f"single-threaded scalar C"}
+
+    out = {
+        "metric": METRIC, "value": f32["value"], "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f32["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mlbm_d3q19_trt_sc_sphere_r0.3", "n_nodes": cloud.n, "n_boundary": cloud.n_bnd,
+                   "nl": 30, "q": 19, "h": "min(0.008+0.16d,0.04)", "tau_plus": 1.0, "magic": 0.25,
+                   "check_every": CHECK_EVERY, "precision": "fp32 shifted populations, fp64 reductions"},
+        "fp64": {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],
+                 "step_kernel_ms": res["f64"]["step_kernel_ms"],
+                 "roofline_frac": bytes_per_node_step(19, 30, 8, 8) * disc.n / (res["f64"]["step_kernel_ms"] * 1e-3)
+                 / 1e9 / HBM_PEAK_GBS},
+        "k": {"fp32": f32["k"], "fp64": res["f64"]["k"], "rel_err_fp32": abs(f32["k"] / res["f64"]["k"] - 1.0),
+              "steps": f32["steps_total"]},
+        "weights_ms": {"fp32": f32["weights_ms"], "fp64": res["f64"]["weights_ms"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * mpf.h -- C ABI of libmpf, the MI355X (gfx950) library for the hot path of the
+ * meshless pore-flow solvers of Strzelczyk, Rot, Kosec and Matyka,
+ * "Cross-validation of meshless Navier-Stokes solvers in porous media flows"
+ * (arXiv 2404.14195).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays named "dev" are device pointers (memory of the current HIP device);
+ *   arrays named "host" are host pointers.  The caller owns all memory: the
+ *   library never allocates or frees caller buffers.  Scratch memory is passed
+ *   in as a caller-owned workspace whose size the matching *_workspace call
+ *   reports.
+ * - Every call is asynchronous on the caller's stream (a hipStream_t passed as
+ *   void*; NULL is the default stream).  Scalar results are written to device
+ *   memory.  Host-side argument checks happen before any launch.
+ * - Return value: MPF_OK (0) or a negative MPF_ERR_* code; mpf_strerror()
+ *   names it.  No C++ exception crosses the ABI.
+ * - Layouts are structure-of-arrays with the node index fastest:
+ *     positions        pos[3][n]          double
+ *     stencils         sten[nl][m]        int32, column 0 = the row's centre
+ *     weights          w[n_ops][nl][m]    double or float
+ *     velocity         v[3][n]            double or float (precision flag)
+ *     populations      f[q][n]            double or float, stored shifted by
+ *                                         the lattice weight: f~_k = f_k - w_k
+ * - Nodes [0, n_int) are interior; nodes [n_int, n) lie on the grain surface,
+ *   with unit normals nrm[3][nb] (nb = n - n_int) pointing from the solid into
+ *   the fluid.
+ * - Velocity sets (both follow the pairing of the paper's D3Q15 table, Sec.
+ *   2.2: k = 0 rest, odd k a listed vector, even k = the opposite of k - 1):
+ *     D3Q15 odd k = 1..13: (1,0,0) (0,1,0) (0,0,1) (1,1,1) (1,1,-1) (1,-1,1)
+ *                          (1,-1,-1); weights 2/9, 1/9, 1/72
+ *     D3Q19 odd k = 1..17: (1,0,0) (0,1,0) (0,0,1) (1,1,0) (1,-1,0) (1,0,1)
+ *                          (1,0,-1) (0,1,1) (0,1,-1); weights 1/3, 1/18, 1/36
+ */
+#ifndef MPF_H
+#define MPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPF_OK 0
+#define MPF_ERR_ARG (-1)         /* invalid argument (host check, nothing launched) */
+#define MPF_ERR_HIP (-2)         /* a HIP runtime call failed */
+#define MPF_ERR_UNSUPPORTED (-3) /* valid but not built: e.g. a stencil size without a kernel */
+#define MPF_ERR_WORKSPACE (-4)   /* workspace missing or too small */
+
+/* precision of fields and stencil weights */
+#define MPF_F64 0
+#define MPF_F32 1
+
+/* Static description of an error code; never NULL. */
+const char* mpf_strerror(int code);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int mpf_version(void);
+
+/* ------------------------------------------------------------- geometry
+ * Porosity and grain-surface area of the periodic simple-cubic cell of side
+ * 1 holding one sphere of radius r at its centre (Sec. 2.4; A enters
+ * Delta A = A / N_b of Eq. integration_force).  For r > 1/2 the six caps that
+ * leave the cell are removed.  Host-only; valid for 0 <= r < sqrt(2)/2,
+ * otherwise MPF_ERR_ARG. */
+int mpf_sc_cell(double r, double* porosity_host, double* area_host);
+
+/* ------------------------------------------------------------- RBF-FD weights
+ * Weights w of Eq. operatorApprox for m stencil rows, from the augmented
+ * polyharmonic system of Eq. augmentedSystem: PHS r^3 plus the ten monomials
+ * 1, x, y, z, x^2, xy, xz, y^2, yz, z^2, all in coordinates centred on the
+ * row's centre c = sten[0][i] and scaled by delta_i = |x_{sten[1][i]} - x_c|
+ * (Eq. rbfScaling; with nearest-first stencils the nearest-neighbour
+ * distance).  Each system (size nl + 10) is solved in FP64 by Gaussian
+ * elimination with partial pivoting; the Lagrange part is discarded.
+ *
+ * Operators (mpf_op.kind):                          right-hand side for
+ *   MPF_OP_DX, _DY, _DZ   d/dx_a                    b_j = L |x - x_j|^3 at c,
+ *   MPF_OP_LAP            Laplacian                 c_l = L p_l at c
+ *   MPF_OP_DIR            vec . grad
+ *   MPF_OP_SHIFT          value at c + vec          (L = 1 at a shifted point)
+ *   MPF_OP_DN             rowvec_i . grad           (rowvec: dev [3][m])
+ *   MPF_OP_SHIFT_ROW      value at c + rowvec_i
+ *
+ * pos      dev [3][n_nodes] double, in the unit periodic cell (displacements
+ *          use the minimum image)
+ * sten     dev [nl][m] int32, entries in [0, n_nodes) (not checked on device)
+ * ops      host [n_ops], 1 <= n_ops <= 32
+ * rowvec   dev [3][m] double, required iff an op is MPF_OP_DN/_SHIFT_ROW
+ * w64      dev [n_ops][nl][m] double, or NULL
+ * w32      dev [n_ops][nl][m] float, or NULL: the FP32 copy; its self weight
+ *          (column 0) is replaced so that the row sums, computed in FP64, equal
+ *          the exact ones (1 for the two shift kinds, 0 for derivatives)
+ * info     dev [m] int32: 0, or 1 + the column of a zero pivot (weights of
+ *          that row are then NaN)
+ * nl must be one of 20, 25, 27, 30, 35, 40, 45, 50 (MPF_ERR_UNSUPPORTED
+ * otherwise).  At least one of w64 / w32 must be given. */
+#define MPF_OP_DX 0
+#define MPF_OP_DY 1
+#define MPF_OP_DZ 2
+#define MPF_OP_LAP 3
+#define MPF_OP_DIR 4
+#define MPF_OP_SHIFT 5
+#define MPF_OP_DN 6
+#define MPF_OP_SHIFT_ROW 7
+
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double vec[3];
+} mpf_op;
+
+int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_t m, int nl, int n_ops,
+                      const mpf_op* ops, const double* rowvec, double* w64, float* w32, int32_t* info,
+                      void* stream);
+
+/* ------------------------------------------------------------- ACM step
+ * Explicit artificial-compressibility Navier-Stokes steps (Sec. 2.3, Eqs.
+ * MNS_intermediate, MNS_pressure, MNS_velocity, MNS_C; MNS algorithm of
+ * Appendix A).  One step:
+ *   v'_i = v_i + dt (nu Lap v_i - (v_i . grad) v_i + g)   interior i; v' = 0 on
+ *                                                          the boundary
+ *   n_p times:
+ *     p_i -= dt C^2 rho (div v)_i                         interior (v = v' at
+ *                                                          the first iteration)
+ *     p_b  = -(sum_{j>=1} wn_bj p_{sn_b(j)}) / wn_b0      boundary, dp/dn = 0
+ *     v_i  = v'_i - (dt / rho) (grad p)_i                 interior
+ *     C    = beta max(max_i |v_i|, v_ref)
+ * The Neumann stencil sn of boundary node b must hold b itself in column 0
+ * and only interior nodes after it (then the boundary update reads no other
+ * boundary value and runs in place).
+ *
+ * w     dev [4][nl][n]: d/dx, d/dy, d/dz, Laplacian weights of every node
+ *       (rows of boundary nodes are not read)
+ * sten  dev [nl][n]
+ * sn    dev [nl][nb]; wn dev [nl][nb] normal-derivative weights on sn
+ * v     dev [3][n], p dev [n]: state, updated in place (v stays 0 on the
+ *       boundary)
+ * vmax  dev double [1]: max_i |v_i| of the current state, in/out (0 for a
+ *       state at rest); C is derived from it
+ * ws    workspace of mpf_acm_workspace() bytes
+ * Fields and weights share one precision (MPF_F64 or MPF_F32).  With MPF_F32
+ * all arithmetic except the max is FP32. */
+typedef struct {
+  double nu, rho, dt, beta, v_ref;
+  double g[3];
+  int32_t n_p;
+  int32_t precision;
+} mpf_acm_params;
+
+size_t mpf_acm_workspace(int64_t n, int precision);
+int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* w,
+                const int32_t* sn, const void* wn, void* v, void* p, double* vmax, int n_steps, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------- MLBM step
+ * Meshless lattice Boltzmann steps with TRT collision (Sec. 2.2, Eqs.
+ * LBM_streaming, LBM_collision, feq, macro_var, force_lbm,
+ * interpolated_bounceback_mlbm; MLBM algorithm of Appendix A).  The state f
+ * holds the populations at step boundaries (after streaming and bounce-back),
+ * shifted: f~_k = f_k - w_k.  One step:
+ *   collide on every node: rho = 1 + sum f~, u = sum f~ e / rho, f^eq of Eq.
+ *     feq, F_k = 3 w_k e_k . (rho g_lb), TRT relaxation with tau+ and tau-;
+ *   stream: f_k(i) = sum_j W_k[j][i] f^post_k(sten[j][i]) for k >= 1 (W_k
+ *     interpolates at the departure point of population k), f_0 = f^post_0;
+ *   bounce-back at boundary node b: where e_k . n_b > 0, f_k = f_{opp(k)}.
+ * W     dev [q-1][nl][n] (population k uses slice k - 1), precision as f
+ * nrm   dev [3][nb] double
+ * f     dev [q][n] state, updated in place; f_tmp dev [q][n] scratch
+ * q is 15 or 19. */
+typedef struct {
+  int32_t q;
+  int32_t precision;
+  double tau_plus, tau_minus;
+  double g_lb[3];
+} mpf_lbm_params;
+
+/* f~ = f^eq(rho, u) - w_k on every node. */
+int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, const double* u_host, void* f, void* stream);
+int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* W,
+                const double* nrm, void* f, void* f_tmp, int n_steps, void* stream);
+/* Macroscopic fields in physical units (Eq. conversion_factors): v[3][n] =
+ * vel_scale * u_lb, p[n] = vel_scale^2 (rho - 1) / 3 (not centred: the drag
+ * reduction subtracts the node mean).  Outputs are double. */
+int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double vel_scale, double* v, double* p,
+                    void* stream);
+
+/* ------------------------------------------------------------- reductions
+ * Mean x-velocity over the five cross-sections, Eq. k_definition, as the mean
+ * over all n_all = 5 M^2 midpoint samples, solid samples counting zero.  The
+ * ns fluid samples interpolate v_x with weights s_w over stencils s_idx.
+ * s_idx dev [nl][ns]; s_w dev [nl][ns] double; vx dev [n] (precision);
+ * q_out dev double[1].  The sum is a fixed-order FP64 tree, so results are
+ * bitwise reproducible. */
+size_t mpf_reduce_workspace(int64_t n_items);
+int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx, int precision,
+                    int64_t n_all, double* q_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Hydrodynamic force on the grains, Eqs. stress_tensor_force and
+ * integration_force: F = dA sum_b (-(p_b - <p>) n_b + rho nu (grad v + grad
+ * v^T) n_b), with <p> the mean of p over all n nodes and grad v at boundary
+ * node b from derivative weights wg dev [3][nl][nb] over stencils sb dev
+ * [nl][nb].  v dev [3][n], p dev [n] (precision); nrm dev [3][nb]; F_out dev
+ * double[3].  Fixed-order FP64 sums.  Workspace: mpf_reduce_workspace(max(n,
+ * nb)) bytes. */
+int mpf_drag(int64_t n, const void* v, const void* p, int precision, int64_t nb, int nl, const int32_t* sb,
+             const double* wg, const double* nrm, double rho, double nu, double dA, double* F_out, void* ws,
+             size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPF_H */

@@ -1,0 +1,108 @@
+"""ctypes binding of libmpf (include/mpf.h).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.  Arrays are torch
+tensors on the current HIP device; pointers and the current stream are passed
+through unchanged.  If the library is not built this module raises at import:
+there is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_INC = os.path.join(os.path.dirname(_HERE), "include")
+SO_PATH = os.path.join(_HERE, "libmpf.so")
+SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip"]
+
+MPF_F64, MPF_F32 = 0, 1
+OP = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shift_row": 7}
+
+
+class MPFError(RuntimeError):
+    pass
+
+
+def hipcc_command(out: str):
+    src = [os.path.join(_HERE, "csrc", s) for s in SOURCES]
+    return ["/opt/rocm/bin/hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I" + _INC, "-I" + os.path.join(_HERE, "csrc")] + src + ["-o", out]
+
+
+def build() -> str:
+    """Compile libmpf.so for gfx950 in-tree (hipcc cross-compiles without a GPU)."""
+    tmp = SO_PATH + ".tmp"
+    subprocess.check_call(hipcc_command(tmp))
+    os.replace(tmp, SO_PATH)
+    return SO_PATH
+
+
+class _Op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("vec", ctypes.c_double * 3)]
+
+
+class AcmParams(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("rho", ctypes.c_double), ("dt", ctypes.c_double),
+                ("beta", ctypes.c_double), ("v_ref", ctypes.c_double), ("g", ctypes.c_double * 3),
+                ("n_p", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("precision", ctypes.c_int32), ("tau_plus", ctypes.c_double),
+                ("tau_minus", ctypes.c_double), ("g_lb", ctypes.c_double * 3)]
+
+
+def _load():
+    if not os.path.exists(SO_PATH):
+        raise MPFError(f"libmpf.so is not built ({SO_PATH}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(SO_PATH)
+    vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "mpf_strerror": (ctypes.c_char_p, [i32]),
+        "mpf_version": (i32, []),
+        "mpf_sc_cell": (i32, [dbl, vp, vp]),
+        "mpf_rbffd_weights": (i32, [vp, i64, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "mpf_acm_workspace": (sz, [i64, i32]),
+        "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
+        "mpf_lbm_init": (i32, [vp, i64, dbl, vp, vp, vp]),
+        "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, i32, vp]),
+        "mpf_lbm_moments": (i32, [vp, i64, vp, dbl, vp, vp, vp]),
+        "mpf_reduce_workspace": (sz, [i64]),
+        "mpf_flux_planes": (i32, [i64, i32, vp, vp, vp, i32, i64, vp, vp, sz, vp]),
+        "mpf_drag": (i32, [i64, vp, vp, i32, i64, i32, vp, vp, vp, dbl, dbl, dbl, vp, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded library; raises MPFError if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_rbffd_weights", "mpf_acm_workspace", "mpf_acm_run",
+            "mpf_lbm_init", "mpf_lbm_run", "mpf_lbm_moments", "mpf_reduce_workspace", "mpf_flux_planes", "mpf_drag"]
+
+
+def check(rc: int, what: str):
+    if rc != 0:
+        raise MPFError(f"{what}: {lib().mpf_strerror(rc).decode()} ({rc})")
+
+
+def make_ops(ops):
+    arr = (_Op * len(ops))()
+    for i, o in enumerate(ops):
+        arr[i].kind = OP[o[0]]
+        vec = o[1] if len(o) > 1 and o[1] is not None else (0.0, 0.0, 0.0)
+        for t in range(3):
+            arr[i].vec[t] = float(vec[t])
+    return arr

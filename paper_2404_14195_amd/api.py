@@ -1,0 +1,149 @@
+"""Python face of libmpf: one function per C entry point, same names without
+the ``mpf_`` prefix.  Tensors must be contiguous and on the current HIP device;
+every call is enqueued on torch's current stream."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MPF_F32, MPF_F64, AcmParams, LbmParams, check, lib, make_ops
+
+_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def precision_of(dtype) -> int:
+    if dtype == torch.float64:
+        return MPF_F64
+    if dtype == torch.float32:
+        return MPF_F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def version() -> int:
+    return lib().mpf_version()
+
+
+def sc_cell(r: float):
+    """(porosity, grain area) of the simple-cubic cell, from the library."""
+    phi = ctypes.c_double()
+    area = ctypes.c_double()
+    check(lib().mpf_sc_cell(float(r), ctypes.byref(phi), ctypes.byref(area)), "mpf_sc_cell")
+    return phi.value, area.value
+
+
+def rbffd_weights(pos, sten, ops, rowvec=None, want64=True, want32=False):
+    """pos [3][n] f64, sten [nl][m] i32; ops: list of (name, vec).  Returns
+    (w64 [n_ops][nl][m] or None, w32 or None, info [m])."""
+    _need(pos, torch.float64, name="pos")
+    _need(sten, torch.int32, name="sten")
+    nl, m = sten.shape
+    dev = pos.device
+    w64 = torch.empty((len(ops), nl, m), dtype=torch.float64, device=dev) if want64 else None
+    w32 = torch.empty((len(ops), nl, m), dtype=torch.float32, device=dev) if want32 else None
+    info = torch.empty(m, dtype=torch.int32, device=dev)
+    if rowvec is not None:
+        _need(rowvec, torch.float64, (3, m), "rowvec")
+    arr = make_ops(ops)
+    check(lib().mpf_rbffd_weights(_p(pos), pos.shape[1], _p(sten), m, nl, len(ops), arr, _p(rowvec), _p(w64), _p(w32),
+                                _p(info), _stream()), "mpf_rbffd_weights")
+    return w64, w32, info
+
+
+def acm_workspace(n: int, precision: int, device) -> torch.Tensor:
+    nbytes = lib().mpf_acm_workspace(n, precision)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: int, ws=None):
+    prec = prm.precision
+    dt = _DT[prec]
+    nl, n = sten.shape
+    _need(w, dt, (4, nl, n), "w")
+    _need(v, dt, (3, n), "v")
+    _need(p, dt, (n,), "p")
+    _need(vmax, torch.float64, (1,), "vmax")
+    if n > n_int:
+        _need(wn, dt, (nl, n - n_int), "wn")
+        _need(sn, torch.int32, (nl, n - n_int), "sn")
+    if ws is None:
+        ws = acm_workspace(n, prec, v.device)
+    check(lib().mpf_acm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(w), _p(sn), _p(wn), _p(v), _p(p), _p(vmax),
+                          int(n_steps), _p(ws), ws.numel(), _stream()), "mpf_acm_run")
+
+
+def lbm_init(prm: LbmParams, f, rho=1.0, u=(0.0, 0.0, 0.0)):
+    _need(f, _DT[prm.precision], name="f")
+    uu = (ctypes.c_double * 3)(*[float(x) for x in u])
+    check(lib().mpf_lbm_init(ctypes.byref(prm), f.shape[1], float(rho), uu, _p(f), _stream()), "mpf_lbm_init")
+
+
+def lbm_run(prm: LbmParams, n_int: int, sten, W, nrm, f, f_tmp, n_steps: int):
+    dt = _DT[prm.precision]
+    nl, n = sten.shape
+    _need(W, dt, (prm.q - 1, nl, n), "W")
+    _need(f, dt, (prm.q, n), "f")
+    _need(f_tmp, dt, (prm.q, n), "f_tmp")
+    if n > n_int:
+        _need(nrm, torch.float64, (3, n - n_int), "nrm")
+    check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(nrm), _p(f), _p(f_tmp), int(n_steps),
+                          _stream()), "mpf_lbm_run")
+
+
+def lbm_moments(prm: LbmParams, f, vel_scale: float, v=None, p=None):
+    n = f.shape[1]
+    v = torch.empty((3, n), dtype=torch.float64, device=f.device) if v is None else v
+    p = torch.empty(n, dtype=torch.float64, device=f.device) if p is None else p
+    check(lib().mpf_lbm_moments(ctypes.byref(prm), n, _p(f), float(vel_scale), _p(v), _p(p), _stream()),
+          "mpf_lbm_moments")
+    return v, p
+
+
+def reduce_workspace(n_items: int, device) -> torch.Tensor:
+    return torch.empty(lib().mpf_reduce_workspace(n_items), dtype=torch.uint8, device=device)
+
+
+def flux_planes(s_idx, s_w, vx, n_all: int, q_out=None, ws=None):
+    nl, ns = s_idx.shape
+    _need(s_w, torch.float64, (nl, ns), "s_w")
+    q_out = torch.empty(1, dtype=torch.float64, device=vx.device) if q_out is None else q_out
+    ws = reduce_workspace(ns, vx.device) if ws is None else ws
+    check(lib().mpf_flux_planes(ns, nl, _p(s_idx), _p(s_w), _p(vx), precision_of(vx.dtype), int(n_all), _p(q_out),
+                              _p(ws), ws.numel(), _stream()), "mpf_flux_planes")
+    return q_out
+
+
+def drag(v, p, sb, wg, nrm, rho: float, nu: float, dA: float, F_out=None, ws=None):
+    n = p.shape[0]
+    nl, nb = sb.shape
+    _need(wg, torch.float64, (3, nl, nb), "wg")
+    _need(nrm, torch.float64, (3, nb), "nrm")
+    if v.dtype != p.dtype:
+        raise TypeError("v and p must share a dtype")
+    F_out = torch.empty(3, dtype=torch.float64, device=v.device) if F_out is None else F_out
+    ws = reduce_workspace(max(n, nb), v.device) if ws is None else ws
+    check(lib().mpf_drag(n, _p(v), _p(p), precision_of(p.dtype), nb, nl, _p(sb), _p(wg), _p(nrm), float(rho), float(nu),
+                       float(dA), _p(F_out), _p(ws), ws.numel(), _stream()), "mpf_drag")
+    return F_out

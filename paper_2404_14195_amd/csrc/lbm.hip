@@ -1,0 +1,243 @@
+// Meshless TRT lattice Boltzmann steps (Sec. 2.2) on gfx950.
+//
+// State: populations shifted by their lattice weight, f~_k = f_k - w_k, in
+// [q][n] layout.  The shift makes FP32 storage usable: the forcing term per
+// step is about 1e-9 of f_k, below FP32 resolution of f_k itself but not of
+// the deviation f~_k.  The equilibrium and the TRT split are written for the
+// shifted values directly (w_k = w_{opp(k)}, so the shift cancels in f - f^eq).
+//
+// A step is one fused pass per node: gather-stream the post-collision
+// populations of the stencil (Eq. LBM_streaming with interpolation weights of
+// Eq. operatorApprox), bounce back the unknown populations of surface nodes
+// (Eq. interpolated_bounceback_mlbm), then collide (Eqs. macro_var, feq,
+// LBM_collision, force_lbm) and write the next post-collision state.  The
+// stencil index of column j is loaded once and reused by all q - 1 moving
+// populations; weights stream coalesced from [k][j][node].
+#include "common.hpp"
+
+namespace mpf {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T>
+struct Prm {
+  T itp, itm;  // 1/tau+, 1/tau-
+  T g0, g1, g2;
+};
+
+// TRT collision of one node's shifted populations, in place.
+template <typename T, int Q>
+__device__ __forceinline__ void collide(T (&f)[Q], const Prm<T>& pr) {
+  using L = Lattice<Q>;
+  T drho = T(0), j0 = T(0), j1 = T(0), j2 = T(0);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    drho += f[k];
+    if (L::ex[k]) j0 += L::ex[k] > 0 ? f[k] : -f[k];
+    if (L::ey[k]) j1 += L::ey[k] > 0 ? f[k] : -f[k];
+    if (L::ez[k]) j2 += L::ez[k] > 0 ? f[k] : -f[k];
+  }
+  const T rho = T(1) + drho;
+  const T ir = T(1) / rho;
+  const T u0 = j0 * ir, u1 = j1 * ir, u2 = j2 * ir;
+  const T uu = u0 * u0 + u1 * u1 + u2 * u2;
+  const T F0 = rho * pr.g0, F1 = rho * pr.g1, F2 = rho * pr.g2;
+  T feq[Q], Fk[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const T eu = T(L::ex[k]) * u0 + T(L::ey[k]) * u1 + T(L::ez[k]) * u2;
+    const T wk = (T)lat_w<Q>(k);
+    // f^eq_k - w_k = w_k (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu))
+    feq[k] = wk * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu));
+    Fk[k] = T(3) * wk * (T(L::ex[k]) * F0 + T(L::ey[k]) * F1 + T(L::ez[k]) * F2);
+  }
+  T out[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int kb = lat_opp(k);
+    const T fp = T(0.5) * (f[k] + f[kb]), fm = T(0.5) * (f[k] - f[kb]);
+    const T ep = T(0.5) * (feq[k] + feq[kb]), em = T(0.5) * (feq[k] - feq[kb]);
+    out[k] = f[k] - (fp - ep) * pr.itp - (fm - em) * pr.itm + Fk[k];
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) f[k] = out[k];
+}
+
+// src may equal dst: each thread reads and writes only its own node
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void lbm_collide(int64_t n, const T* src, T* dst,
+                                                      Prm<T> pr) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T f[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) f[k] = src[k * n + i];
+  collide<T, Q>(f, pr);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) dst[k * n + i] = f[k];
+}
+
+template <typename T, int Q, bool COLLIDE>
+__global__ __launch_bounds__(kBlock) void lbm_step(int64_t n, int64_t n_int, int nl, const int32_t* __restrict__ sten,
+                                                   const T* __restrict__ W, const double* __restrict__ nrm,
+                                                   const T* __restrict__ src, T* __restrict__ dst, Prm<T> pr) {
+  using L = Lattice<Q>;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t ks = (int64_t)nl * n;  // population stride in W
+  T f[Q];
+  f[0] = src[i];
+#pragma unroll
+  for (int k = 1; k < Q; ++k) f[k] = T(0);
+  for (int j = 0; j < nl; ++j) {
+    const int64_t at = (int64_t)j * n + i;
+    const int s = sten[at];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) f[k] += W[(k - 1) * ks + at] * src[k * n + s];
+  }
+  if (i >= n_int) {
+    const int64_t b = i - n_int, nb = n - n_int;
+    const double nx = nrm[b], ny = nrm[nb + b], nz = nrm[2 * nb + b];
+    T g[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) g[k] = f[k];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const double en = (double)L::ex[k] * nx + (double)L::ey[k] * ny + (double)L::ez[k] * nz;
+      if (en > 0.0) f[k] = g[lat_opp(k)];
+    }
+  }
+  if (COLLIDE) collide<T, Q>(f, pr);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) dst[k * n + i] = f[k];
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void lbm_init(int64_t n, T* __restrict__ f, double rho, double u0, double u1,
+                                                   double u2) {
+  using L = Lattice<Q>;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double eu = L::ex[k] * u0 + L::ey[k] * u1 + L::ez[k] * u2;
+    const double wk = lat_w<Q>(k);
+    f[k * n + i] = (T)(wk * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
+  }
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __restrict__ f, double vs,
+                                                      double* __restrict__ v, double* __restrict__ p) {
+  using L = Lattice<Q>;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double drho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double fk = (double)f[k * n + i];
+    drho += fk;
+    j0 += L::ex[k] * fk;
+    j1 += L::ey[k] * fk;
+    j2 += L::ez[k] * fk;
+  }
+  const double rho = 1.0 + drho;
+  v[i] = vs * j0 / rho;
+  v[n + i] = vs * j1 / rho;
+  v[2 * n + i] = vs * j2 / rho;
+  if (p) p[i] = vs * vs * drho / 3.0;
+}
+
+template <typename T, int Q>
+int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const T* W,
+        const double* nrm, T* f, T* ft, int n_steps, hipStream_t st) {
+  Prm<T> pr{(T)(1.0 / prm->tau_plus), (T)(1.0 / prm->tau_minus), (T)prm->g_lb[0], (T)prm->g_lb[1],
+            (T)prm->g_lb[2]};
+  const unsigned g = grid_for(n, kBlock);
+  // collide so that after n_steps - 1 fused passes the current state sits in
+  // ft, and the last (stream-only) pass lands in f
+  T* cur;
+  if ((n_steps - 1) % 2 == 0) {
+    hipLaunchKernelGGL((lbm_collide<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, ft, pr);
+    cur = ft;
+  } else {
+    hipLaunchKernelGGL((lbm_collide<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, f, pr);
+    cur = f;
+  }
+  for (int s = 0; s < n_steps - 1; ++s) {
+    T* nxt = cur == f ? ft : f;
+    hipLaunchKernelGGL((lbm_step<T, Q, true>), dim3(g), dim3(kBlock), 0, st, n, n_int, nl, sten, W, nrm,
+                       (const T*)cur, nxt, pr);
+    cur = nxt;
+  }
+  hipLaunchKernelGGL((lbm_step<T, Q, false>), dim3(g), dim3(kBlock), 0, st, n, n_int, nl, sten, W, nrm,
+                     (const T*)cur, f, pr);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+}  // namespace
+}  // namespace mpf
+
+extern "C" int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, const double* u_host, void* f,
+                            void* stream) {
+  using namespace mpf;
+  if (!prm || !f || !u_host || n < 1) return MPF_ERR_ARG;
+  hipStream_t st = as_stream(stream);
+  const unsigned g = grid_for(n, kBlock);
+  const double u0 = u_host[0], u1 = u_host[1], u2 = u_host[2];
+  if (prm->q == 19 && prm->precision == MPF_F64)
+    hipLaunchKernelGGL((lbm_init<double, 19>), dim3(g), dim3(kBlock), 0, st, n, (double*)f, rho, u0, u1, u2);
+  else if (prm->q == 19 && prm->precision == MPF_F32)
+    hipLaunchKernelGGL((lbm_init<float, 19>), dim3(g), dim3(kBlock), 0, st, n, (float*)f, rho, u0, u1, u2);
+  else if (prm->q == 15 && prm->precision == MPF_F64)
+    hipLaunchKernelGGL((lbm_init<double, 15>), dim3(g), dim3(kBlock), 0, st, n, (double*)f, rho, u0, u1, u2);
+  else if (prm->q == 15 && prm->precision == MPF_F32)
+    hipLaunchKernelGGL((lbm_init<float, 15>), dim3(g), dim3(kBlock), 0, st, n, (float*)f, rho, u0, u1, u2);
+  else
+    return MPF_ERR_ARG;
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
+                           const void* W, const double* nrm, void* f, void* f_tmp, int n_steps, void* stream) {
+  using namespace mpf;
+  if (!prm || !sten || !W || !f || !f_tmp || n < 1 || n_int < 0 || n_int > n || nl < 1 || n_steps < 0)
+    return MPF_ERR_ARG;
+  if (n > n_int && !nrm) return MPF_ERR_ARG;
+  if (!(prm->tau_plus > 0.5) || !(prm->tau_minus > 0.5)) return MPF_ERR_ARG;
+  if (n_steps == 0) return MPF_OK;
+  hipStream_t st = as_stream(stream);
+  if (prm->q == 19 && prm->precision == MPF_F64)
+    return run<double, 19>(prm, n, n_int, nl, sten, (const double*)W, nrm, (double*)f, (double*)f_tmp, n_steps, st);
+  if (prm->q == 19 && prm->precision == MPF_F32)
+    return run<float, 19>(prm, n, n_int, nl, sten, (const float*)W, nrm, (float*)f, (float*)f_tmp, n_steps, st);
+  if (prm->q == 15 && prm->precision == MPF_F64)
+    return run<double, 15>(prm, n, n_int, nl, sten, (const double*)W, nrm, (double*)f, (double*)f_tmp, n_steps, st);
+  if (prm->q == 15 && prm->precision == MPF_F32)
+    return run<float, 15>(prm, n, n_int, nl, sten, (const float*)W, nrm, (float*)f, (float*)f_tmp, n_steps, st);
+  return MPF_ERR_ARG;
+}
+
+extern "C" int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double vel_scale, double* v,
+                               double* p, void* stream) {
+  using namespace mpf;
+  if (!prm || !f || !v || n < 1) return MPF_ERR_ARG;
+  hipStream_t st = as_stream(stream);
+  const unsigned g = grid_for(n, kBlock);
+  if (prm->q == 19 && prm->precision == MPF_F64)
+    hipLaunchKernelGGL((lbm_moments<double, 19>), dim3(g), dim3(kBlock), 0, st, n, (const double*)f, vel_scale, v, p);
+  else if (prm->q == 19 && prm->precision == MPF_F32)
+    hipLaunchKernelGGL((lbm_moments<float, 19>), dim3(g), dim3(kBlock), 0, st, n, (const float*)f, vel_scale, v, p);
+  else if (prm->q == 15 && prm->precision == MPF_F64)
+    hipLaunchKernelGGL((lbm_moments<double, 15>), dim3(g), dim3(kBlock), 0, st, n, (const double*)f, vel_scale, v, p);
+  else if (prm->q == 15 && prm->precision == MPF_F32)
+    hipLaunchKernelGGL((lbm_moments<float, 15>), dim3(g), dim3(kBlock), 0, st, n, (const float*)f, vel_scale, v, p);
+  else
+    return MPF_ERR_ARG;
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}

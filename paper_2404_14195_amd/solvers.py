@@ -1,0 +1,174 @@
+"""Device-resident drivers for the two meshless solvers.
+
+They hold the node cloud, stencils, weights and state in HBM and call the C
+ABI (``api``) for every step of the computation; the host only launches and,
+at checks, reads back one or three doubles."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+import nodecloud
+
+from . import api
+from ._lib import MPF_F32, MPF_F64, AcmParams, LbmParams
+
+_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32}
+
+
+class Discretization:
+    """A node cloud on the device: positions [3][n], stencils [nl][n], the
+    Neumann stencils of the boundary nodes [nl][nb], normals [3][nb] and the
+    plane-sample plan of the permeability."""
+
+    def __init__(self, cloud: nodecloud.Cloud, nl: int = 30, M: int = 64, device="cuda", plan: bool = True):
+        self.cloud, self.nl, self.M = cloud, nl, M
+        self.n, self.n_int, self.nb = cloud.n, cloud.n_int, cloud.n_bnd
+        self.device = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)
+        self.pos = t(cloud.pos.T, torch.float64)
+        self.sten_host = nodecloud.stencils(cloud.pos, nl)
+        self.sten = t(self.sten_host.T, torch.int32)
+        self.nrm = t(cloud.nrm.T, torch.float64) if self.nb else torch.zeros((3, 0), dtype=torch.float64,
+                                                                               device=self.device)
+        self.sn = t(nodecloud.neumann_stencils(cloud, nl).T, torch.int32)
+        self.sb = self.sten[:, self.n_int:].contiguous()
+        if plan:
+            pp = nodecloud.plane_plan(cloud, M, nl)
+            self.plan = pp
+            self.s_idx = t(pp.idx.T, torch.int32)
+            self.s_shift = t(pp.shift.T, torch.float64)
+            self.n_all = len(pp.planes) * M * M
+            self.s_w = api.rbffd_weights(self.pos, self.s_idx, [("shift_row",)], rowvec=self.s_shift)[0][0].contiguous()
+        self.phi, self.area = api.sc_cell(cloud.r) if cloud.r > 0 else (1.0, 0.0)
+        self.red_ws = api.reduce_workspace(max(self.n, 5 * M * M), self.device)
+
+
+class ACMSolver:
+    """Artificial-compressibility Navier-Stokes (Sec. 2.3) on a Discretization."""
+
+    def __init__(self, disc: Discretization, precision: int = MPF_F64, nu=1.0, rho=1.0, dt=None, beta=10.0,
+                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3):
+        self.d, self.precision = disc, precision
+        dt = 0.1 * disc.cloud.h_min ** 2 / (2.0 * nu) if dt is None else dt
+        self.prm = AcmParams(nu=nu, rho=rho, dt=dt, beta=beta, v_ref=v_ref, g=(ctypesarr(g)), n_p=n_p,
+                             precision=precision)
+        self.g = tuple(g)
+        w64, w32, info = api.rbffd_weights(disc.pos, disc.sten, [("dx",), ("dy",), ("dz",), ("lap",)],
+                                           want64=True, want32=precision == MPF_F32)
+        wn64, wn32, infon = api.rbffd_weights(disc.pos, disc.sn, [("dn",)], rowvec=disc.nrm, want64=True,
+                                              want32=precision == MPF_F32) if disc.nb else (None, None, None)
+        self.info = info
+        self.w64 = w64
+        self.w = w64 if precision == MPF_F64 else w32
+        self.wn = (wn64 if precision == MPF_F64 else wn32)[0].contiguous() if disc.nb else None
+        self.wg = w64[:3, :, disc.n_int:].contiguous()
+        dtp = _DT[precision]
+        self.v = torch.zeros((3, disc.n), dtype=dtp, device=disc.device)
+        self.p = torch.zeros(disc.n, dtype=dtp, device=disc.device)
+        self.vmax = torch.zeros(1, dtype=torch.float64, device=disc.device)
+        self.ws = api.acm_workspace(disc.n, precision, disc.device)
+        self.steps = 0
+
+    def run(self, n_steps: int):
+        api.acm_run(self.prm, self.d.n_int, self.d.sten, self.w, self.d.sn, self.wn, self.v, self.p, self.vmax,
+                    n_steps, self.ws)
+        self.steps += n_steps
+
+    def flux(self):
+        return api.flux_planes(self.d.s_idx, self.d.s_w, self.v[0], self.d.n_all, ws=self.d.red_ws)
+
+    def permeability(self) -> float:
+        """k/d^2 = q nu / (|g| d^2), Eq. k_definition."""
+        q = float(self.flux().item())
+        return q * self.prm.nu / math.sqrt(sum(x * x for x in self.g))
+
+    def drag(self):
+        """(F [3], K) with K = F_x / (6 pi r phi q mu), Eq. K_definition."""
+        d = self.d
+        F = api.drag(self.v, self.p, d.sb, self.wg, d.nrm, self.prm.rho, self.prm.nu, d.area / d.nb, ws=d.red_ws)
+        F = F.cpu().numpy()
+        q = float(self.flux().item())
+        K = F[0] / (6.0 * math.pi * d.cloud.r * d.phi * q * self.prm.rho * self.prm.nu)
+        return F, K
+
+
+def ctypesarr(g):
+    import ctypes
+    return (ctypes.c_double * 3)(*[float(x) for x in g])
+
+
+def lbm_units(h_min: float, nu: float, tau_plus: float, g, magic: float):
+    """dx = h_min / 2 (Sec. 2.2), nu_lb = (tau+ - 1/2)/3 (Eq. lbm_viscosity),
+    dt and g_lb from Eq. conversion_factors, tau- from the magic parameter."""
+    dx = 0.5 * h_min
+    nu_lb = (tau_plus - 0.5) / 3.0
+    dt = nu_lb * dx * dx / nu
+    return dict(dx=dx, dt=dt, nu_lb=nu_lb, g_lb=[x * dt * dt / dx for x in g],
+                tau_minus=0.5 + magic / (tau_plus - 0.5), vel_scale=dx / dt)
+
+
+def lattice_vectors(q: int):
+    """e_k in the pairing of the paper's D3Q15 table (rest; odd k listed; even
+    k opposite), for building the shift operators of the departure points."""
+    base = {15: [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1)],
+            19: [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1),
+                 (0, 1, -1)]}[q]
+    e = [(0, 0, 0)]
+    for b in base:
+        e.append(b)
+        e.append(tuple(-x for x in b))
+    return e
+
+
+class MLBMSolver:
+    """Meshless TRT lattice Boltzmann (Sec. 2.2) on a Discretization."""
+
+    def __init__(self, disc: Discretization, q=19, precision: int = MPF_F64, nu=1.0, tau_plus=1.0, magic=0.25,
+                 g=(1.0, 0.0, 0.0), dx=None, W=None):
+        self.d, self.q, self.precision = disc, q, precision
+        h = disc.cloud.h_min if dx is None else 2.0 * dx
+        self.units = u = lbm_units(h, nu, tau_plus, g, magic)
+        self.nu, self.g = nu, tuple(g)
+        self.prm = LbmParams(q=q, precision=precision, tau_plus=tau_plus, tau_minus=u["tau_minus"],
+                             g_lb=ctypesarr(u["g_lb"]))
+        e = lattice_vectors(q)
+        if W is None:
+            ops = [("shift", tuple(-u["dx"] * x for x in e[k])) for k in range(1, q)]
+            w64, w32, self.info = api.rbffd_weights(disc.pos, disc.sten, ops, want64=precision == MPF_F64,
+                                                    want32=precision == MPF_F32)
+            W = w64 if precision == MPF_F64 else w32
+        self.W = W
+        dtp = _DT[precision]
+        self.f = torch.empty((q, disc.n), dtype=dtp, device=disc.device)
+        self.f_tmp = torch.empty_like(self.f)
+        api.lbm_init(self.prm, self.f)
+        self.steps = 0
+        self._v = torch.empty((3, disc.n), dtype=torch.float64, device=disc.device)
+        self._p = torch.empty(disc.n, dtype=torch.float64, device=disc.device)
+        self._wg = None
+
+    def run(self, n_steps: int):
+        api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.d.nrm, self.f, self.f_tmp, n_steps)
+        self.steps += n_steps
+
+    def macros(self):
+        return api.lbm_moments(self.prm, self.f, self.units["vel_scale"], self._v, self._p)
+
+    def permeability(self) -> float:
+        v, _ = self.macros()
+        q = float(api.flux_planes(self.d.s_idx, self.d.s_w, v[0], self.d.n_all, ws=self.d.red_ws).item())
+        return q * self.nu / math.sqrt(sum(x * x for x in self.g))
+
+    def drag(self):
+        d = self.d
+        v, p = self.macros()
+        v[:, d.n_int:] = 0.0  # the no-slip value on the grain enters the stress
+        if self._wg is None:
+            self._wg = api.rbffd_weights(d.pos, d.sb, [("dx",), ("dy",), ("dz",)])[0]
+        F = api.drag(v, p, d.sb, self._wg, d.nrm, 1.0, self.nu, d.area / d.nb, ws=d.red_ws).cpu().numpy()
+        q = float(api.flux_planes(d.s_idx, d.s_w, v[0], d.n_all, ws=d.red_ws).item())
+        K = F[0] / (6.0 * math.pi * d.cloud.r * d.phi * q * self.nu)
+        return F, K

@@ -1,0 +1,265 @@
+"""HIP path (libmpf through its C ABI) against the CPU oracle, element by
+element, on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import nodecloud as nc
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2404_14195_amd import api as A
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return A
+
+
+@pytest.fixture(scope="module")
+def disc_small(api, small_cloud):
+    from paper_2404_14195_amd.solvers import Discretization
+    return Discretization(small_cloud, nl=30, M=64)
+
+
+def dev(a, dt):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+# ----------------------------------------------------------------- weights
+
+def row_rel_err(w_gpu, w_ref):
+    """max over rows of max_j |dw_j| / max_j |w_ref_j| (w_* as [m][nl])."""
+    scale = np.abs(w_ref).max(1)
+    return (np.abs(w_gpu - w_ref).max(1) / scale).max()
+
+
+def test_weights_parity_fp64(api, small_cloud, small_stencils):
+    c, S = small_cloud, small_stencils
+    rng = np.random.default_rng(0)
+    rv = rng.normal(size=(c.n, 3)) * 0.01
+    e19 = [(1, 0, 0), (1, 1, 0), (0, -1, 1)]
+    ops = [("dx",), ("dy",), ("dz",), ("lap",), ("dir", (0.3, -0.5, 0.8)), ("dn",), ("shift_row",)] + \
+          [("shift", tuple(-0.01 * np.array(v))) for v in e19]
+    w_ref, info_ref = O.weights(c.pos, S, ops, rowvec=rv)
+    w64, w32, info = api.rbffd_weights(dev(c.pos.T, torch.float64), dev(S.T, torch.int32), ops,
+                                       rowvec=dev(rv.T, torch.float64), want64=True, want32=True)
+    w64 = w64.cpu().numpy().transpose(2, 0, 1)  # -> [m][op][nl]
+    assert not info.cpu().numpy().any() and not info_ref.any()
+    for o in range(len(ops)):
+        err = row_rel_err(w64[:, o], w_ref[:, o])
+        assert err < 1e-10, (ops[o], err)
+    # FP32 copy: within FP32 rounding of the FP64 weights, row sums restored
+    w32 = w32.cpu().numpy().transpose(2, 0, 1).astype(np.float64)
+    assert row_rel_err(w32[:, 0], w_ref[:, 0]) < 1e-6
+    assert np.abs(w32[:, 0].sum(1)).max() < 1e-6 * np.abs(w_ref[:, 0]).max()
+    assert np.abs(w32[:, 7].sum(1) - 1.0).max() < 1e-7
+
+
+@pytest.mark.parametrize("nl", [20, 25, 27, 35, 40, 45, 50])
+def test_weights_parity_stencil_sizes(api, small_cloud, nl):
+    c = small_cloud
+    S = nc.stencils(c.pos, nl)[::13]
+    ops = [("dx",), ("lap",), ("shift", (0.003, 0.004, -0.002))]
+    w_ref, _ = O.weights(c.pos, S, ops)
+    w64, _, info = api.rbffd_weights(dev(c.pos.T, torch.float64), dev(S.T, torch.int32), ops)
+    w64 = w64.cpu().numpy().transpose(2, 0, 1)
+    assert not info.cpu().numpy().any()
+    for o in range(len(ops)):
+        assert row_rel_err(w64[:, o], w_ref[:, o]) < 1e-9
+
+
+def test_weights_singular_row_flagged(api):
+    rng = np.random.default_rng(4)
+    pts = 0.5 + rng.uniform(-0.05, 0.05, size=(60, 3))
+    S = nc.stencils(pts, 30)[:3].copy()
+    S[1, 5] = S[1, 6]  # repeated node in one stencil: singular system
+    _, _, info = api.rbffd_weights(dev(pts.T, torch.float64), dev(S.T, torch.int32), [("dx",)])
+    info = info.cpu().numpy()
+    assert info[0] == 0 and info[1] > 0 and info[2] == 0
+
+
+def test_weights_argument_errors(api, small_cloud):
+    from paper_2404_14195_amd import MPFError
+    c = small_cloud
+    S = nc.stencils(c.pos, 31)[:4]
+    with pytest.raises(MPFError, match="unsupported"):
+        api.rbffd_weights(dev(c.pos.T, torch.float64), dev(S.T, torch.int32), [("dx",)])
+    S = nc.stencils(c.pos, 30)[:4]
+    with pytest.raises(MPFError, match="invalid"):
+        api.rbffd_weights(dev(c.pos.T, torch.float64), dev(S.T, torch.int32), [("dn",)])  # no rowvec
+
+
+# ----------------------------------------------------------------- ACM
+
+def acm_pair(api, disc, precision, steps, v_ref=1e-3):
+    from paper_2404_14195_amd.solvers import ACMSolver
+    c = disc.cloud
+    g = ACMSolver(disc, precision=precision, v_ref=v_ref)
+    o = O.ACM(c.pos, c.n_int, disc.sten_host, c.nrm, sten_n=nc.neumann_stencils(c, 30), h_min=c.h_min,
+              v_ref=v_ref)
+    g.run(steps)
+    o.run(steps)
+    return g, o
+
+
+def test_acm_parity_fp64_500_steps(api, disc_small):
+    """The plain-ACM workload: 500 explicit steps, FP64, GPU weights vs
+    oracle weights end to end: fields and permeability within 1e-10."""
+    g, o = acm_pair(api, disc_small, 0, 500)
+    v = g.v.cpu().numpy().T
+    p = g.p.cpu().numpy()
+    assert np.abs(v - o.v).max() <= 1e-10 * np.abs(o.v).max()
+    assert np.abs(p - o.p).max() <= 1e-10 * np.abs(o.p).max()
+    C = 10.0 * max(g.vmax.item(), 1e-3)
+    assert C == pytest.approx(o.C[0], rel=1e-12)
+    pp = disc_small.plan
+    q_o = O.flux(pp.idx, O.plane_weights(disc_small.cloud.pos, pp.idx, pp.shift), o.v[:, 0], disc_small.n_all)
+    assert g.permeability() == pytest.approx(q_o, rel=1e-10)
+
+
+def test_acm_fp32_error_vs_fp64(api, disc_small):
+    """FP32 stencil apply and state, FP64 reductions: permeability after 500
+    steps within 1e-4 of the FP64 oracle."""
+    g, o = acm_pair(api, disc_small, 1, 500)
+    pp = disc_small.plan
+    q_o = O.flux(pp.idx, O.plane_weights(disc_small.cloud.pos, pp.idx, pp.shift), o.v[:, 0], disc_small.n_all)
+    k32 = g.permeability()
+    print(f"[acm fp32] k32={k32:.9e} k64={q_o:.9e} rel={abs(k32 / q_o - 1):.3e}", flush=True)
+    assert k32 == pytest.approx(q_o, rel=1e-4)
+
+
+def test_acm_zero_steps_and_rest(api, disc_small):
+    from paper_2404_14195_amd.solvers import ACMSolver
+    g = ACMSolver(disc_small, g=(0.0, 0.0, 0.0))
+    g.run(0)
+    g.run(3)
+    assert not g.v.any().item() and not g.p.any().item()
+
+
+# ----------------------------------------------------------------- MLBM
+
+@pytest.mark.parametrize("q", [19, 15])
+def test_lbm_step_parity_shared_weights(api, disc_small, q):
+    """Stream/bounce-back/collide against the oracle with the same (oracle)
+    interpolation weights, over an odd and an even number of steps."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    c = disc_small.cloud
+    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=q, h_min=c.h_min)
+    W = dev(o.W[:, 1:, :].transpose(1, 2, 0), torch.float64)  # [q-1][nl][n]
+    g = MLBMSolver(disc_small, q=q, precision=0, W=W)
+    e, wk, _ = O.lattice(q)
+    done = 0
+    for steps in (1, 2, 37):
+        g.run(steps)
+        o.run(steps)
+        done += steps
+        fg = g.f.cpu().numpy().T + wk  # shifted storage -> f
+        dev_o = o.f - wk
+        assert np.abs(fg - o.f).max() <= 1e-10 * np.abs(dev_o).max(), (steps, np.abs(fg - o.f).max())
+    _, u_o = O.moments(q, o.f)
+    v, _ = g.macros()
+    u_g = v.cpu().numpy().T / g.units["vel_scale"]
+    assert np.abs(u_g - u_o).max() <= 1e-10 * np.abs(u_o).max()
+
+
+def test_lbm_parity_fp64_own_weights(api, disc_small):
+    """End to end (each side its own weights), 200 steps, D3Q19."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    c = disc_small.cloud
+    g = MLBMSolver(disc_small, q=19, precision=0)
+    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=19, h_min=c.h_min)
+    g.run(200)
+    o.run(200)
+    v_o, _ = o.macros()
+    pp = disc_small.plan
+    k_o = O.flux(pp.idx, O.plane_weights(c.pos, pp.idx, pp.shift), v_o[:, 0], disc_small.n_all)
+    k_g = g.permeability()
+    print(f"[lbm fp64 e2e] k_gpu={k_g:.12e} k_oracle={k_o:.12e} rel={abs(k_g / k_o - 1):.3e}", flush=True)
+    assert k_g == pytest.approx(k_o, rel=1e-8)
+
+
+def test_lbm_fp32_shifted_error(api, disc_small):
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    c = disc_small.cloud
+    g = MLBMSolver(disc_small, q=19, precision=1)
+    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=19, h_min=c.h_min)
+    g.run(200)
+    o.run(200)
+    v_o, _ = o.macros()
+    pp = disc_small.plan
+    k_o = O.flux(pp.idx, O.plane_weights(c.pos, pp.idx, pp.shift), v_o[:, 0], disc_small.n_all)
+    k_g = g.permeability()
+    print(f"[lbm fp32] k32={k_g:.9e} k64={k_o:.9e} rel={abs(k_g / k_o - 1):.3e}", flush=True)
+    assert k_g == pytest.approx(k_o, rel=1e-4)
+
+
+# ----------------------------------------------------------------- reductions
+
+def test_flux_and_drag_parity(api, disc_small):
+    c = disc_small.cloud
+    rng = np.random.default_rng(9)
+    v = rng.normal(size=(c.n, 3))
+    p = rng.normal(size=c.n)
+    pp = disc_small.plan
+    pw = O.plane_weights(c.pos, pp.idx, pp.shift)
+    q_o = O.flux(pp.idx, pw, v[:, 0], disc_small.n_all)
+    vd = dev(v.T, torch.float64)
+    q_g = api.flux_planes(disc_small.s_idx, disc_small.s_w, vd[0], disc_small.n_all).item()
+    assert q_g == pytest.approx(q_o, rel=1e-12)
+    S = disc_small.sten_host
+    wg, _ = O.weights(c.pos, S[c.n_int:], [("dx",), ("dy",), ("dz",)])
+    dA = O.area(c.r) / c.n_bnd
+    F_o = O.drag(S[c.n_int:], wg, c.nrm, v, p, 1.1, 0.9, dA)
+    wg_d = dev(wg.transpose(1, 2, 0), torch.float64)
+    F_g = api.drag(vd, dev(p, torch.float64), disc_small.sb, wg_d, disc_small.nrm, 1.1, 0.9, dA).cpu().numpy()
+    assert np.abs(F_g - F_o).max() <= 1e-11 * np.abs(F_o).max()
+    # bitwise reproducible reruns (fixed-order sums)
+    q_g2 = api.flux_planes(disc_small.s_idx, disc_small.s_w, vd[0], disc_small.n_all).item()
+    assert q_g2 == q_g
+
+
+def test_geometry_from_library(api):
+    for r in (0.04, 0.3, 0.55, 0.69):
+        phi, A = api.sc_cell(r)
+        assert phi == pytest.approx(O.porosity(r), rel=1e-15)
+        assert A == pytest.approx(O.area(r), rel=1e-15)
+
+
+# ----------------------------------------------------------------- full size
+
+def test_lbm_full_size_one_cell(api):
+    """The MLBM workload cell at full size (about 71k nodes), in the launch
+    configuration the benchmark times: 3 steps FP64 against the oracle with
+    shared weights, and the FP32 path's state deviation."""
+    from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
+    cloud = nc.config_cloud("lbm_mid")
+    disc = Discretization(cloud, nl=30, M=64, plan=False)
+    o = O.MLBM(cloud.pos, cloud.n_int, disc.sten_host, cloud.nrm, q=19, h_min=cloud.h_min)
+    W = dev(o.W[:, 1:, :].transpose(1, 2, 0), torch.float64)
+    g = MLBMSolver(disc, q=19, precision=0, W=W)
+    g.run(3)
+    o.run(3)
+    _, wk, _ = O.lattice(19)
+    fg = g.f.cpu().numpy().T + wk
+    assert np.abs(fg - o.f).max() <= 1e-10 * np.abs(o.f - wk).max()
+    # GPU weights of a sample of rows against the oracle
+    rows = np.arange(0, cloud.n, 997)
+    ops = [("shift", (-0.004, 0, 0)), ("shift", (0, 0.004, -0.004))]
+    w_ref, _ = O.weights(cloud.pos, disc.sten_host[rows], ops)
+    w64, _, _ = api.rbffd_weights(disc.pos, dev(disc.sten_host[rows].T, torch.int32), ops)
+    w64 = w64.cpu().numpy().transpose(2, 0, 1)
+    for o_ in range(2):
+        assert row_rel_err(w64[:, o_], w_ref[:, o_]) < 1e-10

@@ -1,0 +1,70 @@
+"""libmpf loads on the host, exports every symbol include/mpf.h declares, and
+rejects bad arguments before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_14195_amd import _lib
+    return _lib.lib()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mpf.h")).read()
+    return sorted(set(re.findall(r"\b(mpf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_binding_covers_the_header():
+    from paper_2404_14195_amd import _lib
+    assert sorted(_lib.EXPORTED) == declared_symbols()
+
+
+def test_error_strings_and_version(lib):
+    assert lib.mpf_strerror(0) == b"ok"
+    for code in (-1, -2, -3, -4):
+        assert lib.mpf_strerror(code) not in (b"", b"unknown error code")
+    assert lib.mpf_version() >= 100
+
+
+def test_sc_cell_host(lib):
+    phi, area = ctypes.c_double(), ctypes.c_double()
+    assert lib.mpf_sc_cell(0.3, ctypes.byref(phi), ctypes.byref(area)) == 0
+    assert phi.value == pytest.approx(1 - 4 / 3 * 3.141592653589793 * 0.027, rel=1e-15)
+    assert lib.mpf_sc_cell(0.8, ctypes.byref(phi), ctypes.byref(area)) == -1
+
+
+def test_host_argument_checks(lib):
+    from paper_2404_14195_amd._lib import AcmParams, LbmParams, make_ops
+    ops = make_ops([("dx",)])
+    # null pointers, bad sizes: rejected before any launch
+    assert lib.mpf_rbffd_weights(None, 10, None, 5, 30, 1, ops, None, None, None, None, None) == -1
+    fake = ctypes.c_void_p(16)
+    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 30, 0, ops, None, fake, None, fake, None) == -1
+    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 31, 1, ops, None, fake, None, fake, None) == -3
+    prm = AcmParams(nu=1, rho=1, dt=1e-5, beta=10, v_ref=1e-3, n_p=3, precision=0)
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 0,
+                           None) == -4  # workspace too small
+    prm.n_p = 0
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 1 << 20,
+                           None) == -1
+    lp = LbmParams(q=17, precision=0, tau_plus=1.0, tau_minus=1.0)
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, 1, None) == -1
+    lp.q, lp.tau_plus = 19, 0.5
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, 1, None) == -1
+    assert lib.mpf_flux_planes(5, 30, fake, fake, fake, 0, 0, fake, fake, 1 << 20, None) == -1
+    assert lib.mpf_drag(10, fake, fake, 0, 2, 30, fake, fake, fake, 1.0, 1.0, 0.1, fake, fake, 8, None) == -4
+    assert lib.mpf_acm_workspace(1000, 0) >= 3 * 1000 * 8
+    assert lib.mpf_acm_workspace(1000, 1) >= 3 * 1000 * 4
