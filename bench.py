@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
@@ -54,6 +56,12 @@ def main():
     from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
 
     torch.cuda.set_device(0)
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_setup = time.perf_counter()
     cloud = nc.config_cloud("lbm_mid")
     disc = Discretization(cloud, nl=30, M=64)
