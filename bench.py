@@ -33,6 +33,56 @@ def bytes_per_node_step(q, nl, s_w, s_f, s_i=4):
     return (q - 1) * s_w * nl + s_i * nl + 2 * q * s_f
 
 
+def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4):
+    """Algorithmic bytes of one ACM node-step: predictor (4 operators, v in,
+    v' out), then per coupling iteration a pressure pass (3 operators, v and p
+    in, p out) and a velocity pass (3 operators, p and v' in, v out)."""
+    return ((4 * s_w + s_i) * nl + 6 * s_f + n_p * ((3 * s_w + s_i) * nl + 5 * s_f)
+            + n_p * ((3 * s_w + s_i) * nl + 7 * s_f))
+
+
+def acm_and_weights(torch, nc, api):
+    """Side measurements: the plain-ACM cell (about 8k nodes, 500 steps) and the
+    large ACM sweep cell (r = 0.3, h 0.002 -> 0.008, about 1.9M nodes)."""
+    from paper_2404_14195_amd import MPF_F32, MPF_F64
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization
+    out = {}
+    for name, steps in (("acm_small", 500), ("acm_large", 200)):
+        t0 = time.perf_counter()
+        cloud = nc.config_cloud(name)
+        disc = Discretization(cloud, nl=30, M=64)
+        print(f"[bench] {name}: {cloud.n} nodes, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        rec = {"n_nodes": cloud.n, "n_boundary": cloud.n_bnd, "steps": steps}
+        for pname, prec in (("fp64", MPF_F64), ("fp32", MPF_F32)):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            s = ACMSolver(disc, precision=prec)
+            ev1.record()
+            torch.cuda.synchronize()
+            w_ms = ev0.elapsed_time(ev1)
+            s.run(5)
+            torch.cuda.synchronize()
+            s2 = ACMSolver(disc, precision=prec)
+            ev0.record()
+            s2.run(steps)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            bpn = acm_bytes_per_node_step(30, 8 if prec == MPF_F64 else 4, 8 if prec == MPF_F64 else 4)
+            rec[pname] = {"us_per_step": ms * 1e3 / steps, "node_steps_per_s": cloud.n * steps / (ms * 1e-3),
+                          "k_after": s2.permeability(), "hbm_frac": bpn * cloud.n / (ms * 1e-3 / steps) / 1e9
+                          / HBM_PEAK_GBS, "weights_ms": w_ms}
+            print(f"[bench] {name} {pname}: {ms * 1e3 / steps:.1f} us/step k={rec[pname]['k_after']:.6e}",
+                  file=sys.stderr, flush=True)
+            del s, s2
+        rec["k_rel_err_fp32"] = abs(rec["fp32"]["k_after"] / rec["fp64"]["k_after"] - 1.0)
+        out[name] = rec
+        del disc
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +90,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the ACM and weight-solve side measurements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -139,6 +190,8 @@ def main():
                "sample": f"{n_cpu} FP64 steps of the full {cloud.n}-node cell (weights precomputed, not timed), "
                          f"single-threaded scalar C"}
 
+    extra = None if args.no_extra else acm_and_weights(torch, nc, api)
+
     out = {
         "metric": METRIC, "value": f32["value"], "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": f32["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -155,6 +208,7 @@ def main():
         "weights_ms": {"fp32": f32["weights_ms"], "fp64": res["f64"]["weights_ms"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "acm": extra,
     }
     print(json.dumps(out))
 

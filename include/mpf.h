@@ -21,8 +21,11 @@
  *     stencils         sten[nl][m]        int32, column 0 = the row's centre
  *     weights          w[n_ops][nl][m]    double or float
  *     velocity         v[3][n]            double or float (precision flag)
- *     populations      f[q][n]            double or float, stored shifted by
- *                                         the lattice weight: f~_k = f_k - w_k
+ *     populations      f[n][qp]           double or float, node-major records
+ *                                         of qp = 20 (D3Q19) or 16 (D3Q15)
+ *                                         values; entries k >= q are zero.
+ *                                         Stored shifted by the lattice
+ *                                         weight: f~_k = f_k - w_k
  * - Nodes [0, n_int) are interior; nodes [n_int, n) lie on the grain surface,
  *   with unit normals nrm[3][nb] (nb = n - n_int) pointing from the solid into
  *   the fluid.
@@ -168,7 +171,7 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  *   bounce-back at boundary node b: where e_k . n_b > 0, f_k = f_{opp(k)}.
  * W     dev [q-1][nl][n] (population k uses slice k - 1), precision as f
  * nrm   dev [3][nb] double
- * f     dev [q][n] state, updated in place; f_tmp dev [q][n] scratch
+ * f     dev [n][qp] state, updated in place; f_tmp dev [n][qp] scratch
  * q is 15 or 19. */
 typedef struct {
   int32_t q;

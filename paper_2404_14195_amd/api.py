@@ -94,18 +94,25 @@ def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: in
                           int(n_steps), _p(ws), ws.numel(), _stream()), "mpf_acm_run")
 
 
+def record_len(q: int) -> int:
+    """Padded length of one node's population record (node-major layout)."""
+    return {19: 20, 15: 16}[q]
+
+
 def lbm_init(prm: LbmParams, f, rho=1.0, u=(0.0, 0.0, 0.0)):
     _need(f, _DT[prm.precision], name="f")
+    if f.dim() != 2 or f.shape[1] != record_len(prm.q):
+        raise ValueError("f must be [n][qp]")
     uu = (ctypes.c_double * 3)(*[float(x) for x in u])
-    check(lib().mpf_lbm_init(ctypes.byref(prm), f.shape[1], float(rho), uu, _p(f), _stream()), "mpf_lbm_init")
+    check(lib().mpf_lbm_init(ctypes.byref(prm), f.shape[0], float(rho), uu, _p(f), _stream()), "mpf_lbm_init")
 
 
 def lbm_run(prm: LbmParams, n_int: int, sten, W, nrm, f, f_tmp, n_steps: int):
     dt = _DT[prm.precision]
     nl, n = sten.shape
     _need(W, dt, (prm.q - 1, nl, n), "W")
-    _need(f, dt, (prm.q, n), "f")
-    _need(f_tmp, dt, (prm.q, n), "f_tmp")
+    _need(f, dt, (n, record_len(prm.q)), "f")
+    _need(f_tmp, dt, (n, record_len(prm.q)), "f_tmp")
     if n > n_int:
         _need(nrm, torch.float64, (3, n - n_int), "nrm")
     check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(nrm), _p(f), _p(f_tmp), int(n_steps),
@@ -113,7 +120,8 @@ def lbm_run(prm: LbmParams, n_int: int, sten, W, nrm, f, f_tmp, n_steps: int):
 
 
 def lbm_moments(prm: LbmParams, f, vel_scale: float, v=None, p=None):
-    n = f.shape[1]
+    _need(f, _DT[prm.precision], name="f")
+    n = f.shape[0]
     v = torch.empty((3, n), dtype=torch.float64, device=f.device) if v is None else v
     p = torch.empty(n, dtype=torch.float64, device=f.device) if p is None else p
     check(lib().mpf_lbm_moments(ctypes.byref(prm), n, _p(f), float(vel_scale), _p(v), _p(p), _stream()),

@@ -1,18 +1,19 @@
 // Meshless TRT lattice Boltzmann steps (Sec. 2.2) on gfx950.
 //
-// State: populations shifted by their lattice weight, f~_k = f_k - w_k, in
-// [q][n] layout.  The shift makes FP32 storage usable: the forcing term per
+// State: populations shifted by their lattice weight, f~_k = f_k - w_k, stored
+// node-major as records of qp values (qp = 20 for D3Q19, 16 for D3Q15; the
+// padding entries stay zero), so one neighbour's populations arrive with a
+// few 16-byte loads from one or two cache lines.  The shift makes FP32 storage usable: the forcing term per
 // step is about 1e-9 of f_k, below FP32 resolution of f_k itself but not of
 // the deviation f~_k.  The equilibrium and the TRT split are written for the
 // shifted values directly (w_k = w_{opp(k)}, so the shift cancels in f - f^eq).
 //
-// A step is one fused pass per node: gather-stream the post-collision
+// A step is one fused pass per node tile: gather-stream the post-collision
 // populations of the stencil (Eq. LBM_streaming with interpolation weights of
 // Eq. operatorApprox), bounce back the unknown populations of surface nodes
 // (Eq. interpolated_bounceback_mlbm), then collide (Eqs. macro_var, feq,
-// LBM_collision, force_lbm) and write the next post-collision state.  The
-// stencil index of column j is loaded once and reused by all q - 1 moving
-// populations; weights stream coalesced from [k][j][node].
+// LBM_collision, force_lbm) and write the next post-collision state.  Weights
+// stream coalesced from [k][j][node].
 #include "common.hpp"
 
 namespace mpf {
@@ -24,6 +25,31 @@ template <typename T>
 struct Prm {
   T itp, itm;  // 1/tau+, 1/tau-
   T g0, g1, g2;
+};
+
+// Record length of a node's populations in the node-major layout.
+template <int Q>
+struct Pad;
+template <>
+struct Pad<19> {
+  static constexpr int QP = 20;
+};
+template <>
+struct Pad<15> {
+  static constexpr int QP = 16;
+};
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
 };
 
 // TRT collision of one node's shifted populations, in place.
@@ -68,34 +94,94 @@ __device__ __forceinline__ void collide(T (&f)[Q], const Prm<T>& pr) {
 template <typename T, int Q>
 __global__ __launch_bounds__(kBlock) void lbm_collide(int64_t n, const T* src, T* dst,
                                                       Prm<T> pr) {
+  constexpr int QP = Pad<Q>::QP;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   T f[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) f[k] = src[k * n + i];
+  for (int k = 0; k < Q; ++k) f[k] = src[i * QP + k];
   collide<T, Q>(f, pr);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) dst[k * n + i] = f[k];
+  for (int k = 0; k < Q; ++k) dst[i * QP + k] = f[k];
 }
 
+// Blocks take 64-node tiles; hardware hands workgroups to the 8 XCDs round
+// robin, so block b works on tile (b % 8) * (G / 8) + b / 8 and each XCD's L2
+// sees one contiguous (Morton-ordered, hence compact) range of nodes.
+constexpr int kTile = 64;
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) { return (b % kXcd) * (G / kXcd) + b / kXcd; }
+
+inline unsigned tiles_grid(int64_t n) {
+  int64_t t = (n + kTile - 1) / kTile;
+  t = (t + kXcd - 1) / kXcd * kXcd;
+  return (unsigned)t;
+}
+
+// One step for a tile of 64 nodes (lane = node).  The four waves of the
+// block take every fourth stencil column; for each column a lane loads its
+// neighbour's whole population record with 16-byte loads and accumulates all
+// q - 1 moving populations against the coalesced weights.  The four partial
+// sums meet in LDS and are added in a fixed order by the first wave, which
+// then applies bounce-back and the collision and writes the tile.  Weights
+// are read once per step and never reused, so they are loaded
+// non-temporally to leave L2 to the gathered records.
 template <typename T, int Q, bool COLLIDE>
 __global__ __launch_bounds__(kBlock) void lbm_step(int64_t n, int64_t n_int, int nl, const int32_t* __restrict__ sten,
                                                    const T* __restrict__ W, const double* __restrict__ nrm,
                                                    const T* __restrict__ src, T* __restrict__ dst, Prm<T> pr) {
   using L = Lattice<Q>;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+  constexpr int QP = Pad<Q>::QP;
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int NV = QP / VN;
+  constexpr int NW = kBlock / kWave;
+  __shared__ T part[NW][Q - 1][kTile];
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile * kTile >= n) return;  // whole block
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int64_t i = tile * kTile + lane;
+  const bool live = i < n;
+  const int64_t ic = live ? i : n - 1;
   const int64_t ks = (int64_t)nl * n;  // population stride in W
-  T f[Q];
-  f[0] = src[i];
+  T acc[Q];
 #pragma unroll
-  for (int k = 1; k < Q; ++k) f[k] = T(0);
-  for (int j = 0; j < nl; ++j) {
-    const int64_t at = (int64_t)j * n + i;
-    const int s = sten[at];
+  for (int k = 0; k < Q; ++k) acc[k] = T(0);
+#pragma unroll 2
+  for (int j = wv; j < nl; j += NW) {
+    const int64_t at = (int64_t)j * n + ic;
+    const int64_t s = sten[at];
+    const V* rec = reinterpret_cast<const V*>(src + s * QP);
+    T r[QP];
 #pragma unroll
-    for (int k = 1; k < Q; ++k) f[k] += W[(k - 1) * ks + at] * src[k * n + s];
+    for (int v = 0; v < NV; ++v) {
+      V x = rec[v];
+      if constexpr (VN == 4) {
+        r[4 * v] = x.x; r[4 * v + 1] = x.y; r[4 * v + 2] = x.z; r[4 * v + 3] = x.w;
+      } else {
+        r[2 * v] = x.x; r[2 * v + 1] = x.y;
+      }
+    }
+#pragma unroll
+    for (int k = 1; k < Q; ++k) acc[k] += __builtin_nontemporal_load(&W[(k - 1) * ks + at]) * r[k];
   }
+#pragma unroll
+  for (int k = 1; k < Q; ++k) part[wv][k - 1][lane] = acc[k];
+  __syncthreads();
+  if (wv != 0 || !live) return;
+  T f[QP];
+  f[0] = src[ic * QP];
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    T sum = part[0][k - 1][lane];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) sum += part[w][k - 1][lane];
+    f[k] = sum;
+  }
+#pragma unroll
+  for (int k = Q; k < QP; ++k) f[k] = T(0);
   if (i >= n_int) {
     const int64_t b = i - n_int, nb = n - n_int;
     const double nx = nrm[b], ny = nrm[nb + b], nz = nrm[2 * nb + b];
@@ -108,9 +194,25 @@ __global__ __launch_bounds__(kBlock) void lbm_step(int64_t n, int64_t n_int, int
       if (en > 0.0) f[k] = g[lat_opp(k)];
     }
   }
-  if (COLLIDE) collide<T, Q>(f, pr);
+  if (COLLIDE) {
+    T c[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) dst[k * n + i] = f[k];
+    for (int k = 0; k < Q; ++k) c[k] = f[k];
+    collide<T, Q>(c, pr);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = c[k];
+  }
+  V* out = reinterpret_cast<V*>(dst + i * QP);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    V x;
+    if constexpr (VN == 4) {
+      x.x = f[4 * v]; x.y = f[4 * v + 1]; x.z = f[4 * v + 2]; x.w = f[4 * v + 3];
+    } else {
+      x.x = f[2 * v]; x.y = f[2 * v + 1];
+    }
+    out[v] = x;
+  }
 }
 
 template <typename T, int Q>
@@ -119,13 +221,16 @@ __global__ __launch_bounds__(kBlock) void lbm_init(int64_t n, T* __restrict__ f,
   using L = Lattice<Q>;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  constexpr int QP = Pad<Q>::QP;
   const double uu = u0 * u0 + u1 * u1 + u2 * u2;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const double eu = L::ex[k] * u0 + L::ey[k] * u1 + L::ez[k] * u2;
     const double wk = lat_w<Q>(k);
-    f[k * n + i] = (T)(wk * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
+    f[i * QP + k] = (T)(wk * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
   }
+#pragma unroll
+  for (int k = Q; k < QP; ++k) f[i * QP + k] = T(0);
 }
 
 template <typename T, int Q>
@@ -137,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __rest
   double drho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const double fk = (double)f[k * n + i];
+    const double fk = (double)f[i * Pad<Q>::QP + k];
     drho += fk;
     j0 += L::ex[k] * fk;
     j1 += L::ey[k] * fk;
@@ -166,13 +271,14 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
     hipLaunchKernelGGL((lbm_collide<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, f, pr);
     cur = f;
   }
+  const unsigned gt = tiles_grid(n);
   for (int s = 0; s < n_steps - 1; ++s) {
     T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<T, Q, true>), dim3(g), dim3(kBlock), 0, st, n, n_int, nl, sten, W, nrm,
+    hipLaunchKernelGGL((lbm_step<T, Q, true>), dim3(gt), dim3(kBlock), 0, st, n, n_int, nl, sten, W, nrm,
                        (const T*)cur, nxt, pr);
     cur = nxt;
   }
-  hipLaunchKernelGGL((lbm_step<T, Q, false>), dim3(g), dim3(kBlock), 0, st, n, n_int, nl, sten, W, nrm,
+  hipLaunchKernelGGL((lbm_step<T, Q, false>), dim3(gt), dim3(kBlock), 0, st, n, n_int, nl, sten, W, nrm,
                      (const T*)cur, f, pr);
   MPF_LAUNCH_CHECK();
   return MPF_OK;

@@ -123,6 +123,14 @@ def lattice_vectors(q: int):
     return e
 
 
+def lattice_weights(q: int):
+    """w_k of the velocity set in the same order (used only to convert the
+    shifted device state for host-side inspection)."""
+    w0, w1, w2 = (1 / 3, 1 / 18, 1 / 36) if q == 19 else (2 / 9, 1 / 9, 1 / 72)
+    return np.array([w0 if sum(x * x for x in v) == 0 else (w1 if sum(x * x for x in v) == 1 else w2)
+                     for v in lattice_vectors(q)])
+
+
 class MLBMSolver:
     """Meshless TRT lattice Boltzmann (Sec. 2.2) on a Discretization."""
 
@@ -142,7 +150,7 @@ class MLBMSolver:
             W = w64 if precision == MPF_F64 else w32
         self.W = W
         dtp = _DT[precision]
-        self.f = torch.empty((q, disc.n), dtype=dtp, device=disc.device)
+        self.f = torch.empty((disc.n, api.record_len(q)), dtype=dtp, device=disc.device)
         self.f_tmp = torch.empty_like(self.f)
         api.lbm_init(self.prm, self.f)
         self.steps = 0
@@ -153,6 +161,16 @@ class MLBMSolver:
     def run(self, n_steps: int):
         api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.d.nrm, self.f, self.f_tmp, n_steps)
         self.steps += n_steps
+
+    def populations(self):
+        """Host copy of the state as f [n][q] (unshifted)."""
+        return self.f[:, :self.q].double().cpu().numpy() + lattice_weights(self.q)
+
+    def set_populations(self, f):
+        """Load f [n][q] (unshifted, host) into the device state."""
+        buf = np.zeros(tuple(self.f.shape))
+        buf[:, :self.q] = np.asarray(f) - lattice_weights(self.q)
+        self.f.copy_(torch.as_tensor(buf, dtype=self.f.dtype, device=self.f.device))
 
     def macros(self):
         return api.lbm_moments(self.prm, self.f, self.units["vel_scale"], self._v, self._p)
