@@ -33,6 +33,22 @@ def bytes_per_node_step(q, nl, s_w, s_f, s_i=4):
     return (q - 1) * s_w * nl + s_i * nl + 2 * q * s_f
 
 
+def measured_traffic():
+    """HBM bytes per launch of the FP32 step kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE runs (scaled by a plain copy), or None
+    if the kernel source has changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "lbm_step_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4):
     """Algorithmic bytes of one ACM node-step: predictor (4 operators, v in,
     v' out), then per coupling iteration a pressure pass (3 operators, v and p
@@ -169,10 +185,11 @@ def main():
         torch.cuda.empty_cache()
 
     f32 = res["f32"]
+    traffic = measured_traffic()
     bpn = bytes_per_node_step(19, 30, 4, 4)
     achieved = bpn * disc.n / (f32["step_kernel_ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "lbm_step<float,19,true>", "bytes_per_node_step": bpn,
+            "traffic": traffic, "kernel": "lbm_step<float,19,true>", "bytes_per_node_step": bpn,
             "launch_ms": f32["step_kernel_ms"]}
 
     cpu = None
