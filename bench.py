@@ -69,6 +69,18 @@ def acm_and_weights(torch, nc, api):
         disc = Discretization(cloud, nl=30, M=64)
         print(f"[bench] {name}: {cloud.n} nodes, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
         rec = {"n_nodes": cloud.n, "n_boundary": cloud.n_bnd, "steps": steps}
+        if name == "acm_large" and os.environ.get("MPF_BENCH_LANE_SWEEP"):
+            for lanes in (1, 2, 4, 8, 16):
+                s3 = ACMSolver(disc, precision=MPF_F32, lanes=lanes)
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                s3.run(50)
+                ev1.record()
+                torch.cuda.synchronize()
+                print(f"[bench] {name} fp32 lanes={lanes}: {ev0.elapsed_time(ev1) * 1e3 / 50:.1f} us/step",
+                      file=sys.stderr, flush=True)
+                del s3
         for pname, prec in (("fp64", MPF_F64), ("fp32", MPF_F32)):
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)

@@ -145,12 +145,17 @@ int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, i
  *       state at rest); C is derived from it
  * ws    workspace of mpf_acm_workspace() bytes
  * Fields and weights share one precision (MPF_F64 or MPF_F32).  With MPF_F32
- * all arithmetic except the max is FP32. */
+ * all arithmetic except the max is FP32.
+ * lanes: how many adjacent lanes share one node's stencil sum (1, 2, 4, 8 or
+ * 16; 0 picks 8 for n_int <= 200000 and 2 above).  Results agree to rounding
+ * (the order of the partial sums differs). */
 typedef struct {
   double nu, rho, dt, beta, v_ref;
   double g[3];
   int32_t n_p;
   int32_t precision;
+  int32_t lanes;
+  int32_t reserved;
 } mpf_acm_params;
 
 size_t mpf_acm_workspace(int64_t n, int precision);

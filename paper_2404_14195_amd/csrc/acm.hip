@@ -1,11 +1,9 @@
 // Artificial-compressibility Navier-Stokes steps (Sec. 2.3, Eqs.
 // MNS_intermediate, MNS_pressure, MNS_velocity, MNS_C) on gfx950.
 //
-// Every pass is an HBM-bound stencil apply: one thread per node walks its
-// nl stencil columns; weights and stencil indices are stored [op][j][node]
-// so the 64 lanes of a wave read consecutive addresses, while the gathered
-// field values come from the caches (nodes are Morton ordered).  A step is
-// 1 + 3 n_p dependent passes:
+// Every pass is a stencil apply: weights and stencil indices are stored
+// [op][j][node], field values are gathered through the caches (nodes are
+// Morton ordered).  A step is 1 + 3 n_p dependent passes:
 //   predictor  (interior)     v' from v: 4 operators x 3 components
 //   n_p x { pressure (interior)  p -= dt C^2 rho div v
 //           neumann  (boundary)  p_b from dp/dn = 0, in place (its stencil
@@ -14,6 +12,13 @@
 // C is never stored: each pressure pass derives it from the running max |v|
 // (device double, updated with an integer atomicMax on the bit pattern, which
 // orders non-negative doubles), so no host round trip enters a step.
+//
+// Each node's stencil sum is split over LPN adjacent lanes (lane sl takes
+// columns sl, sl + LPN, ...) and closed with a fixed butterfly, which shortens
+// the chain of dependent gathers per lane.  One launch per pass: measured on
+// the 8k-node cell, a persistent cooperative kernel with grid barriers between
+// passes and a replayed HIP graph were both slower than plain launches once
+// the gather chain was split 8 ways (126 -> 50 us per step).
 #include "common.hpp"
 
 namespace mpf {
@@ -21,24 +26,42 @@ namespace {
 
 constexpr int kBlock = 256;
 
+template <int LPN, typename T>
+__device__ __forceinline__ T group_sum(T x) {
+#pragma unroll
+  for (int off = LPN / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void acm_predictor(int64_t n, int64_t n_int, int nl,
-                                                        const int32_t* __restrict__ sten, const T* __restrict__ w,
-                                                        const T* __restrict__ v, T* __restrict__ vp, T nu, T dt,
-                                                        T g0, T g1, T g2) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n_int) return;
-  const int64_t os = (int64_t)nl * n;  // operator stride in w
+struct Fields {
+  int64_t n, n_int, nb;
+  int nl;
+  const int32_t* sten;
+  const T* w;  // [4][nl][n]
+  const int32_t* sn;
+  const T* wn;  // [nl][nb]
+  T* v;         // [3][n]
+  T* p;         // [n]
+  T* vp;        // [3][n]
+  double* vmax;
+  T nu, dt, dt_rho, g0, g1, g2;
+  double dtd, rho, beta, v_ref;
+};
+
+template <typename T, int LPN>
+__device__ __forceinline__ void predictor_node(const Fields<T>& F, int64_t i, int sl) {
+  const int64_t n = F.n, os = (int64_t)F.nl * n;
   T d[3][4];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int o = 0; o < 4; ++o) d[a][o] = T(0);
-  for (int j = 0; j < nl; ++j) {
+  for (int j = sl; j < F.nl; j += LPN) {
     const int64_t at = (int64_t)j * n + i;
-    const int s = sten[at];
-    const T wx = w[at], wy = w[os + at], wz = w[2 * os + at], wl = w[3 * os + at];
-    const T u[3] = {v[s], v[n + s], v[2 * n + s]};
+    const int s = F.sten[at];
+    const T wx = F.w[at], wy = F.w[os + at], wz = F.w[2 * os + at], wl = F.w[3 * os + at];
+    const T u[3] = {F.v[s], F.v[n + s], F.v[2 * n + s]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       d[a][0] += wx * u[a];
@@ -47,90 +70,126 @@ __global__ __launch_bounds__(kBlock) void acm_predictor(int64_t n, int64_t n_int
       d[a][3] += wl * u[a];
     }
   }
-  const T vi[3] = {v[i], v[n + i], v[2 * n + i]};
-  const T g[3] = {g0, g1, g2};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const T adv = vi[0] * d[a][0] + vi[1] * d[a][1] + vi[2] * d[a][2];
-    vp[a * n + i] = vi[a] + dt * (nu * d[a][3] - adv + g[a]);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void acm_pressure(int64_t n, int64_t n_int, int nl,
-                                                       const int32_t* __restrict__ sten, const T* __restrict__ w,
-                                                       const T* __restrict__ v, T* __restrict__ p,
-                                                       const double* __restrict__ vmax, double dt, double rho,
-                                                       double beta, double v_ref) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n_int) return;
-  const double vm = *vmax;
-  const double C = beta * (vm > v_ref ? vm : v_ref);
-  const T coef = (T)(dt * (C * C) * rho);
-  const int64_t os = (int64_t)nl * n;
-  T div = T(0);
-  for (int j = 0; j < nl; ++j) {
-    const int64_t at = (int64_t)j * n + i;
-    const int s = sten[at];
-    div += w[at] * v[s] + w[os + at] * v[n + s] + w[2 * os + at] * v[2 * n + s];
-  }
-  p[i] -= coef * div;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void acm_neumann(int64_t n_int, int64_t nb, int nl,
-                                                      const int32_t* __restrict__ sn, const T* __restrict__ wn,
-                                                      T* __restrict__ p, double* __restrict__ vmax) {
-  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (b == 0) *vmax = 0.0;  // the pressure pass has consumed it; the velocity pass rebuilds it
-  if (b >= nb) return;
-  T s = T(0);
-  for (int j = 1; j < nl; ++j) {
-    const int64_t at = (int64_t)j * nb + b;
-    s += wn[at] * p[sn[at]];
-  }
-  p[n_int + b] = -s / wn[b];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void acm_velocity(int64_t n, int64_t n_int, int nl,
-                                                       const int32_t* __restrict__ sten, const T* __restrict__ w,
-                                                       const T* __restrict__ vp, const T* __restrict__ p,
-                                                       T* __restrict__ v, T dt_rho,
-                                                       unsigned long long* __restrict__ vmax_bits) {
-  __shared__ double red[kBlock / kWave];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double mag = 0.0;
-  if (i < n_int) {
-    const int64_t os = (int64_t)nl * n;
-    T gp[3] = {T(0), T(0), T(0)};
-    for (int j = 0; j < nl; ++j) {
-      const int64_t at = (int64_t)j * n + i;
-      const T ps = p[sten[at]];
-      gp[0] += w[at] * ps;
-      gp[1] += w[os + at] * ps;
-      gp[2] += w[2 * os + at] * ps;
-    }
-    double m2 = 0.0;
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int o = 0; o < 4; ++o) d[a][o] = group_sum<LPN>(d[a][o]);
+  if (sl == 0) {
+    const T vi[3] = {F.v[i], F.v[n + i], F.v[2 * n + i]};
+    const T g[3] = {F.g0, F.g1, F.g2};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T va = vp[a * n + i] - dt_rho * gp[a];
-      v[a * n + i] = va;
-      m2 += (double)va * (double)va;
+      const T adv = vi[0] * d[a][0] + vi[1] * d[a][1] + vi[2] * d[a][2];
+      F.vp[a * n + i] = vi[a] + F.dt * (F.nu * d[a][3] - adv + g[a]);
     }
-    mag = sqrt(m2);
   }
-  // block max; the max is exact, so any reduction order gives the same value
+}
+
+template <typename T, int LPN>
+__device__ __forceinline__ void pressure_node(const Fields<T>& F, const T* __restrict__ vsrc, T coef, int64_t i,
+                                              int sl) {
+  const int64_t n = F.n, os = (int64_t)F.nl * n;
+  T div = T(0);
+  for (int j = sl; j < F.nl; j += LPN) {
+    const int64_t at = (int64_t)j * n + i;
+    const int s = F.sten[at];
+    div += F.w[at] * vsrc[s] + F.w[os + at] * vsrc[n + s] + F.w[2 * os + at] * vsrc[2 * n + s];
+  }
+  div = group_sum<LPN>(div);
+  if (sl == 0) F.p[i] -= coef * div;
+}
+
+template <typename T, int LPN>
+__device__ __forceinline__ void neumann_node(const Fields<T>& F, int64_t b, int sl) {
+  T s = T(0);
+  for (int j = 1 + sl; j < F.nl; j += LPN) {
+    const int64_t at = (int64_t)j * F.nb + b;
+    s += F.wn[at] * F.p[F.sn[at]];
+  }
+  s = group_sum<LPN>(s);
+  if (sl == 0) F.p[F.n_int + b] = -s / F.wn[b];
+}
+
+// returns |v_i| (valid in every lane of the node's group)
+template <typename T, int LPN>
+__device__ __forceinline__ double velocity_node(const Fields<T>& F, int64_t i, int sl) {
+  const int64_t n = F.n, os = (int64_t)F.nl * n;
+  T gp[3] = {T(0), T(0), T(0)};
+  for (int j = sl; j < F.nl; j += LPN) {
+    const int64_t at = (int64_t)j * n + i;
+    const T ps = F.p[F.sten[at]];
+    gp[0] += F.w[at] * ps;
+    gp[1] += F.w[os + at] * ps;
+    gp[2] += F.w[2 * os + at] * ps;
+  }
+  double m2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gp[a] = group_sum<LPN>(gp[a]);
+    const T va = F.vp[a * n + i] - F.dt_rho * gp[a];
+    if (sl == 0) F.v[a * n + i] = va;
+    m2 += (double)va * (double)va;
+  }
+  return sqrt(m2);
+}
+
+template <typename T>
+__device__ __forceinline__ T coupling_coef(const Fields<T>& F) {
+  const double vm = *F.vmax;
+  const double C = F.beta * (vm > F.v_ref ? vm : F.v_ref);
+  return (T)(F.dtd * (C * C) * F.rho);
+}
+
+// Block max of |v| into the running max (exact, so any order gives the same).
+__device__ __forceinline__ void block_max_into(double mag, double* lds, double* vmax) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mag = fmax(mag, __shfl_xor(mag, off));
-  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mag;
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x / kWave] = mag;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double m = red[0];
-    for (int t = 1; t < kBlock / kWave; ++t) m = fmax(m, red[t]);
+    double m = lds[0];
+    for (int t = 1; t < (int)(blockDim.x / kWave); ++t) m = fmax(m, lds[t]);
     if (m != m) m = __builtin_inf();  // a non-finite state shows up as C = inf
-    atomicMax(vmax_bits, (unsigned long long)__double_as_longlong(m));
+    atomicMax(reinterpret_cast<unsigned long long*>(vmax), (unsigned long long)__double_as_longlong(m));
   }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- one launch per pass
+
+template <typename T, int LPN>
+__global__ __launch_bounds__(kBlock) void k_predictor(Fields<T> F) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = g / LPN;
+  if (i >= F.n_int) return;  // whole LPN groups exit together
+  predictor_node<T, LPN>(F, i, (int)(g % LPN));
+}
+
+template <typename T, int LPN>
+__global__ __launch_bounds__(kBlock) void k_pressure(Fields<T> F, const T* __restrict__ vsrc) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = g / LPN;
+  if (i >= F.n_int) return;
+  pressure_node<T, LPN>(F, vsrc, coupling_coef(F), i, (int)(g % LPN));
+}
+
+template <typename T, int LPN>
+__global__ __launch_bounds__(kBlock) void k_neumann(Fields<T> F) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g == 0) *F.vmax = 0.0;  // the pressure pass has consumed it; the velocity pass rebuilds it
+  const int64_t b = g / LPN;
+  if (b >= F.nb) return;
+  neumann_node<T, LPN>(F, b, (int)(g % LPN));
+}
+
+template <typename T, int LPN>
+__global__ __launch_bounds__(kBlock) void k_velocity(Fields<T> F) {
+  __shared__ double red[kBlock / kWave];
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = g / LPN;
+  double mag = 0.0;
+  if (i < F.n_int) mag = velocity_node<T, LPN>(F, i, (int)(g % LPN));
+  block_max_into(mag, red, F.vmax);
 }
 
 template <typename T>
@@ -139,30 +198,49 @@ __global__ void fill_zero(T* __restrict__ x, int64_t n) {
   if (i < n) x[i] = T(0);
 }
 
-template <typename T>
-int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const T* w,
-        const int32_t* sn, const T* wn, T* v, T* p, double* vmax, int n_steps, void* ws, hipStream_t st) {
-  const int64_t nb = n - n_int;
-  T* vp = reinterpret_cast<T*>(ws);
-  const unsigned gi = grid_for(n_int, kBlock), gb = grid_for(nb, kBlock);
-  // v' is zero on the boundary for the whole run
-  for (int a = 0; a < 3; ++a) {
-    if (nb > 0) hipLaunchKernelGGL(fill_zero<T>, dim3(gb), dim3(kBlock), 0, st, vp + a * n + n_int, nb);
-  }
-  const T nu = (T)prm->nu, dt = (T)prm->dt, dt_rho = (T)(prm->dt / prm->rho);
+// below this many interior nodes a pass cannot fill the chip and is bound by
+// the chain of dependent gathers of one node: split each stencil 8 ways
+constexpr int64_t kFewNodes = 200000;
+
+template <typename T, int LPN>
+int run_launches(Fields<T>& F, int n_steps, int n_p, hipStream_t st) {
+  const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   for (int s = 0; s < n_steps; ++s) {
-    hipLaunchKernelGGL(acm_predictor<T>, dim3(gi), dim3(kBlock), 0, st, n, n_int, nl, sten, w, v, vp, nu, dt,
-                       (T)prm->g[0], (T)prm->g[1], (T)prm->g[2]);
-    for (int it = 0; it < prm->n_p; ++it) {
-      hipLaunchKernelGGL(acm_pressure<T>, dim3(gi), dim3(kBlock), 0, st, n, n_int, nl, sten, w,
-                         (const T*)(it == 0 ? vp : v), p, vmax, prm->dt, prm->rho, prm->beta, prm->v_ref);
-      hipLaunchKernelGGL(acm_neumann<T>, dim3(gb), dim3(kBlock), 0, st, n_int, nb, nl, sn, wn, p, vmax);
-      hipLaunchKernelGGL(acm_velocity<T>, dim3(gi), dim3(kBlock), 0, st, n, n_int, nl, sten, w, (const T*)vp,
-                         (const T*)p, v, dt_rho, reinterpret_cast<unsigned long long*>(vmax));
+    hipLaunchKernelGGL((k_predictor<T, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
+    for (int it = 0; it < n_p; ++it) {
+      hipLaunchKernelGGL((k_pressure<T, LPN>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.vp : F.v));
+      hipLaunchKernelGGL((k_neumann<T, LPN>), dim3(gb), dim3(kBlock), 0, st, F);
+      hipLaunchKernelGGL((k_velocity<T, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
     }
   }
   MPF_LAUNCH_CHECK();
   return MPF_OK;
+}
+
+template <typename T>
+int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const T* w,
+        const int32_t* sn, const T* wn, T* v, T* p, double* vmax, int n_steps, void* ws, hipStream_t st) {
+  Fields<T> F;
+  F.n = n; F.n_int = n_int; F.nb = n - n_int; F.nl = nl;
+  F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.v = v; F.p = p;
+  F.vp = reinterpret_cast<T*>(ws);
+  F.vmax = vmax;
+  F.nu = (T)prm->nu; F.dt = (T)prm->dt; F.dt_rho = (T)(prm->dt / prm->rho);
+  F.g0 = (T)prm->g[0]; F.g1 = (T)prm->g[1]; F.g2 = (T)prm->g[2];
+  F.dtd = prm->dt; F.rho = prm->rho; F.beta = prm->beta; F.v_ref = prm->v_ref;
+  // v' is zero on the boundary for the whole run
+  if (F.nb > 0)
+    for (int a = 0; a < 3; ++a)
+      hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(F.nb, kBlock)), dim3(kBlock), 0, st, F.vp + a * n + n_int, F.nb);
+  int lanes = prm->lanes;
+  if (lanes == 0) lanes = n_int <= kFewNodes ? 8 : 2;
+  switch (lanes) {
+    case 1: return run_launches<T, 1>(F, n_steps, prm->n_p, st);
+    case 2: return run_launches<T, 2>(F, n_steps, prm->n_p, st);
+    case 4: return run_launches<T, 4>(F, n_steps, prm->n_p, st);
+    case 8: return run_launches<T, 8>(F, n_steps, prm->n_p, st);
+    default: return run_launches<T, 16>(F, n_steps, prm->n_p, st);
+  }
 }
 
 }  // namespace
@@ -182,6 +260,9 @@ extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, 
     return MPF_ERR_ARG;
   if (n > n_int && (!sn || !wn)) return MPF_ERR_ARG;
   if (prm->precision != MPF_F64 && prm->precision != MPF_F32) return MPF_ERR_ARG;
+  if (prm->lanes != 0 && prm->lanes != 1 && prm->lanes != 2 && prm->lanes != 4 && prm->lanes != 8 &&
+      prm->lanes != 16)
+    return MPF_ERR_ARG;
   if (!ws || ws_bytes < mpf_acm_workspace(n, prm->precision)) return MPF_ERR_WORKSPACE;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);

@@ -104,10 +104,10 @@ def test_weights_argument_errors(api, small_cloud):
 
 # ----------------------------------------------------------------- ACM
 
-def acm_pair(api, disc, precision, steps, v_ref=1e-3):
+def acm_pair(api, disc, precision, steps, v_ref=1e-3, lanes=0):
     from paper_2404_14195_amd.solvers import ACMSolver
     c = disc.cloud
-    g = ACMSolver(disc, precision=precision, v_ref=v_ref)
+    g = ACMSolver(disc, precision=precision, v_ref=v_ref, lanes=lanes)
     o = O.ACM(c.pos, c.n_int, disc.sten_host, c.nrm, sten_n=nc.neumann_stencils(c, 30), h_min=c.h_min,
               v_ref=v_ref)
     g.run(steps)
@@ -115,10 +115,12 @@ def acm_pair(api, disc, precision, steps, v_ref=1e-3):
     return g, o
 
 
-def test_acm_parity_fp64_500_steps(api, disc_small):
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4, 16])
+def test_acm_parity_fp64_500_steps(api, disc_small, lanes):
     """The plain-ACM workload: 500 explicit steps, FP64, GPU weights vs
-    oracle weights end to end: fields and permeability within 1e-10."""
-    g, o = acm_pair(api, disc_small, 0, 500)
+    oracle weights end to end: fields and permeability within 1e-10, for every
+    split of the stencil sums over lanes (0 = automatic)."""
+    g, o = acm_pair(api, disc_small, 0, 500, lanes=lanes)
     v = g.v.cpu().numpy().T
     p = g.p.cpu().numpy()
     assert np.abs(v - o.v).max() <= 1e-10 * np.abs(o.v).max()

@@ -57,6 +57,10 @@ def test_host_argument_checks(lib):
     prm = AcmParams(nu=1, rho=1, dt=1e-5, beta=10, v_ref=1e-3, n_p=3, precision=0)
     assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 0,
                            None) == -4  # workspace too small
+    prm.lanes = 3
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 1 << 20,
+                           None) == -1
+    prm.lanes = 0
     prm.n_p = 0
     assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 1 << 20,
                            None) == -1
