@@ -96,8 +96,10 @@ int mpf_sc_cell(double r, double* porosity_host, double* area_host);
  * w32      dev [n_ops][nl][m] float, or NULL: the FP32 copy; its self weight
  *          (column 0) is replaced so that the row sums, computed in FP64, equal
  *          the exact ones (1 for the two shift kinds, 0 for derivatives)
- * info     dev [m] int32: 0, or 1 + the column of a zero pivot (weights of
- *          that row are then NaN)
+ * info     dev [m] int32: 0; 1 + the column of a zero pivot (weights of that
+ *          row are then NaN); -1 if FP32 refinement did not settle and the
+ *          row was re-solved in FP64 (batched call with MPF_SOLVE_FP32_IR)
+ * ws       workspace of mpf_weights_workspace() bytes (holds the row table)
  * nl must be one of 20, 25, 27, 30, 35, 40, 45, 50 (MPF_ERR_UNSUPPORTED
  * otherwise).  At least one of w64 / w32 must be given. */
 #define MPF_OP_DX 0
@@ -115,9 +117,54 @@ typedef struct {
   double vec[3];
 } mpf_op;
 
+size_t mpf_weights_workspace(void);
 int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_t m, int nl, int n_ops,
-                      const mpf_op* ops, const double* rowvec, double* w64, float* w32, int32_t* info,
-                      void* stream);
+                      const mpf_op* ops, const double* rowvec, double* w64, float* w32, int32_t* info, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Batched weights: every row of up to 16 node clouds (same nl and operators)
+ * in one launch over their concatenated rows; each wave solves rows_per_wave
+ * consecutive rows, so clouds of very different sizes share the chip.  Each
+ * cloud is described by an mpf_wgeom with the same
+ * meaning as the arguments of mpf_rbffd_weights (rowvec per cloud when an
+ * operator needs it).
+ * solve: MPF_SOLVE_FP64 (direct), or MPF_SOLVE_FP32_IR: FP32 factors with
+ *        FP64-residual iterative refinement (at most three sweeps, stop at
+ *        |dx| <= 1e-15 |x|; otherwise the row is re-solved in FP64, info -1).
+ * tune:  host pointer to the tile shape, or NULL for the shape that
+ *        mpf_weights_autotune last chose for (device, nl, n_ops, solve), or a
+ *        default (4 waves per block, 1 row per wave).
+ * The geometry table is copied into ws with hipMemcpyAsync on the stream. */
+#define MPF_SOLVE_FP64 0
+#define MPF_SOLVE_FP32_IR 1
+
+typedef struct {
+  const double* pos; /* dev [3][n_nodes] */
+  int64_t n_nodes;
+  const int32_t* sten; /* dev [nl][m] */
+  int64_t m;
+  const double* rowvec; /* dev [3][m] or NULL */
+  double* w64;          /* dev [n_ops][nl][m] or NULL */
+  float* w32;           /* dev [n_ops][nl][m] or NULL */
+  int32_t* info;        /* dev [m] */
+} mpf_wgeom;
+
+typedef struct {
+  int32_t waves_per_block; /* 1..8 */
+  int32_t rows_per_wave;   /* 1..64 */
+} mpf_wtune;
+
+int mpf_rbffd_weights_batched(int n_geoms, const mpf_wgeom* geoms_host, int nl, int n_ops, const mpf_op* ops,
+                              int solve, const mpf_wtune* tune, void* ws, size_t ws_bytes, void* stream);
+
+/* Autotuner: times every candidate tile shape (waves per block 1, 2, 4, 8 x
+ * rows per wave 1, 2, 4, 8) on the first sample_rows rows of *sample (whose
+ * outputs it overwrites), on a
+ * private stream, synchronously; stores the fastest in *out and in the
+ * library's per-process cache used when mpf_rbffd_weights_batched gets
+ * tune = NULL. */
+int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
+                         int64_t sample_rows, mpf_wtune* out, void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------- ACM step
  * Explicit artificial-compressibility Navier-Stokes steps (Sec. 2.3, Eqs.

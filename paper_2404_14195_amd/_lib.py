@@ -15,6 +15,7 @@ SO_PATH = os.path.join(_HERE, "libmpf.so")
 SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip"]
 
 MPF_F64, MPF_F32 = 0, 1
+SOLVE_FP64, SOLVE_FP32_IR = 0, 1
 OP = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shift_row": 7}
 
 
@@ -22,23 +23,43 @@ class MPFError(RuntimeError):
     pass
 
 
-def hipcc_command(out: str):
-    src = [os.path.join(_HERE, "csrc", s) for s in SOURCES]
-    return ["/opt/rocm/bin/hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I" + _INC, "-I" + os.path.join(_HERE, "csrc")] + src + ["-o", out]
+HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def build() -> str:
-    """Compile libmpf.so for gfx950 in-tree (hipcc cross-compiles without a GPU)."""
-    tmp = SO_PATH + ".tmp"
-    subprocess.check_call(hipcc_command(tmp))
-    os.replace(tmp, SO_PATH)
+    """Compile libmpf.so for gfx950 in-tree (hipcc cross-compiles without a
+    GPU): each source to an object in parallel, then one link."""
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmpd:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpd, src + ".o")
+            cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-I" + _INC, "-I" + os.path.join(_HERE, "csrc"), "-c",
+                   os.path.join(_HERE, "csrc", src), "-o", obj]
+            procs.append((src, subprocess.Popen(cmd)))
+            objs.append(obj)
+        for src, p in procs:
+            if p.wait() != 0:
+                raise RuntimeError(f"hipcc failed on {src}")
+        tmp = SO_PATH + ".tmp"
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-shared", *objs, "-o", tmp])
+        os.replace(tmp, SO_PATH)
     return SO_PATH
 
 
 class _Op(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("vec", ctypes.c_double * 3)]
+
+
+class WGeom(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("n_nodes", ctypes.c_int64), ("sten", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("rowvec", ctypes.c_void_p), ("w64", ctypes.c_void_p),
+                ("w32", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
+class WTune(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32)]
 
 
 class AcmParams(ctypes.Structure):
@@ -62,7 +83,10 @@ def _load():
         "mpf_strerror": (ctypes.c_char_p, [i32]),
         "mpf_version": (i32, []),
         "mpf_sc_cell": (i32, [dbl, vp, vp]),
-        "mpf_rbffd_weights": (i32, [vp, i64, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "mpf_weights_workspace": (sz, []),
+        "mpf_rbffd_weights": (i32, [vp, i64, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mpf_rbffd_weights_batched": (i32, [i32, vp, i32, i32, vp, i32, vp, vp, sz, vp]),
+        "mpf_weights_autotune": (i32, [i32, i32, vp, i32, vp, i64, vp, vp, sz]),
         "mpf_acm_workspace": (sz, [i64, i32]),
         "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
         "mpf_lbm_init": (i32, [vp, i64, dbl, vp, vp, vp]),
@@ -90,7 +114,8 @@ def lib():
     return _LIB
 
 
-EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_rbffd_weights", "mpf_acm_workspace", "mpf_acm_run",
+EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
+            "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",
             "mpf_lbm_init", "mpf_lbm_run", "mpf_lbm_moments", "mpf_reduce_workspace", "mpf_flux_planes", "mpf_drag"]
 
 

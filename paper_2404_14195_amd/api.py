@@ -8,7 +8,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import MPF_F32, MPF_F64, AcmParams, LbmParams, check, lib, make_ops
+from ._lib import MPF_F32, MPF_F64, AcmParams, LbmParams, WGeom, WTune, check, lib, make_ops
 
 _DT = {MPF_F64: torch.float64, MPF_F32: torch.float32}
 
@@ -67,9 +67,61 @@ def rbffd_weights(pos, sten, ops, rowvec=None, want64=True, want32=False):
     if rowvec is not None:
         _need(rowvec, torch.float64, (3, m), "rowvec")
     arr = make_ops(ops)
+    ws = weights_workspace(dev)
     check(lib().mpf_rbffd_weights(_p(pos), pos.shape[1], _p(sten), m, nl, len(ops), arr, _p(rowvec), _p(w64), _p(w32),
-                                _p(info), _stream()), "mpf_rbffd_weights")
+                                  _p(info), _p(ws), ws.numel(), _stream()), "mpf_rbffd_weights")
     return w64, w32, info
+
+
+def weights_workspace(device) -> torch.Tensor:
+    return torch.empty(lib().mpf_weights_workspace(), dtype=torch.uint8, device=device)
+
+
+def _wgeom(pos, sten, rowvec, w64, w32, info):
+    return WGeom(pos=_p(pos), n_nodes=pos.shape[1], sten=_p(sten), m=sten.shape[1], rowvec=_p(rowvec), w64=_p(w64),
+                 w32=_p(w32), info=_p(info))
+
+
+def rbffd_weights_batched(clouds, ops, solve=0, want64=True, want32=False, tune=None):
+    """clouds: list of (pos [3][n], sten [nl][m], rowvec or None).  One launch
+    over all rows.  Returns [(w64, w32, info)] per cloud."""
+    nl = clouds[0][1].shape[0]
+    out, geoms = [], (WGeom * len(clouds))()
+    for g, (pos, sten, rowvec) in enumerate(clouds):
+        _need(pos, torch.float64, name="pos")
+        _need(sten, torch.int32, name="sten")
+        if sten.shape[0] != nl:
+            raise ValueError("all clouds must share the stencil size")
+        m = sten.shape[1]
+        w64 = torch.empty((len(ops), nl, m), dtype=torch.float64, device=pos.device) if want64 else None
+        w32 = torch.empty((len(ops), nl, m), dtype=torch.float32, device=pos.device) if want32 else None
+        info = torch.empty(m, dtype=torch.int32, device=pos.device)
+        geoms[g] = _wgeom(pos, sten, rowvec, w64, w32, info)
+        out.append((w64, w32, info))
+    ws = weights_workspace(clouds[0][0].device)
+    t = None
+    if tune is not None:
+        t = WTune(waves_per_block=tune[0], rows_per_wave=tune[1])
+    check(lib().mpf_rbffd_weights_batched(len(clouds), geoms, nl, len(ops), make_ops(ops), int(solve),
+                                          None if t is None else ctypes.byref(t), _p(ws), ws.numel(), _stream()),
+          "mpf_rbffd_weights_batched")
+    return out
+
+
+def weights_autotune(pos, sten, ops, solve=0, sample_rows=16384, rowvec=None):
+    """Time the candidate tile shapes on the first sample_rows rows; returns
+    (waves_per_block, rows_per_wave) and caches it in the library."""
+    nl, m = sten.shape
+    k = min(m, sample_rows)
+    w64 = torch.empty((len(ops), nl, m), dtype=torch.float64, device=pos.device)
+    info = torch.empty(m, dtype=torch.int32, device=pos.device)
+    g = _wgeom(pos, sten, rowvec, w64, None, info)
+    ws = weights_workspace(pos.device)
+    t = WTune()
+    torch.cuda.synchronize()
+    check(lib().mpf_weights_autotune(nl, len(ops), make_ops(ops), int(solve), ctypes.byref(g), k, ctypes.byref(t),
+                                     _p(ws), ws.numel()), "mpf_weights_autotune")
+    return t.waves_per_block, t.rows_per_wave
 
 
 def acm_workspace(n: int, precision: int, device) -> torch.Tensor:

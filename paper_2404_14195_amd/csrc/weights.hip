@@ -1,23 +1,41 @@
 // Batched RBF-FD weight solves (Sec. 2.1, Eqs. operatorApprox, rbfScaling,
 // augmentedSystem) on gfx950.
 //
-// One wave64 owns one stencil row.  Lane j holds row j of the augmented
-// matrix M = [A P; P^T 0] (size N = NL + 10 <= 60) in registers; the first NL
-// lanes also own the output weights w_j.  Gaussian elimination with partial
-// pivoting keeps rows in place: at column c the pivot is the unused lane with
-// the largest |M[.][c]| (wave butterfly, ties to the lowest lane), the pivot
-// row is broadcast with readlane and every still-active lane subtracts its
-// multiple, keeping the multiplier in column c.  The right-hand sides are then
-// processed in chunks of RB with forward and backward substitution over the
-// stored factors, so the O(N^3) factorisation is done once per row whatever
-// the number of operators.  Everything is FP64 on the vector ALU: a 40 x 40
-// pivoted LU is not a dense contraction that MFMA tiles would serve.
+// One wave64 owns one stencil row at a time.  Lane j holds row j of the
+// augmented matrix M = [A P; P^T 0] (size N = NL + 10 <= 60) in registers;
+// the first NL lanes also own the output weights w_j.  Gaussian elimination
+// with partial pivoting keeps rows in place: at column c the pivot is the
+// unused lane with the largest |M[.][c]| (wave butterfly, ties to the lowest
+// lane), the pivot row is broadcast with readlane and every still-active lane
+// subtracts its multiple, keeping the multiplier in column c.  Right-hand
+// sides then go through forward and backward substitution over the stored
+// factors in chunks of RB, so the O(N^3) factorisation is done once per row
+// whatever the number of operators.  Everything runs on the vector ALU: a
+// pivoted 40 x 40 LU per row is not a dense contraction MFMA tiles would
+// serve.
+//
+// Launch: one grid over the concatenated rows of up to kMaxGeoms node clouds
+// (a row-to-cloud table in the workspace), each wave solving `rows_per_wave`
+// consecutive rows, so clouds of any sizes share one launch.  The block shape
+// (waves per block, rows per wave) comes from the autotuner.
+//
+// Precision: FP64 direct, or FP32 factors with FP64-residual iterative
+// refinement (x += LU32^-1 (b - M x) with M and the residual in FP64, up to
+// three sweeps).  A row whose refinement has not reached
+// |dx| <= 1e-15 |x| is re-solved in FP64 and flagged with info < 0.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "common.hpp"
 
 namespace mpf {
 namespace {
 
 constexpr int kMaxOps = 32;
+constexpr int kMaxGeoms = 16;
 constexpr int RB = 4;
 
 struct OpsArg {
@@ -25,6 +43,28 @@ struct OpsArg {
   int kind[kMaxOps];
   double vec[kMaxOps][3];
 };
+
+struct GeomArg {
+  const double* pos;
+  int64_t n_nodes;
+  const int32_t* sten;
+  int64_t m;
+  const double* rowvec;
+  double* w64;
+  float* w32;
+  int32_t* info;
+  int64_t row0;  // first global row of this cloud
+};
+
+struct BatchArg {
+  int n_geoms;
+  int64_t total;
+  GeomArg g[kMaxGeoms];
+};
+
+// workspace layout: 256 bytes reserved, then the geometry table
+constexpr size_t kTableOffset = 256;
+constexpr size_t kWorkspaceBytes = kTableOffset + sizeof(GeomArg) * kMaxGeoms;
 
 __device__ __forceinline__ double mono(int l, double x, double y, double z) {
   switch (l) {
@@ -47,7 +87,7 @@ __device__ __forceinline__ double cube_dist(double ax, double ay, double az, dou
   return r * r * r;
 }
 
-// Right-hand-side entry of row j (lane) for operator o.
+// Right-hand-side entry of row j (lane) for one operator.
 template <int NL>
 __device__ __forceinline__ double rhs_entry(int kind, const double* vec, const double* rv, int j, double xi0,
                                             double xi1, double xi2, double rho, double delta) {
@@ -58,7 +98,7 @@ __device__ __forceinline__ double rhs_entry(int kind, const double* vec, const d
     if (j < NL) return cube_dist(s0, s1, s2, xi0, xi1, xi2);
     return mono(j - NL, s0, s1, s2);
   }
-  if (kind == MPF_OP_LAP) {
+  if (kind == MPF_OP_LAP) {  // lap r^3 = 3 (3 + 3 - 2) r = 12 r; lap of x^2, y^2, z^2 = 2
     if (j < NL) return 12.0 * rho * id * id;
     int l = j - NL;
     return (l == 4 || l == 7 || l == 9) ? 2.0 * id * id : 0.0;
@@ -76,16 +116,18 @@ __device__ __forceinline__ double rhs_entry(int kind, const double* vec, const d
   return l == 1 ? e0 * id : (l == 2 ? e1 * id : (l == 3 ? e2 * id : 0.0));
 }
 
+__device__ __forceinline__ float bcastf(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
 template <int NL>
-__global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__ pos, int64_t n_nodes,
-                                                      const int32_t* __restrict__ sten, int64_t m, OpsArg ops,
-                                                      const double* __restrict__ rowvec, double* __restrict__ w64,
-                                                      float* __restrict__ w32, int32_t* __restrict__ info) {
+__device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, int64_t n_nodes,
+                                               const int32_t* __restrict__ sten, int64_t m, int64_t row,
+                                               const OpsArg& ops, const double* __restrict__ rowvec,
+                                               double* __restrict__ w64, float* __restrict__ w32,
+                                               int32_t* __restrict__ info, int lane) {
   constexpr int N = NL + 10;
   static_assert(N <= kWave, "system does not fit one wave");
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (row >= m) return;  // whole wave exits together
 
   // --- scaled local coordinates xi_j = minimg(x_j - x_c) / delta, with
   // delta the distance from the centre to stencil column 1
@@ -204,46 +246,375 @@ __global__ __launch_bounds__(256) void weights_kernel(const double* __restrict__
   if (lane == 0) info[row] = bad;
 }
 
+
+// FP32 factors with FP64-residual refinement for one stencil row (same lane
+// layout as the FP64 solve).  Returns false if some chunk of right-hand sides
+// has not settled after three sweeps (or the FP32 factorisation met a zero
+// pivot); the caller then re-solves the row in FP64.
 template <int NL>
-int launch_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_t m, const OpsArg& ops,
-                   const double* rowvec, double* w64, float* w32, int32_t* info, hipStream_t st) {
-  const int block = 256;
-  const int per = block / kWave;
-  hipLaunchKernelGGL(weights_kernel<NL>, dim3(grid_for(m, per)), dim3(block), 0, st, pos, n_nodes, sten, m, ops,
-                     rowvec, w64, w32, info);
+__device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int64_t n_nodes,
+                                             const int32_t* __restrict__ sten, int64_t m, int64_t row,
+                                             const OpsArg& ops, const double* __restrict__ rowvec,
+                                             double* __restrict__ w64, float* __restrict__ w32,
+                                             int32_t* __restrict__ info, int lane) {
+  constexpr int N = NL + 10;
+  double xi0, xi1, xi2, delta;
+  {
+    const int sj = sten[(int64_t)(lane < NL ? lane : 0) * m + row];
+    const int sc = sten[row];
+    double d0 = min_image(pos[sj] - pos[sc]);
+    double d1 = min_image(pos[n_nodes + sj] - pos[n_nodes + sc]);
+    double d2 = min_image(pos[2 * n_nodes + sj] - pos[2 * n_nodes + sc]);
+    const double q0 = bcast(d0, 1), q1 = bcast(d1, 1), q2 = bcast(d2, 1);
+    delta = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+    xi0 = d0 / delta; xi1 = d1 / delta; xi2 = d2 / delta;
+    if (lane >= NL) xi0 = xi1 = xi2 = 0.0;
+  }
+  const double rho = sqrt(xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
+  float a[N];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    double x0 = bcast(xi0, k), x1 = bcast(xi1, k), x2 = bcast(xi2, k);
+    a[k] = (float)(lane < NL ? cube_dist(xi0, xi1, xi2, x0, x1, x2) : (lane < N ? mono(lane - NL, x0, x1, x2) : 0.0));
+  }
+#pragma unroll
+  for (int l = 0; l < 10; ++l) a[NL + l] = (float)(lane < NL ? mono(l, xi0, xi1, xi2) : 0.0);
+  int pcol = (lane < N) ? 1 << 20 : -1;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    float cand = (pcol > c) ? fabsf(a[c]) : -1.0f;
+    int cl = lane;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      float ov = __shfl_xor(cand, off);
+      int ol = __shfl_xor(cl, off);
+      if (ov > cand || (ov == cand && ol < cl)) { cand = ov; cl = ol; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(cl);
+    if (!(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(cand), 0)) > 0.0f)) return false;
+    const float pv = bcastf(a[c], p);
+    const bool act = pcol > c && lane != p;
+    if (lane == p) pcol = c;
+    const float l = act ? a[c] / pv : 0.0f;
+    if (act) a[c] = l;
+#pragma unroll
+    for (int k = c + 1; k < N; ++k) {
+      const float pk = bcastf(a[k], p);
+      if (act) a[k] = fmaf(-l, pk, a[k]);
+    }
+  }
+  double rvv[3] = {0.0, 0.0, 0.0};
+  if (rowvec) { rvv[0] = rowvec[row]; rvv[1] = rowvec[m + row]; rvv[2] = rowvec[2 * m + row]; }
+  for (int o0 = 0; o0 < ops.n; o0 += RB) {
+    double b[RB], x[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int o = o0 + r;
+      b[r] = (o < ops.n && lane < N) ? rhs_entry<NL>(ops.kind[o], ops.vec[o], rvv, lane, xi0, xi1, xi2, rho, delta)
+                                     : 0.0;
+      x[r] = 0.0;
+    }
+    bool ok = false;
+    // sweep 0 solves M x = b; later sweeps solve M d = b - M x (FP64 residual)
+    for (int sweep = 0; sweep < 4 && !ok; ++sweep) {
+      float rf[RB];
+      if (sweep == 0) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) rf[r] = (float)b[r];
+      } else {
+        double s[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) s[r] = b[r];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          double mk;
+          if (k < NL) {
+            double x0 = bcast(xi0, k), x1 = bcast(xi1, k), x2 = bcast(xi2, k);
+            mk = lane < NL ? cube_dist(xi0, xi1, xi2, x0, x1, x2) : (lane < N ? mono(lane - NL, x0, x1, x2) : 0.0);
+          } else {
+            mk = lane < NL ? mono(k - NL, xi0, xi1, xi2) : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < RB; ++r) s[r] = fma(-mk, bcast(x[r], k), s[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) rf[r] = (float)(lane < N ? s[r] : 0.0);
+      }
+      // forward and back substitution with the FP32 factors
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(pcol == c)));
+        const bool act = pcol > c;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const float y = bcastf(rf[r], p);
+          if (act) rf[r] = fmaf(-a[c], y, rf[r]);
+        }
+      }
+      float d[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) d[r] = 0.0f;
+#pragma unroll
+      for (int c = N - 1; c >= 0; --c) {
+        const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(pcol == c)));
+        const bool act = pcol < c;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const float xc = bcastf(rf[r] / a[c], p);
+          if (lane == c) d[r] = xc;
+          if (act) rf[r] = fmaf(-a[c], xc, rf[r]);
+        }
+      }
+      double dmax = 0.0, xmax = 0.0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        x[r] += (double)d[r];
+        if (lane < N && o0 + r < ops.n) {
+          dmax = fmax(dmax, fabs((double)d[r]));
+          xmax = fmax(xmax, fabs(x[r]));
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, off));
+        xmax = fmax(xmax, __shfl_xor(xmax, off));
+      }
+      ok = sweep > 0 && dmax <= 1e-15 * xmax;
+    }
+    if (!ok) return false;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int o = o0 + r;
+      if (o >= ops.n) break;
+      if (w64 && lane < NL) w64[((int64_t)o * NL + lane) * m + row] = x[r];
+      if (w32) {
+        float xf = (float)x[r];
+        double part = (lane >= 1 && lane < NL) ? (double)xf : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        const int kd = ops.kind[o];
+        const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW) ? 1.0 : 0.0;
+        if (lane == 0) xf = (float)(target - part);
+        if (lane < NL) w32[((int64_t)o * NL + lane) * m + row] = xf;
+      }
+    }
+  }
+  if (lane == 0) info[row] = 0;
+  return true;
+}
+
+template <int NL, bool IR>
+__global__ __launch_bounds__(512) void weights_batched(const GeomArg* __restrict__ table, int n_geoms, int64_t total,
+                                                       OpsArg ops, int rows_per_wave) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int64_t base = wave * rows_per_wave;
+  const int64_t end = base + rows_per_wave < total ? base + rows_per_wave : total;
+  for (int64_t r = base; r < end; ++r) {
+    int g = 0;
+    while (g + 1 < n_geoms && r >= table[g + 1].row0) ++g;
+    const GeomArg G = table[g];
+    const int64_t row = r - G.row0;
+    bool done = false;
+    if (IR) done = solve_row_ir<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
+    if (!done) {
+      solve_row_fp64<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
+      if (IR && lane == 0 && G.info[row] == 0) G.info[row] = -1;
+    }
+  }
+}
+
+struct Tune {
+  int waves, rows;  // waves per block, consecutive rows per wave
+};
+
+template <int NL, bool IR>
+int launch(const BatchArg& B, const OpsArg& ops, const Tune& t, const void* ws, hipStream_t st) {
+  const int64_t rows_per_block = (int64_t)t.waves * t.rows;
+  const int64_t blocks = (B.total + rows_per_block - 1) / rows_per_block;
+  const GeomArg* table = reinterpret_cast<const GeomArg*>(reinterpret_cast<const char*>(ws) + kTableOffset);
+  hipLaunchKernelGGL((weights_batched<NL, IR>), dim3((unsigned)blocks), dim3(t.waves * kWave), 0, st, table, B.n_geoms,
+                     B.total, ops, t.rows);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
 
-}  // namespace
-}  // namespace mpf
+template <bool IR>
+int dispatch(int nl, const BatchArg& B, const OpsArg& ops, const Tune& t, const void* ws, hipStream_t st) {
+  switch (nl) {
+    case 20: return launch<20, IR>(B, ops, t, ws, st);
+    case 25: return launch<25, IR>(B, ops, t, ws, st);
+    case 27: return launch<27, IR>(B, ops, t, ws, st);
+    case 30: return launch<30, IR>(B, ops, t, ws, st);
+    case 35: return launch<35, IR>(B, ops, t, ws, st);
+    case 40: return launch<40, IR>(B, ops, t, ws, st);
+    case 45: return launch<45, IR>(B, ops, t, ws, st);
+    case 50: return launch<50, IR>(B, ops, t, ws, st);
+    default: return MPF_ERR_UNSUPPORTED;
+  }
+}
+bool nl_supported(int nl) {
+  return nl == 20 || nl == 25 || nl == 27 || nl == 30 || nl == 35 || nl == 40 || nl == 45 || nl == 50;
+}
 
-extern "C" int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_t m, int nl,
-                                 int n_ops, const mpf_op* ops, const double* rowvec, double* w64, float* w32,
-                                 int32_t* info, void* stream) {
-  using namespace mpf;
-  if (!pos || !sten || !ops || !info || n_nodes < 2 || m < 0 || n_ops < 1 || n_ops > kMaxOps) return MPF_ERR_ARG;
-  if (!w64 && !w32) return MPF_ERR_ARG;
-  OpsArg a{};
+int make_ops(int n_ops, const mpf_op* ops, bool have_rowvec, OpsArg& a) {
+  if (!ops || n_ops < 1 || n_ops > kMaxOps) return MPF_ERR_ARG;
+  a = OpsArg{};
   a.n = n_ops;
   for (int o = 0; o < n_ops; ++o) {
     int k = ops[o].kind;
     if (k < MPF_OP_DX || k > MPF_OP_SHIFT_ROW) return MPF_ERR_ARG;
-    if ((k == MPF_OP_DN || k == MPF_OP_SHIFT_ROW) && !rowvec) return MPF_ERR_ARG;
+    if ((k == MPF_OP_DN || k == MPF_OP_SHIFT_ROW) && !have_rowvec) return MPF_ERR_ARG;
     a.kind[o] = k;
     for (int t = 0; t < 3; ++t) a.vec[o][t] = ops[o].vec[t];
   }
-  if (m == 0) return MPF_OK;
-  hipStream_t st = as_stream(stream);
-  switch (nl) {
-    case 20: return launch_weights<20>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 25: return launch_weights<25>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 27: return launch_weights<27>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 30: return launch_weights<30>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 35: return launch_weights<35>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 40: return launch_weights<40>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 45: return launch_weights<45>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    case 50: return launch_weights<50>(pos, n_nodes, sten, m, a, rowvec, w64, w32, info, st);
-    default: return MPF_ERR_UNSUPPORTED;
+  return MPF_OK;
+}
+
+int make_batch(int n_geoms, const mpf_wgeom* geoms, bool needs_rowvec, BatchArg& B) {
+  if (n_geoms < 1 || n_geoms > kMaxGeoms || !geoms) return MPF_ERR_ARG;
+  B = BatchArg{};
+  B.n_geoms = n_geoms;
+  int64_t row = 0;
+  for (int g = 0; g < n_geoms; ++g) {
+    const mpf_wgeom& s = geoms[g];
+    if (!s.pos || !s.sten || !s.info || s.n_nodes < 2 || s.m < 0 || (!s.w64 && !s.w32)) return MPF_ERR_ARG;
+    if (needs_rowvec && !s.rowvec) return MPF_ERR_ARG;
+    B.g[g] = GeomArg{s.pos, s.n_nodes, s.sten, s.m, s.rowvec, s.w64, s.w32, s.info, row};
+    row += s.m;
   }
+  B.total = row;
+  return MPF_OK;
+}
+
+bool ops_need_rowvec(int n_ops, const mpf_op* ops) {
+  for (int o = 0; o < n_ops; ++o)
+    if (ops[o].kind == MPF_OP_DN || ops[o].kind == MPF_OP_SHIFT_ROW) return true;
+  return false;
+}
+
+// autotune cache: (device, nl, n_ops, solve) -> tile shape
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, Tune> g_tune;
+
+const Tune kDefaultTune{4, 1};
+
+}  // namespace
+}  // namespace mpf
+
+using namespace mpf;
+
+extern "C" size_t mpf_weights_workspace(void) { return kWorkspaceBytes; }
+
+
+namespace {
+int upload_table(const BatchArg& B, void* ws, hipStream_t st) {
+  MPF_HIP(hipMemcpyAsync(reinterpret_cast<char*>(ws) + kTableOffset, B.g, sizeof(GeomArg) * B.n_geoms,
+                         hipMemcpyHostToDevice, st));
+  return MPF_OK;
+}
+}  // namespace
+
+extern "C" int mpf_rbffd_weights_batched(int n_geoms, const mpf_wgeom* geoms, int nl, int n_ops, const mpf_op* ops,
+                                         int solve, const mpf_wtune* tune, void* ws, size_t ws_bytes,
+                                         void* stream) {
+  if (solve != MPF_SOLVE_FP64 && solve != MPF_SOLVE_FP32_IR) return MPF_ERR_ARG;
+  if (!ops || n_ops < 1 || n_ops > kMaxOps) return MPF_ERR_ARG;
+  const bool rv = ops_need_rowvec(n_ops, ops);
+  OpsArg a;
+  int rc = make_ops(n_ops, ops, true, a);
+  if (rc) return rc;
+  BatchArg B;
+  rc = make_batch(n_geoms, geoms, rv, B);
+  if (rc) return rc;
+  if (!nl_supported(nl)) return MPF_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < mpf_weights_workspace()) return MPF_ERR_WORKSPACE;
+  if (B.total == 0) return MPF_OK;
+  Tune t = kDefaultTune;
+  if (tune) {
+    if (tune->waves_per_block < 1 || tune->waves_per_block > 8 || tune->rows_per_wave < 1 || tune->rows_per_wave > 64)
+      return MPF_ERR_ARG;
+    t = Tune{tune->waves_per_block, tune->rows_per_wave};
+  } else {
+    int dev = 0;
+    MPF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(dev, nl, n_ops, solve));
+    if (it != g_tune.end()) t = it->second;
+  }
+  hipStream_t st = as_stream(stream);
+  rc = upload_table(B, ws, st);
+  if (rc) return rc;
+  return solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
+}
+
+extern "C" int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
+                                    int64_t sample_rows, mpf_wtune* out, void* ws, size_t ws_bytes) {
+  if (!sample || !out || sample_rows < 1) return MPF_ERR_ARG;
+  if (solve != MPF_SOLVE_FP64 && solve != MPF_SOLVE_FP32_IR) return MPF_ERR_ARG;
+  if (!nl_supported(nl)) return MPF_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < mpf_weights_workspace()) return MPF_ERR_WORKSPACE;
+  OpsArg a;
+  int rc = make_ops(n_ops, ops, sample->rowvec != nullptr, a);
+  if (rc) return rc;
+  mpf_wgeom g = *sample;
+  g.m = std::min<int64_t>(g.m, sample_rows);
+  BatchArg B;
+  rc = make_batch(1, &g, ops_need_rowvec(n_ops, ops), B);
+  if (rc) return rc;
+  hipStream_t st = nullptr;
+  MPF_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  rc = upload_table(B, ws, st);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  MPF_HIP(hipEventCreate(&e0));
+  MPF_HIP(hipEventCreate(&e1));
+  Tune best = kDefaultTune;
+  float best_ms = 1e30f;
+  const int waves[] = {1, 2, 4, 8};
+  const int rows[] = {1, 2, 4, 8};
+  int err = MPF_OK;
+  for (int w : waves) {
+    for (int rr : rows) {
+      Tune t{w, rr};
+      rc = solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
+      if (rc) { err = rc; break; }
+      (void)hipEventRecord(e0, st);
+      rc = solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
+      (void)hipEventRecord(e1, st);
+      if (rc) { err = rc; break; }
+      if (hipEventSynchronize(e1) != hipSuccess) { err = MPF_ERR_HIP; break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    if (err) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  if (err) return err;
+  int dev = 0;
+  MPF_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(dev, nl, n_ops, solve)] = best;
+  }
+  out->waves_per_block = best.waves;
+  out->rows_per_wave = best.rows;
+  return MPF_OK;
+}
+
+extern "C" int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_t m, int nl,
+                                 int n_ops, const mpf_op* ops, const double* rowvec, double* w64, float* w32,
+                                 int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!pos || !sten || !ops || !info || n_nodes < 2 || m < 0 || n_ops < 1 || n_ops > kMaxOps) return MPF_ERR_ARG;
+  if (!w64 && !w32) return MPF_ERR_ARG;
+  if (ops_need_rowvec(n_ops, ops) && !rowvec) return MPF_ERR_ARG;
+  for (int o = 0; o < n_ops; ++o)
+    if (ops[o].kind < MPF_OP_DX || ops[o].kind > MPF_OP_SHIFT_ROW) return MPF_ERR_ARG;
+  if (!nl_supported(nl)) return MPF_ERR_UNSUPPORTED;
+  if (m == 0) return MPF_OK;
+  mpf_wgeom g{pos, n_nodes, sten, m, rowvec, w64, w32, info};
+  return mpf_rbffd_weights_batched(1, &g, nl, n_ops, ops, MPF_SOLVE_FP64, nullptr, ws, ws_bytes, stream);
 }

@@ -300,3 +300,47 @@ def test_lbm_full_size_one_cell(api):
     w64 = w64.cpu().numpy().transpose(2, 0, 1)
     for o_ in range(2):
         assert row_rel_err(w64[:, o_], w_ref[:, o_]) < 1e-10
+
+
+# ----------------------------------------------------------------- batched weights
+
+@pytest.fixture(scope="module")
+def three_clouds():
+    return [nc.sphere_cloud(r, 0.035, 0.3, 0.1, seed=10 + i) for i, r in enumerate((0.15, 0.35, 0.55))]
+
+
+@pytest.mark.parametrize("solve", [0, 1], ids=["fp64", "fp32_ir"])
+def test_batched_weights_parity(api, three_clouds, solve):
+    """Three clouds of different sizes in one launch, FP64 direct and FP32
+    factors with FP64 refinement, against the oracle row by row."""
+    ops = [("dx",), ("dy",), ("dz",), ("lap",)]
+    clouds = []
+    for c in three_clouds:
+        S = nc.stencils(c.pos, 30)
+        clouds.append((dev(c.pos.T, torch.float64), dev(S.T, torch.int32), None))
+    out = api.rbffd_weights_batched(clouds, ops, solve=solve, want32=True)
+    for c, (w64, w32, info) in zip(three_clouds, out):
+        S = nc.stencils(c.pos, 30)
+        w_ref, _ = O.weights(c.pos, S, ops)
+        info = info.cpu().numpy()
+        assert (info <= 0).all()
+        w = w64.cpu().numpy().transpose(2, 0, 1)
+        for o in range(len(ops)):
+            assert row_rel_err(w[:, o], w_ref[:, o]) < 1e-10
+        if solve == 1:
+            print(f"[ir] {c.n} rows, FP64 fallbacks: {(info < 0).sum()}", flush=True)
+
+
+def test_autotune_and_tuned_launch(api, three_clouds):
+    c = three_clouds[1]
+    S = nc.stencils(c.pos, 30)
+    pos, st = dev(c.pos.T, torch.float64), dev(S.T, torch.int32)
+    ops = [("dx",), ("lap",)]
+    waves, rows = api.weights_autotune(pos, st, ops, solve=0, sample_rows=2000)
+    assert waves in (1, 2, 4, 8) and rows in (1, 2, 4, 8)
+    w_ref, _ = O.weights(c.pos, S, ops)
+    for tune in (None, (waves, rows), (1, 8), (8, 1)):
+        (w64, _, info), = api.rbffd_weights_batched([(pos, st, None)], ops, tune=tune)
+        assert not info.cpu().numpy().any()
+        w = w64.cpu().numpy().transpose(2, 0, 1)
+        assert row_rel_err(w[:, 1], w_ref[:, 1]) < 1e-10

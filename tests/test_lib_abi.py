@@ -50,10 +50,21 @@ def test_host_argument_checks(lib):
     from paper_2404_14195_amd._lib import AcmParams, LbmParams, make_ops
     ops = make_ops([("dx",)])
     # null pointers, bad sizes: rejected before any launch
-    assert lib.mpf_rbffd_weights(None, 10, None, 5, 30, 1, ops, None, None, None, None, None) == -1
+    assert lib.mpf_rbffd_weights(None, 10, None, 5, 30, 1, ops, None, None, None, None, None, 0, None) == -1
     fake = ctypes.c_void_p(16)
-    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 30, 0, ops, None, fake, None, fake, None) == -1
-    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 31, 1, ops, None, fake, None, fake, None) == -3
+    big = lib.mpf_weights_workspace()
+    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 30, 0, ops, None, fake, None, fake, fake, big, None) == -1
+    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 31, 1, ops, None, fake, None, fake, fake, big, None) == -3
+    assert lib.mpf_rbffd_weights(fake, 10, fake, 5, 30, 1, ops, None, fake, None, fake, fake, 8, None) == -4
+    from paper_2404_14195_amd._lib import WGeom, WTune
+    geoms = (WGeom * 2)()
+    for g in geoms:
+        g.pos, g.n_nodes, g.sten, g.m, g.w64, g.info = fake, 10, fake, 5, fake, fake
+    assert lib.mpf_rbffd_weights_batched(0, geoms, 30, 1, ops, 0, None, fake, big, None) == -1
+    assert lib.mpf_rbffd_weights_batched(17, geoms, 30, 1, ops, 0, None, fake, big, None) == -1
+    assert lib.mpf_rbffd_weights_batched(2, geoms, 30, 1, ops, 2, None, fake, big, None) == -1
+    bad = WTune(waves_per_block=9, rows_per_wave=1)
+    assert lib.mpf_rbffd_weights_batched(2, geoms, 30, 1, ops, 0, ctypes.byref(bad), fake, big, None) == -1
     prm = AcmParams(nu=1, rho=1, dt=1e-5, beta=10, v_ref=1e-3, n_p=3, precision=0)
     assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 0,
                            None) == -4  # workspace too small
