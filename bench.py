@@ -49,6 +49,126 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"]
 
 
+def time_to_steady(torch, disc, MLBMSolver, F32, F64, check=500, rel=1e-3, max_steps=600_000):
+    """Wall-clock from rest to the first check with |k - k_inf| / k_inf <= rel.
+
+    k_inf: the FP64 run continued until k changes by less than 1e-8 relative
+    per check, then Aitken-extrapolated from its last three checks.  The
+    same FP64 run gives the FP64 time to steady; a fresh FP32 run (shifted
+    populations, FP64 reductions) is timed until it enters the band."""
+    import math
+
+    def trajectory(prec, stop):
+        s = MLBMSolver(disc, q=19, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ks, ts = [], []
+        while s.steps < max_steps:
+            s.run(check)
+            k = s.permeability()  # one device-to-host double per check
+            ks.append(k)
+            ts.append(time.perf_counter() - t0)
+            if stop(ks):
+                break
+        return s.steps, ks, ts
+
+    def settled(ks):
+        return len(ks) > 3 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1])
+
+    steps64, ks64, ts64 = trajectory(F64, settled)
+    k0, k1, k2 = ks64[-3:]
+    den = (k2 - k1) - (k1 - k0)
+    k_inf = k2 - (k2 - k1) ** 2 / den if den != 0 and (k2 - k1) * (k1 - k0) > 0 else k2
+    first = lambda ks: next((i for i, k in enumerate(ks) if abs(k - k_inf) <= rel * abs(k_inf)), None)
+    i64 = first(ks64)
+    steps32, ks32, ts32 = trajectory(F32, lambda ks: abs(ks[-1] - k_inf) <= rel * abs(k_inf))
+    i32 = first(ks32)
+    out = {"k_inf": k_inf, "rel": rel, "check_every": check, "fp64_settled_after_steps": steps64,
+           "fp64": None if i64 is None else {"steps": (i64 + 1) * check, "seconds": ts64[i64]},
+           "fp32": None if i32 is None else {"steps": (i32 + 1) * check, "seconds": ts32[i32]}}
+    if out["fp64"] and out["fp32"]:
+        out["speedup_fp32_vs_fp64"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
+    print(f"[bench] time to steady: k_inf={k_inf:.8e} fp64 {out['fp64']} fp32 {out['fp32']}", file=sys.stderr,
+          flush=True)
+    return out
+
+
+def _batch_cell(args):
+    import nodecloud as nc
+    r, h0, seed = args
+    c = nc.sphere_cloud(r, h0, 0.3, 4 * h0, seed=seed)
+    return c.pos, c.n
+
+
+def weights_batch(torch, nc, api):
+    """Eight SC cells, r uniform in [0.15, 0.6] (seed 4), sized to about
+    0.5, 1, ..., 4 M nodes (a seeded permutation), N_L = 30, four operators
+    (d/dx, d/dy, d/dz, Laplacian): every 40 x 40 saddle system in one launch,
+    FP64 direct and FP32 factors with FP64 refinement, autotuned block shape."""
+    import multiprocessing as mp
+    import numpy as np
+    rng = np.random.default_rng(4)
+    radii = rng.uniform(0.15, 0.6, 8)
+    targets = rng.permutation([0.5e6, 1e6, 1.5e6, 2e6, 2.5e6, 3e6, 3.5e6, 4e6])
+    # h(d) = min(h0 + 0.3 d, 4 h0): node count ~ c / h0^3, c calibrated on the
+    # 1.83M-node cell (h0 = 0.002) and scaled by porosity
+    h0s = [0.002 * (1.83e6 / t * (1 - 4.19 * min(r, 0.5) ** 3) / (1 - 4.19 * 0.027)) ** (1 / 3)
+           for r, t in zip(radii, targets)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(8) as pool:
+        cells = pool.map(_batch_cell, [(float(r), float(h), 40 + i) for i, (r, h) in enumerate(zip(radii, h0s))])
+    torch.cuda.set_device(0)
+    print(f"[bench] 8 cells, {sum(c[1] for c in cells)} nodes, fill {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    clouds = []
+    from scipy.spatial import cKDTree
+    for pos, n in cells:
+        tree = cKDTree(pos % 1.0, boxsize=1.0)
+        _, idx = tree.query(pos % 1.0, k=30, workers=-1)
+        clouds.append((torch.as_tensor(np.ascontiguousarray(pos.T), device="cuda"),
+                       torch.as_tensor(np.ascontiguousarray(idx.T.astype(np.int32)), device="cuda"), None))
+        del tree, idx
+        print(f"[bench] stencils of a {n}-node cell, {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] stencils done {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    ops = [("dx",), ("dy",), ("dz",), ("lap",)]
+    rows = sum(c[1].shape[1] for c in clouds)
+    n = 40
+    flops = (2.0 / 3.0) * n ** 3 + 2 * n * n * len(ops)
+    out = {"cells": [{"r": float(r), "n": int(c[1].shape[1])} for r, c in zip(radii, clouds)], "rows": rows,
+           "flops_per_row": flops}
+    ref = None
+    for name, solve in (("fp64", 0), ("fp32_ir", 1)):
+        tune = api.weights_autotune(clouds[0][0], clouds[0][1], ops, solve=solve, sample_rows=65536)
+        api.rbffd_weights_batched(clouds[:1], ops, solve=solve)  # warm
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        res = api.rbffd_weights_batched(clouds, ops, solve=solve)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        fallbacks = int(sum(int((r[2] < 0).sum().item()) for r in res))
+        singular = int(sum(int((r[2] > 0).sum().item()) for r in res))
+        rec = {"ms": ms, "systems_per_s": rows / (ms * 1e-3), "tflops": rows * flops / (ms * 1e-3) / 1e12,
+               "fp64_peak_frac": rows * flops / (ms * 1e-3) / 78.6e12, "tune": tune, "fp64_fallback_rows": fallbacks,
+               "singular_rows": singular}
+        if ref is None:
+            ref = [r[0] for r in res]
+        else:
+            err = 0.0
+            for a, b in zip(ref, res):
+                d = (a - b[0]).abs().amax(dim=(0, 1)) / a.abs().amax(dim=(0, 1))
+                err = max(err, float(d.max().item()))
+            rec["max_row_rel_err_vs_fp64"] = err
+        out[name] = rec
+        print(f"[bench] weights {name}: {ms:.1f} ms, {rec['systems_per_s']:.3e} systems/s, tune {tune}",
+              file=sys.stderr, flush=True)
+        del res
+        torch.cuda.empty_cache()
+    return out
+
+
 def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4):
     """Algorithmic bytes of one ACM node-step: predictor (4 operators, v in,
     v' out), then per coupling iteration a pressure pass (3 operators, v and p
@@ -119,6 +239,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the ACM and weight-solve side measurements")
+    ap.add_argument("--no-steady", action="store_true", help="skip the time-to-steady measurement")
+    ap.add_argument("--weights-batch", action="store_true",
+                    help="only measure the batched weight solve of 8 cells (about 18M rows) and exit")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -134,6 +257,11 @@ def main():
     from paper_2404_14195_amd import MPF_F32, MPF_F64, api
     from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
 
+    if args.weights_batch:
+        # the node clouds are generated in worker processes before this
+        # process touches the GPU
+        print(json.dumps(weights_batch(torch, nc, api)))
+        return
     torch.cuda.set_device(0)
     if args.copy_calib_mib:
         src = torch.ones(args.copy_calib_mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
@@ -219,6 +347,7 @@ def main():
                "sample": f"{n_cpu} FP64 steps of the full {cloud.n}-node cell (weights precomputed, not timed), "
                          f"single-threaded scalar C"}
 
+    tts = None if args.no_steady else time_to_steady(torch, disc, MLBMSolver, MPF_F32, MPF_F64)
     extra = None if args.no_extra else acm_and_weights(torch, nc, api)
 
     out = {
@@ -237,6 +366,7 @@ def main():
         "weights_ms": {"fp32": f32["weights_ms"], "fp64": res["f64"]["weights_ms"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "time_to_steady": tts,
         "acm": extra,
     }
     print(json.dumps(out))

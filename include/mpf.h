@@ -129,7 +129,7 @@ int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, i
  * meaning as the arguments of mpf_rbffd_weights (rowvec per cloud when an
  * operator needs it).
  * solve: MPF_SOLVE_FP64 (direct), or MPF_SOLVE_FP32_IR: FP32 factors with
- *        FP64-residual iterative refinement (at most three sweeps, stop at
+ *        FP64-residual iterative refinement (at most five sweeps, stop at
  *        |dx| <= 1e-15 |x|; otherwise the row is re-solved in FP64, info -1).
  * tune:  host pointer to the tile shape, or NULL for the shape that
  *        mpf_weights_autotune last chose for (device, nl, n_ops, solve), or a

@@ -98,13 +98,26 @@ class Cloud:
         return self.n - self.n_int
 
 
+def estimate_count(r: float, h0: float, slope: float, hmax: float, hb: float) -> float:
+    """Rough node count of a fill: integral of 1/h^3 over the fluid (midpoint
+    rule on a 64^3 grid, refined near the grain through h itself) plus the
+    surface nodes.  Used only to size the generator's buffers."""
+    g = (np.arange(64) + 0.5) / 64
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    d = sphere_sdf(X, r)
+    h = np.minimum(h0 + slope * np.maximum(d, 0.0), hmax)
+    vol = np.where(d > 0, 1.0 / h ** 3, 0.0).mean()
+    # the midpoint rule misses the thin refined shell; add it explicitly
+    shell = 4 * np.pi * r * r * min(hmax, 4 * h0) / h0 ** 3
+    return vol + shell + 4 * np.pi * r * r / (1.15 * hb * hb)
+
+
 def sphere_cloud(r: float, h0: float, slope: float, hmax: float, seed: int, hb: float | None = None,
                  n_cand: int = 20) -> Cloud:
     """Boundary nodes on the sphere plus an advancing-front fill of the fluid."""
     lib = _load()
     hb = h0 if hb is None else hb
-    est = int(3.0 / hmax ** 3 + 2.0 * 4 * np.pi * r * r / hb ** 2 + 40.0 / h0 ** 3 * min(1.0, 4 * r + 10 * h0)) + 1024
-    cap = max(est, 4096)
+    cap = max(int(1.5 * estimate_count(r, h0, slope, hmax, hb)) + 4096, 16384)
     while True:
         pos = np.zeros((cap, 3))
         nrm = np.zeros((cap, 3))

@@ -21,7 +21,7 @@
 //
 // Precision: FP64 direct, or FP32 factors with FP64-residual iterative
 // refinement (x += LU32^-1 (b - M x) with M and the residual in FP64, up to
-// three sweeps).  A row whose refinement has not reached
+// kIrSweeps sweeps).  A row whose refinement has not reached
 // |dx| <= 1e-15 |x| is re-solved in FP64 and flagged with info < 0.
 #include <algorithm>
 #include <map>
@@ -37,6 +37,9 @@ namespace {
 constexpr int kMaxOps = 32;
 constexpr int kMaxGeoms = 16;
 constexpr int RB = 4;
+// refinement sweeps after the FP32 solve: with kappa ~ 1e4 each sweep gains
+// about log10(1 / (kappa eps32)) = 3.4 digits, so five reach 1e-15
+constexpr int kIrSweeps = 5;
 
 struct OpsArg {
   int n;
@@ -249,7 +252,7 @@ __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, i
 
 // FP32 factors with FP64-residual refinement for one stencil row (same lane
 // layout as the FP64 solve).  Returns false if some chunk of right-hand sides
-// has not settled after three sweeps (or the FP32 factorisation met a zero
+// has not settled after kIrSweeps sweeps (or the FP32 factorisation met a zero
 // pivot); the caller then re-solves the row in FP64.
 template <int NL>
 __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int64_t n_nodes,
@@ -316,7 +319,7 @@ __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int
     }
     bool ok = false;
     // sweep 0 solves M x = b; later sweeps solve M d = b - M x (FP64 residual)
-    for (int sweep = 0; sweep < 4 && !ok; ++sweep) {
+    for (int sweep = 0; sweep < 1 + kIrSweeps && !ok; ++sweep) {
       float rf[RB];
       if (sweep == 0) {
 #pragma unroll
