@@ -81,9 +81,14 @@ def time_to_steady(torch, disc, MLBMSolver, F32, F64, check=500, rel=1e-3, max_s
     k_inf = k2 - (k2 - k1) ** 2 / den if den != 0 and (k2 - k1) * (k1 - k0) > 0 else k2
     first = lambda ks: next((i for i, k in enumerate(ks) if abs(k - k_inf) <= rel * abs(k_inf)), None)
     i64 = first(ks64)
-    steps32, ks32, ts32 = trajectory(F32, lambda ks: abs(ks[-1] - k_inf) <= rel * abs(k_inf))
+    # the FP32 run continues until it settles too, so that its own steady k
+    # (where FP32 rounding stalls the iteration) is measured against k_inf
+    steps32, ks32, ts32 = trajectory(F32, settled)
     i32 = first(ks32)
     out = {"k_inf": k_inf, "rel": rel, "check_every": check, "fp64_settled_after_steps": steps64,
+           "fp32_settled_after_steps": steps32, "fp32_settled_k": ks32[-1],
+           "fp32_settled_rel_err": abs(ks32[-1] - k_inf) / abs(k_inf),
+           "fp64_settled_rel_err": abs(ks64[-1] - k_inf) / abs(k_inf),
            "fp64": None if i64 is None else {"steps": (i64 + 1) * check, "seconds": ts64[i64]},
            "fp32": None if i32 is None else {"steps": (i32 + 1) * check, "seconds": ts32[i32]}}
     if out["fp64"] and out["fp32"]:
