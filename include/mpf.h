@@ -52,9 +52,18 @@ extern "C" {
 #define MPF_ERR_UNSUPPORTED (-3) /* valid but not built: e.g. a stencil size without a kernel */
 #define MPF_ERR_WORKSPACE (-4)   /* workspace missing or too small */
 
-/* precision of fields and stencil weights */
+/* Precision of stencil weights and state.
+ *   MPF_F64    weights and state FP64
+ *   MPF_F32    weights and state FP32 (reductions stay FP64)
+ *   MPF_MIXED  weights FP32, state and all step arithmetic FP64.  An explicit
+ *              iteration whose slowest mode decays over tau steps settles
+ *              within about tau ulp of its fixed point, so FP32 state stalls
+ *              at ~1e-3 relative on the cells here (tau ~ 2e4 steps); the
+ *              weights, which dominate the bytes per step, carry the FP32
+ *              saving without that stall. */
 #define MPF_F64 0
 #define MPF_F32 1
+#define MPF_MIXED 2
 
 /* Static description of an error code; never NULL. */
 const char* mpf_strerror(int code);
@@ -129,8 +138,10 @@ int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, i
  * meaning as the arguments of mpf_rbffd_weights (rowvec per cloud when an
  * operator needs it).
  * solve: MPF_SOLVE_FP64 (direct), or MPF_SOLVE_FP32_IR: FP32 factors with
- *        FP64-residual iterative refinement (at most five sweeps, stop at
- *        |dx| <= 1e-15 |x|; otherwise the row is re-solved in FP64, info -1).
+ *        FP64-residual iterative refinement (at most five sweeps; stop at
+ *        |dx| <= 1e-15 |x|, or once |dx| <= 1e-9 |x| no longer shrinks 4x per
+ *        sweep, the FP64-residual floor; otherwise the row is re-solved in
+ *        FP64, info -1).
  * tune:  host pointer to the tile shape, or NULL for the shape that
  *        mpf_weights_autotune last chose for (device, nl, n_ops, solve), or a
  *        default (4 waves per block, 1 row per wave).
@@ -191,8 +202,9 @@ int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const 
  * vmax  dev double [1]: max_i |v_i| of the current state, in/out (0 for a
  *       state at rest); C is derived from it
  * ws    workspace of mpf_acm_workspace() bytes
- * Fields and weights share one precision (MPF_F64 or MPF_F32).  With MPF_F32
- * all arithmetic except the max is FP32.
+ * precision: MPF_F64, MPF_F32 (weights and fields FP32, all arithmetic
+ * except the max FP32) or MPF_MIXED (weights w, wn FP32; fields v, p and the
+ * workspace FP64; FP64 arithmetic).
  * lanes: how many adjacent lanes share one node's stencil sum (1, 2, 4, 8 or
  * 16; 0 picks 8 for n_int <= 200000 and 2 above).  Results agree to rounding
  * (the order of the partial sums differs). */
@@ -221,9 +233,11 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  *   stream: f_k(i) = sum_j W_k[j][i] f^post_k(sten[j][i]) for k >= 1 (W_k
  *     interpolates at the departure point of population k), f_0 = f^post_0;
  *   bounce-back at boundary node b: where e_k . n_b > 0, f_k = f_{opp(k)}.
- * W     dev [q-1][nl][n] (population k uses slice k - 1), precision as f
+ * W     dev [q-1][nl][n] (population k uses slice k - 1): double for
+ *       MPF_F64, float for MPF_F32 and MPF_MIXED
  * nrm   dev [3][nb] double
- * f     dev [n][qp] state, updated in place; f_tmp dev [n][qp] scratch
+ * f     dev [n][qp] state, updated in place; f_tmp dev [n][qp] scratch:
+ *       double for MPF_F64 and MPF_MIXED, float for MPF_F32
  * q is 15 or 19. */
 typedef struct {
   int32_t q;
@@ -234,6 +248,12 @@ typedef struct {
 
 /* f~ = f^eq(rho, u) - w_k on every node. */
 int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, const double* u_host, void* f, void* stream);
+/* f~ = f^eq(rho_i, u_i) - w_k from fields in physical units, the inverse of
+ * mpf_lbm_moments: u_i = v_i / vel_scale, rho_i = 1 + 3 p_i / vel_scale^2.
+ * v dev [3][n] double, p dev [n] double (any gauge: only differences of p
+ * drive the flow).  Starts a run from a predicted field (warm start). */
+int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const double* v, const double* p, double vel_scale,
+                        void* f, void* stream);
 int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* W,
                 const double* nrm, void* f, void* f_tmp, int n_steps, void* stream);
 /* Macroscopic fields in physical units (Eq. conversion_factors): v[3][n] =
@@ -246,7 +266,8 @@ int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double 
  * Mean x-velocity over the five cross-sections, Eq. k_definition, as the mean
  * over all n_all = 5 M^2 midpoint samples, solid samples counting zero.  The
  * ns fluid samples interpolate v_x with weights s_w over stencils s_idx.
- * s_idx dev [nl][ns]; s_w dev [nl][ns] double; vx dev [n] (precision);
+ * s_idx dev [nl][ns]; s_w dev [nl][ns] double; vx dev [n] (float for MPF_F32,
+ * double for MPF_F64 and MPF_MIXED: the type of the state);
  * q_out dev double[1].  The sum is a fixed-order FP64 tree, so results are
  * bitwise reproducible. */
 size_t mpf_reduce_workspace(int64_t n_items);
@@ -263,6 +284,77 @@ int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w,
 int mpf_drag(int64_t n, const void* v, const void* p, int precision, int64_t nb, int nl, const int32_t* sb,
              const double* wg, const double* nrm, double rho, double nu, double dA, double* F_out, void* ws,
              size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------- learned warm start
+ * An addition to the paper's method: a multilayer perceptron maps per-node
+ * features of a cell to a predicted steady state (velocity and pressure),
+ * which starts the explicit iteration of either solver instead of rest.  It
+ * is trained on the solvers' own steady fields; the cold-started solver stays
+ * the reference for its error.
+ *
+ * Shape (the only one built): in_dim 5, width 128, depth 4 linear layers,
+ * out_dim 4, i.e. 5 -> 128 -> 128 -> 128 -> 4 with SiLU, z / (1 + e^-z),
+ * after each hidden layer; any other desc gives MPF_ERR_UNSUPPORTED.
+ * master   dev float [mpf_mlp_param_count()]: W_1, b_1, ..., W_4, b_4, with
+ *          W_l [out][in] row-major (the FP32 master copy Adam updates)
+ * packed   dev BF16 [mpf_mlp_packed_count()]: the weights as the products
+ *          read them; refresh with mpf_mlp_pack after every update
+ * x        dev float [rows][5]: features (mpf_mlp_features)
+ * rows     dev int64 [B] or NULL: sample b of a batch is row rows[b] of x
+ *          (and of t in mpf_mlp_mse); NULL means b itself
+ * y        dev float [B][4]: outputs (v_x, v_y, v_z, p) / (U, P)
+ * Products use BF16 operands with FP32 accumulation (MFMA); biases,
+ * pre-activations and the derivative of SiLU are FP32.  All sums are in a
+ * fixed order: repeated calls give identical bits.  Workspaces are device
+ * memory of at least the stated size; they are not zeroed by the caller. */
+typedef struct {
+  int32_t in_dim, width, depth, out_dim;
+} mpf_mlp_desc;
+
+int64_t mpf_mlp_param_count(const mpf_mlp_desc* d);  /* 34308, or -1 */
+int64_t mpf_mlp_packed_count(const mpf_mlp_desc* d); /* BF16 elements, or -1 */
+/* Bytes for a batch of B samples; train != 0 adds what backward reads. 0 for
+ * an unsupported desc or B outside [1, 2^26]. */
+size_t mpf_mlp_workspace(const mpf_mlp_desc* d, int64_t B, int train);
+int mpf_mlp_pack(const mpf_mlp_desc* d, const float* master, void* packed, void* stream);
+/* y = net(x[rows]).  train != 0 keeps the activations in ws for
+ * mpf_mlp_backward (ws sized with train = 1). */
+int mpf_mlp_forward(const mpf_mlp_desc* d, const float* master, const void* packed, const float* x,
+                    const int64_t* rows, float* y, int64_t B, int train, void* ws, size_t ws_bytes, void* stream);
+/* grad (dev float, master layout) = d(sum dy . y)/d(params) for the batch of
+ * the last mpf_mlp_forward with train = 1 on the same ws and B; dy dev float
+ * [B][4].  grad is overwritten. */
+int mpf_mlp_backward(const mpf_mlp_desc* d, const void* packed, const float* dy, float* grad, int64_t B, void* ws,
+                     size_t ws_bytes, void* stream);
+/* loss (dev double[1]) = mean over B x 4 entries of (y - t[rows])^2 (FP64
+ * fixed-order sum); dy (dev float [B][4]) = 2 (y - t) / (4 B).  t dev float
+ * [rows][4].  ws: mpf_reduce_workspace(4 B) bytes. */
+int mpf_mlp_mse(int64_t B, const float* y, const float* t, const int64_t* rows, float* dy, double* loss, void* ws,
+                size_t ws_bytes, void* stream);
+/* One Adam step (t = step >= 1, bias-corrected): m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * p, g, m, v dev float [n]; m and v start at zero. */
+int mpf_adam_step(int64_t n, float* p, const float* g, float* m, float* v, int step, float lr, float b1, float b2,
+                  float eps, void* stream);
+/* Features of the nodes of the simple-cubic cell with a grain of radius r at
+ * (1/2, 1/2, 1/2) (Sec. 2.4): x[i] = (d_x, d_y, d_z, |d| - r, phi) with d the
+ * minimum-image offset of pos_i from the grain centre.  pos dev [3][n]
+ * double; x dev float [n][5]. */
+int mpf_mlp_features(int64_t n, const double* pos, double r, double phi, float* x, void* stream);
+/* Network outputs y dev float [n][4] -> solver state: v = U y_{0..2} on the
+ * interior nodes [0, n_int) and 0 on the grain (no slip), p = P y_3 minus its
+ * node mean (fixed-order FP64 mean).  v dev [3][n], p dev [n], of the state
+ * type of precision (float for MPF_F32, else double).  vmax dev double[1] or
+ * NULL: receives max |v| (the input mpf_acm_run expects).  ws:
+ * mpf_reduce_workspace(n) bytes. */
+int mpf_mlp_to_state(int64_t n, int64_t n_int, const float* y, double U, double P, int precision, void* v, void* p,
+                     double* vmax, void* ws, size_t ws_bytes, void* stream);
+/* The library's BF16 product on its own: C[m][n] = sum_k A[m][k] Bt[n][k]
+ * with FP32 accumulation.  A dev BF16 [M][lda], Bt dev BF16 [N][ldb] (16-byte
+ * aligned, lda and ldb multiples of 8), C dev float [M][ldc]; K a multiple of
+ * 32, K <= lda, ldb; N <= ldc. */
+int mpf_gemm_bf16(int64_t M, int N, int64_t K, const void* A, int64_t lda, const void* Bt, int64_t ldb, float* C,
+                  int64_t ldc, void* stream);
 
 #ifdef __cplusplus
 }

@@ -12,9 +12,9 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _INC = os.path.join(os.path.dirname(_HERE), "include")
 SO_PATH = os.path.join(_HERE, "libmpf.so")
-SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip"]
+SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip"]
 
-MPF_F64, MPF_F32 = 0, 1
+MPF_F64, MPF_F32, MPF_MIXED = 0, 1, 2
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
 OP = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shift_row": 7}
 
@@ -48,6 +48,11 @@ def build() -> str:
     return SO_PATH
 
 
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("out_dim", ctypes.c_int32)]
+
+
 class _Op(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("vec", ctypes.c_double * 3)]
 
@@ -79,6 +84,7 @@ def _load():
         raise MPFError(f"libmpf.so is not built ({SO_PATH}); run __graft_entry__.build()")
     lib = ctypes.CDLL(SO_PATH)
     vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    flt = ctypes.c_float
     sig = {
         "mpf_strerror": (ctypes.c_char_p, [i32]),
         "mpf_version": (i32, []),
@@ -90,11 +96,23 @@ def _load():
         "mpf_acm_workspace": (sz, [i64, i32]),
         "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
         "mpf_lbm_init": (i32, [vp, i64, dbl, vp, vp, vp]),
+        "mpf_lbm_init_fields": (i32, [vp, i64, vp, vp, dbl, vp, vp]),
         "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, i32, vp]),
         "mpf_lbm_moments": (i32, [vp, i64, vp, dbl, vp, vp, vp]),
         "mpf_reduce_workspace": (sz, [i64]),
         "mpf_flux_planes": (i32, [i64, i32, vp, vp, vp, i32, i64, vp, vp, sz, vp]),
         "mpf_drag": (i32, [i64, vp, vp, i32, i64, i32, vp, vp, vp, dbl, dbl, dbl, vp, vp, sz, vp]),
+        "mpf_mlp_param_count": (i64, [vp]),
+        "mpf_mlp_packed_count": (i64, [vp]),
+        "mpf_mlp_workspace": (sz, [vp, i64, i32]),
+        "mpf_mlp_pack": (i32, [vp, vp, vp, vp]),
+        "mpf_mlp_forward": (i32, [vp, vp, vp, vp, vp, vp, i64, i32, vp, sz, vp]),
+        "mpf_mlp_backward": (i32, [vp, vp, vp, vp, i64, vp, sz, vp]),
+        "mpf_mlp_mse": (i32, [i64, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mpf_adam_step": (i32, [i64, vp, vp, vp, vp, i32, flt, flt, flt, flt, vp]),
+        "mpf_mlp_features": (i32, [i64, vp, dbl, dbl, vp, vp]),
+        "mpf_mlp_to_state": (i32, [i64, i64, vp, dbl, dbl, i32, vp, vp, vp, vp, sz, vp]),
+        "mpf_gemm_bf16": (i32, [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -116,7 +134,10 @@ def lib():
 
 EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",
-            "mpf_lbm_init", "mpf_lbm_run", "mpf_lbm_moments", "mpf_reduce_workspace", "mpf_flux_planes", "mpf_drag"]
+            "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_moments", "mpf_reduce_workspace",
+            "mpf_flux_planes", "mpf_drag", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
+            "mpf_mlp_pack", "mpf_mlp_forward", "mpf_mlp_backward", "mpf_mlp_mse", "mpf_adam_step",
+            "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16"]
 
 
 def check(rc: int, what: str):

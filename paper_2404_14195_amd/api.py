@@ -8,9 +8,11 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import MPF_F32, MPF_F64, AcmParams, LbmParams, WGeom, WTune, check, lib, make_ops
+from ._lib import MPF_F32, MPF_F64, MPF_MIXED, AcmParams, LbmParams, WGeom, WTune, check, lib, make_ops
 
-_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32}
+# element type of the state (fields, populations) and of the stencil weights
+_ST = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64}
+_WT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float32}
 
 
 def _stream():
@@ -131,14 +133,14 @@ def acm_workspace(n: int, precision: int, device) -> torch.Tensor:
 
 def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: int, ws=None):
     prec = prm.precision
-    dt = _DT[prec]
+    dt, dw = _ST[prec], _WT[prec]
     nl, n = sten.shape
-    _need(w, dt, (4, nl, n), "w")
+    _need(w, dw, (4, nl, n), "w")
     _need(v, dt, (3, n), "v")
     _need(p, dt, (n,), "p")
     _need(vmax, torch.float64, (1,), "vmax")
     if n > n_int:
-        _need(wn, dt, (nl, n - n_int), "wn")
+        _need(wn, dw, (nl, n - n_int), "wn")
         _need(sn, torch.int32, (nl, n - n_int), "sn")
     if ws is None:
         ws = acm_workspace(n, prec, v.device)
@@ -152,17 +154,27 @@ def record_len(q: int) -> int:
 
 
 def lbm_init(prm: LbmParams, f, rho=1.0, u=(0.0, 0.0, 0.0)):
-    _need(f, _DT[prm.precision], name="f")
+    _need(f, _ST[prm.precision], name="f")
     if f.dim() != 2 or f.shape[1] != record_len(prm.q):
         raise ValueError("f must be [n][qp]")
     uu = (ctypes.c_double * 3)(*[float(x) for x in u])
     check(lib().mpf_lbm_init(ctypes.byref(prm), f.shape[0], float(rho), uu, _p(f), _stream()), "mpf_lbm_init")
 
 
+def lbm_init_fields(prm: LbmParams, f, v, p, vel_scale: float):
+    """Equilibrium state of fields v [3][n], p [n] (double, physical units)."""
+    _need(f, _ST[prm.precision], name="f")
+    n = f.shape[0]
+    _need(v, torch.float64, (3, n), "v")
+    _need(p, torch.float64, (n,), "p")
+    check(lib().mpf_lbm_init_fields(ctypes.byref(prm), n, _p(v), _p(p), float(vel_scale), _p(f), _stream()),
+          "mpf_lbm_init_fields")
+
+
 def lbm_run(prm: LbmParams, n_int: int, sten, W, nrm, f, f_tmp, n_steps: int):
-    dt = _DT[prm.precision]
+    dt = _ST[prm.precision]
     nl, n = sten.shape
-    _need(W, dt, (prm.q - 1, nl, n), "W")
+    _need(W, _WT[prm.precision], (prm.q - 1, nl, n), "W")
     _need(f, dt, (n, record_len(prm.q)), "f")
     _need(f_tmp, dt, (n, record_len(prm.q)), "f_tmp")
     if n > n_int:
@@ -172,7 +184,7 @@ def lbm_run(prm: LbmParams, n_int: int, sten, W, nrm, f, f_tmp, n_steps: int):
 
 
 def lbm_moments(prm: LbmParams, f, vel_scale: float, v=None, p=None):
-    _need(f, _DT[prm.precision], name="f")
+    _need(f, _ST[prm.precision], name="f")
     n = f.shape[0]
     v = torch.empty((3, n), dtype=torch.float64, device=f.device) if v is None else v
     p = torch.empty(n, dtype=torch.float64, device=f.device) if p is None else p
@@ -207,3 +219,110 @@ def drag(v, p, sb, wg, nrm, rho: float, nu: float, dA: float, F_out=None, ws=Non
     check(lib().mpf_drag(n, _p(v), _p(p), precision_of(p.dtype), nb, nl, _p(sb), _p(wg), _p(nrm), float(rho), float(nu),
                        float(dA), _p(F_out), _p(ws), ws.numel(), _stream()), "mpf_drag")
     return F_out
+
+
+# ---------------------------------------------------------------- learned warm start
+
+MLP_DESC = _lib.MlpDesc(5, 128, 4, 4)
+
+
+def mlp_param_count() -> int:
+    return int(lib().mpf_mlp_param_count(ctypes.byref(MLP_DESC)))
+
+
+def mlp_packed_count() -> int:
+    return int(lib().mpf_mlp_packed_count(ctypes.byref(MLP_DESC)))
+
+
+def mlp_workspace(batch: int, train: bool, device="cuda") -> torch.Tensor:
+    nbytes = lib().mpf_mlp_workspace(ctypes.byref(MLP_DESC), int(batch), int(bool(train)))
+    if nbytes == 0:
+        raise ValueError(f"unsupported MLP batch {batch}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def mlp_pack(master, packed):
+    _need(master, torch.float32, (mlp_param_count(),), "master")
+    _need(packed, torch.bfloat16, (mlp_packed_count(),), "packed")
+    check(lib().mpf_mlp_pack(ctypes.byref(MLP_DESC), _p(master), _p(packed), _stream()), "mpf_mlp_pack")
+
+
+def mlp_forward(master, packed, x, y, ws, rows=None, train=False):
+    """y [B][4] = net(x[rows]) (B = len(rows) or len(x))."""
+    _need(x, torch.float32, name="x")
+    if x.dim() != 2 or x.shape[1] != 5:
+        raise ValueError("x must be [rows][5]")
+    B = x.shape[0] if rows is None else rows.shape[0]
+    if rows is not None:
+        _need(rows, torch.int64, (B,), "rows")
+    _need(y, torch.float32, (B, 4), "y")
+    check(lib().mpf_mlp_forward(ctypes.byref(MLP_DESC), _p(master), _p(packed), _p(x), _p(rows), _p(y), B,
+                                int(bool(train)), _p(ws), ws.numel(), _stream()), "mpf_mlp_forward")
+
+
+def mlp_backward(packed, dy, grad, ws):
+    B = dy.shape[0]
+    _need(dy, torch.float32, (B, 4), "dy")
+    _need(grad, torch.float32, (mlp_param_count(),), "grad")
+    check(lib().mpf_mlp_backward(ctypes.byref(MLP_DESC), _p(packed), _p(dy), _p(grad), B, _p(ws), ws.numel(),
+                                 _stream()), "mpf_mlp_backward")
+
+
+def mlp_mse(y, t, dy, loss, ws, rows=None):
+    B = y.shape[0]
+    _need(y, torch.float32, (B, 4), "y")
+    _need(t, torch.float32, name="t")
+    _need(dy, torch.float32, (B, 4), "dy")
+    _need(loss, torch.float64, (1,), "loss")
+    if rows is not None:
+        _need(rows, torch.int64, (B,), "rows")
+    check(lib().mpf_mlp_mse(B, _p(y), _p(t), _p(rows), _p(dy), _p(loss), _p(ws), ws.numel(), _stream()),
+          "mpf_mlp_mse")
+
+
+def adam_step(p, g, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    n = p.numel()
+    for t, name in ((p, "p"), (g, "g"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, (n,), name)
+    check(lib().mpf_adam_step(n, _p(p), _p(g), _p(m), _p(v), int(step), float(lr), float(b1), float(b2),
+                              float(eps), _stream()), "mpf_adam_step")
+
+
+def mlp_features(pos, r: float, phi: float, x=None):
+    n = pos.shape[1]
+    _need(pos, torch.float64, (3, n), "pos")
+    if x is None:
+        x = torch.empty((n, 5), dtype=torch.float32, device=pos.device)
+    _need(x, torch.float32, (n, 5), "x")
+    check(lib().mpf_mlp_features(n, _p(pos), float(r), float(phi), _p(x), _stream()), "mpf_mlp_features")
+    return x
+
+
+def mlp_to_state(y, n_int: int, U: float, P: float, v, p, vmax=None, ws=None):
+    n = y.shape[0]
+    _need(y, torch.float32, (n, 4), "y")
+    if v.dtype != p.dtype or v.dtype not in (torch.float32, torch.float64):
+        raise TypeError("v and p must share float32 or float64")
+    _need(v, v.dtype, (3, n), "v")
+    _need(p, v.dtype, (n,), "p")
+    if vmax is not None:
+        _need(vmax, torch.float64, (1,), "vmax")
+    if ws is None:
+        ws = reduce_workspace(n, y.device)
+    prec = MPF_F32 if v.dtype == torch.float32 else MPF_F64
+    check(lib().mpf_mlp_to_state(n, int(n_int), _p(y), float(U), float(P), prec, _p(v), _p(p), _p(vmax), _p(ws),
+                                 ws.numel(), _stream()), "mpf_mlp_to_state")
+
+
+def gemm_bf16(A, Bt, C=None, K=None):
+    """C [M][N] = A[:, :K] Bt[:, :K]^T, BF16 in, FP32 out."""
+    _need(A, torch.bfloat16, name="A")
+    _need(Bt, torch.bfloat16, name="Bt")
+    M, lda = A.shape
+    N, ldb = Bt.shape
+    K = lda if K is None else K
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _need(C, torch.float32, name="C")
+    check(lib().mpf_gemm_bf16(M, N, K, _p(A), lda, _p(Bt), ldb, _p(C), C.shape[1], _stream()), "mpf_gemm_bf16")
+    return C

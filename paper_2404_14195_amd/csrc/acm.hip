@@ -33,14 +33,14 @@ __device__ __forceinline__ T group_sum(T x) {
   return x;
 }
 
-template <typename T>
+template <typename T, typename TW>
 struct Fields {
   int64_t n, n_int, nb;
   int nl;
   const int32_t* sten;
-  const T* w;  // [4][nl][n]
+  const TW* w;  // [4][nl][n]
   const int32_t* sn;
-  const T* wn;  // [nl][nb]
+  const TW* wn;  // [nl][nb]
   T* v;         // [3][n]
   T* p;         // [n]
   T* vp;        // [3][n]
@@ -49,8 +49,8 @@ struct Fields {
   double dtd, rho, beta, v_ref;
 };
 
-template <typename T, int LPN>
-__device__ __forceinline__ void predictor_node(const Fields<T>& F, int64_t i, int sl) {
+template <typename T, typename TW, int LPN>
+__device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i, int sl) {
   const int64_t n = F.n, os = (int64_t)F.nl * n;
   T d[3][4];
 #pragma unroll
@@ -60,7 +60,7 @@ __device__ __forceinline__ void predictor_node(const Fields<T>& F, int64_t i, in
   for (int j = sl; j < F.nl; j += LPN) {
     const int64_t at = (int64_t)j * n + i;
     const int s = F.sten[at];
-    const T wx = F.w[at], wy = F.w[os + at], wz = F.w[2 * os + at], wl = F.w[3 * os + at];
+    const T wx = (T)F.w[at], wy = (T)F.w[os + at], wz = (T)F.w[2 * os + at], wl = (T)F.w[3 * os + at];
     const T u[3] = {F.v[s], F.v[n + s], F.v[2 * n + s]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -85,42 +85,42 @@ __device__ __forceinline__ void predictor_node(const Fields<T>& F, int64_t i, in
   }
 }
 
-template <typename T, int LPN>
-__device__ __forceinline__ void pressure_node(const Fields<T>& F, const T* __restrict__ vsrc, T coef, int64_t i,
+template <typename T, typename TW, int LPN>
+__device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* __restrict__ vsrc, T coef, int64_t i,
                                               int sl) {
   const int64_t n = F.n, os = (int64_t)F.nl * n;
   T div = T(0);
   for (int j = sl; j < F.nl; j += LPN) {
     const int64_t at = (int64_t)j * n + i;
     const int s = F.sten[at];
-    div += F.w[at] * vsrc[s] + F.w[os + at] * vsrc[n + s] + F.w[2 * os + at] * vsrc[2 * n + s];
+    div += (T)F.w[at] * vsrc[s] + (T)F.w[os + at] * vsrc[n + s] + (T)F.w[2 * os + at] * vsrc[2 * n + s];
   }
   div = group_sum<LPN>(div);
   if (sl == 0) F.p[i] -= coef * div;
 }
 
-template <typename T, int LPN>
-__device__ __forceinline__ void neumann_node(const Fields<T>& F, int64_t b, int sl) {
+template <typename T, typename TW, int LPN>
+__device__ __forceinline__ void neumann_node(const Fields<T, TW>& F, int64_t b, int sl) {
   T s = T(0);
   for (int j = 1 + sl; j < F.nl; j += LPN) {
     const int64_t at = (int64_t)j * F.nb + b;
-    s += F.wn[at] * F.p[F.sn[at]];
+    s += (T)F.wn[at] * F.p[F.sn[at]];
   }
   s = group_sum<LPN>(s);
-  if (sl == 0) F.p[F.n_int + b] = -s / F.wn[b];
+  if (sl == 0) F.p[F.n_int + b] = -s / (T)F.wn[b];
 }
 
 // returns |v_i| (valid in every lane of the node's group)
-template <typename T, int LPN>
-__device__ __forceinline__ double velocity_node(const Fields<T>& F, int64_t i, int sl) {
+template <typename T, typename TW, int LPN>
+__device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, int64_t i, int sl) {
   const int64_t n = F.n, os = (int64_t)F.nl * n;
   T gp[3] = {T(0), T(0), T(0)};
   for (int j = sl; j < F.nl; j += LPN) {
     const int64_t at = (int64_t)j * n + i;
     const T ps = F.p[F.sten[at]];
-    gp[0] += F.w[at] * ps;
-    gp[1] += F.w[os + at] * ps;
-    gp[2] += F.w[2 * os + at] * ps;
+    gp[0] += (T)F.w[at] * ps;
+    gp[1] += (T)F.w[os + at] * ps;
+    gp[2] += (T)F.w[2 * os + at] * ps;
   }
   double m2 = 0.0;
 #pragma unroll
@@ -133,8 +133,8 @@ __device__ __forceinline__ double velocity_node(const Fields<T>& F, int64_t i, i
   return sqrt(m2);
 }
 
-template <typename T>
-__device__ __forceinline__ T coupling_coef(const Fields<T>& F) {
+template <typename T, typename TW>
+__device__ __forceinline__ T coupling_coef(const Fields<T, TW>& F) {
   const double vm = *F.vmax;
   const double C = F.beta * (vm > F.v_ref ? vm : F.v_ref);
   return (T)(F.dtd * (C * C) * F.rho);
@@ -157,38 +157,38 @@ __device__ __forceinline__ void block_max_into(double mag, double* lds, double* 
 
 // ---------------------------------------------------------------- one launch per pass
 
-template <typename T, int LPN>
-__global__ __launch_bounds__(kBlock) void k_predictor(Fields<T> F) {
+template <typename T, typename TW, int LPN>
+__global__ __launch_bounds__(kBlock) void k_predictor(Fields<T, TW> F) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;  // whole LPN groups exit together
-  predictor_node<T, LPN>(F, i, (int)(g % LPN));
+  predictor_node<T, TW, LPN>(F, i, (int)(g % LPN));
 }
 
-template <typename T, int LPN>
-__global__ __launch_bounds__(kBlock) void k_pressure(Fields<T> F, const T* __restrict__ vsrc) {
+template <typename T, typename TW, int LPN>
+__global__ __launch_bounds__(kBlock) void k_pressure(Fields<T, TW> F, const T* __restrict__ vsrc) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_node<T, LPN>(F, vsrc, coupling_coef(F), i, (int)(g % LPN));
+  pressure_node<T, TW, LPN>(F, vsrc, coupling_coef(F), i, (int)(g % LPN));
 }
 
-template <typename T, int LPN>
-__global__ __launch_bounds__(kBlock) void k_neumann(Fields<T> F) {
+template <typename T, typename TW, int LPN>
+__global__ __launch_bounds__(kBlock) void k_neumann(Fields<T, TW> F) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g == 0) *F.vmax = 0.0;  // the pressure pass has consumed it; the velocity pass rebuilds it
   const int64_t b = g / LPN;
   if (b >= F.nb) return;
-  neumann_node<T, LPN>(F, b, (int)(g % LPN));
+  neumann_node<T, TW, LPN>(F, b, (int)(g % LPN));
 }
 
-template <typename T, int LPN>
-__global__ __launch_bounds__(kBlock) void k_velocity(Fields<T> F) {
+template <typename T, typename TW, int LPN>
+__global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F) {
   __shared__ double red[kBlock / kWave];
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   double mag = 0.0;
-  if (i < F.n_int) mag = velocity_node<T, LPN>(F, i, (int)(g % LPN));
+  if (i < F.n_int) mag = velocity_node<T, TW, LPN>(F, i, (int)(g % LPN));
   block_max_into(mag, red, F.vmax);
 }
 
@@ -202,25 +202,25 @@ __global__ void fill_zero(T* __restrict__ x, int64_t n) {
 // the chain of dependent gathers of one node: split each stencil 8 ways
 constexpr int64_t kFewNodes = 200000;
 
-template <typename T, int LPN>
-int run_launches(Fields<T>& F, int n_steps, int n_p, hipStream_t st) {
+template <typename T, typename TW, int LPN>
+int run_launches(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   for (int s = 0; s < n_steps; ++s) {
-    hipLaunchKernelGGL((k_predictor<T, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
+    hipLaunchKernelGGL((k_predictor<T, TW, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
     for (int it = 0; it < n_p; ++it) {
-      hipLaunchKernelGGL((k_pressure<T, LPN>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.vp : F.v));
-      hipLaunchKernelGGL((k_neumann<T, LPN>), dim3(gb), dim3(kBlock), 0, st, F);
-      hipLaunchKernelGGL((k_velocity<T, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
+      hipLaunchKernelGGL((k_pressure<T, TW, LPN>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.vp : F.v));
+      hipLaunchKernelGGL((k_neumann<T, TW, LPN>), dim3(gb), dim3(kBlock), 0, st, F);
+      hipLaunchKernelGGL((k_velocity<T, TW, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
     }
   }
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
 
-template <typename T>
-int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const T* w,
-        const int32_t* sn, const T* wn, T* v, T* p, double* vmax, int n_steps, void* ws, hipStream_t st) {
-  Fields<T> F;
+template <typename T, typename TW>
+int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* w,
+        const int32_t* sn, const TW* wn, T* v, T* p, double* vmax, int n_steps, void* ws, hipStream_t st) {
+  Fields<T, TW> F;
   F.n = n; F.n_int = n_int; F.nb = n - n_int; F.nl = nl;
   F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.v = v; F.p = p;
   F.vp = reinterpret_cast<T*>(ws);
@@ -235,11 +235,11 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   int lanes = prm->lanes;
   if (lanes == 0) lanes = n_int <= kFewNodes ? 8 : 2;
   switch (lanes) {
-    case 1: return run_launches<T, 1>(F, n_steps, prm->n_p, st);
-    case 2: return run_launches<T, 2>(F, n_steps, prm->n_p, st);
-    case 4: return run_launches<T, 4>(F, n_steps, prm->n_p, st);
-    case 8: return run_launches<T, 8>(F, n_steps, prm->n_p, st);
-    default: return run_launches<T, 16>(F, n_steps, prm->n_p, st);
+    case 1: return run_launches<T, TW, 1>(F, n_steps, prm->n_p, st);
+    case 2: return run_launches<T, TW, 2>(F, n_steps, prm->n_p, st);
+    case 4: return run_launches<T, TW, 4>(F, n_steps, prm->n_p, st);
+    case 8: return run_launches<T, TW, 8>(F, n_steps, prm->n_p, st);
+    default: return run_launches<T, TW, 16>(F, n_steps, prm->n_p, st);
   }
 }
 
@@ -259,7 +259,7 @@ extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, 
       prm->n_p < 1 || !(prm->dt > 0.0) || !(prm->rho > 0.0))
     return MPF_ERR_ARG;
   if (n > n_int && (!sn || !wn)) return MPF_ERR_ARG;
-  if (prm->precision != MPF_F64 && prm->precision != MPF_F32) return MPF_ERR_ARG;
+  if (prm->precision != MPF_F64 && prm->precision != MPF_F32 && prm->precision != MPF_MIXED) return MPF_ERR_ARG;
   if (prm->lanes != 0 && prm->lanes != 1 && prm->lanes != 2 && prm->lanes != 4 && prm->lanes != 8 &&
       prm->lanes != 16)
     return MPF_ERR_ARG;
@@ -267,8 +267,11 @@ extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, 
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);
   if (prm->precision == MPF_F64)
-    return run<double>(prm, n, n_int, nl, sten, (const double*)w, sn, (const double*)wn, (double*)v, (double*)p,
-                       vmax, n_steps, ws, st);
-  return run<float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (float*)v, (float*)p, vmax,
+    return run<double, double>(prm, n, n_int, nl, sten, (const double*)w, sn, (const double*)wn, (double*)v,
+                               (double*)p, vmax, n_steps, ws, st);
+  if (prm->precision == MPF_MIXED)
+    return run<double, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (double*)v,
+                              (double*)p, vmax, n_steps, ws, st);
+  return run<float, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (float*)v, (float*)p, vmax,
                     n_steps, ws, st);
 }

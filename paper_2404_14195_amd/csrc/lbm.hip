@@ -14,6 +14,8 @@
 // (Eq. interpolated_bounceback_mlbm), then collide (Eqs. macro_var, feq,
 // LBM_collision, force_lbm) and write the next post-collision state.  Weights
 // stream coalesced from [k][j][node].
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace mpf {
@@ -130,11 +132,11 @@ inline unsigned tiles_grid(int64_t n) {
 // is deliberately not unrolled and the weights use plain (cached) loads:
 // measured on the 71k-node cell, both unrolling and non-temporal weight loads
 // cost 30-60 % of the step time.
-template <typename T, int Q, bool COLLIDE>
+template <typename TW, typename T, int Q, bool COLLIDE>
 __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int, int nl,
                                                        const int32_t* __restrict__ sten,
-                                                   const T* __restrict__ W, const double* __restrict__ nrm,
-                                                   const T* __restrict__ src, T* __restrict__ dst, Prm<T> pr) {
+                                                       const TW* __restrict__ W, const double* __restrict__ nrm,
+                                                       const T* __restrict__ src, T* __restrict__ dst, Prm<T> pr) {
   using L = Lattice<Q>;
   constexpr int QP = Pad<Q>::QP;
   using V = typename Vec16<T>::type;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int,
       }
     }
 #pragma unroll
-    for (int k = 1; k < Q; ++k) acc[k] += W[(k - 1) * ks + at] * r[k];
+    for (int k = 1; k < Q; ++k) acc[k] += (T)W[(k - 1) * ks + at] * r[k];
   }
 #pragma unroll
   for (int k = 1; k < Q; ++k) part[wv][k - 1][lane] = acc[k];
@@ -237,6 +239,28 @@ __global__ __launch_bounds__(kBlock) void lbm_init(int64_t n, T* __restrict__ f,
   for (int k = Q; k < QP; ++k) f[i * QP + k] = T(0);
 }
 
+// Equilibrium populations of given macroscopic fields in physical units, the
+// inverse of lbm_moments: u_lb = v / vs, rho = 1 + 3 p / vs^2.
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void lbm_init_fields(int64_t n, const double* __restrict__ v,
+                                                          const double* __restrict__ p, double vs,
+                                                          T* __restrict__ f) {
+  using L = Lattice<Q>;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  constexpr int QP = Pad<Q>::QP;
+  const double u0 = v[i] / vs, u1 = v[n + i] / vs, u2 = v[2 * n + i] / vs;
+  const double drho = 3.0 * p[i] / (vs * vs), rho = 1.0 + drho;
+  const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double eu = L::ex[k] * u0 + L::ey[k] * u1 + L::ez[k] * u2;
+    f[i * QP + k] = (T)(lat_w<Q>(k) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
+  }
+#pragma unroll
+  for (int k = Q; k < QP; ++k) f[i * QP + k] = T(0);
+}
+
 template <typename T, int Q>
 __global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __restrict__ f, double vs,
                                                       double* __restrict__ v, double* __restrict__ p) {
@@ -259,8 +283,8 @@ __global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __rest
   if (p) p[i] = vs * vs * drho / 3.0;
 }
 
-template <typename T, int Q>
-int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const T* W,
+template <typename TW, typename T, int Q>
+int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W,
         const double* nrm, T* f, T* ft, int n_steps, hipStream_t st) {
   Prm<T> pr{(T)(1.0 / prm->tau_plus), (T)(1.0 / prm->tau_minus), (T)prm->g_lb[0], (T)prm->g_lb[1],
             (T)prm->g_lb[2]};
@@ -278,14 +302,29 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   const unsigned gt = tiles_grid(n);
   for (int s = 0; s < n_steps - 1; ++s) {
     T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<T, Q, true>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, nrm,
+    hipLaunchKernelGGL((lbm_step<TW, T, Q, true>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, nrm,
                        (const T*)cur, nxt, pr);
     cur = nxt;
   }
-  hipLaunchKernelGGL((lbm_step<T, Q, false>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, nrm,
+  hipLaunchKernelGGL((lbm_step<TW, T, Q, false>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, nrm,
                      (const T*)cur, f, pr);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
+}
+
+// Populations are double for MPF_F64 and MPF_MIXED, float for MPF_F32.
+template <int Q, typename F>
+int with_state(int precision, F&& fn) {
+  if (precision == MPF_F32) return fn(float{});
+  if (precision == MPF_F64 || precision == MPF_MIXED) return fn(double{});
+  return MPF_ERR_ARG;
+}
+
+template <typename F>
+int with_q(int q, F&& fn) {
+  if (q == 19) return fn(std::integral_constant<int, 19>{});
+  if (q == 15) return fn(std::integral_constant<int, 15>{});
+  return MPF_ERR_ARG;
 }
 
 }  // namespace
@@ -298,18 +337,32 @@ extern "C" int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, co
   hipStream_t st = as_stream(stream);
   const unsigned g = grid_for(n, kBlock);
   const double u0 = u_host[0], u1 = u_host[1], u2 = u_host[2];
-  if (prm->q == 19 && prm->precision == MPF_F64)
-    hipLaunchKernelGGL((lbm_init<double, 19>), dim3(g), dim3(kBlock), 0, st, n, (double*)f, rho, u0, u1, u2);
-  else if (prm->q == 19 && prm->precision == MPF_F32)
-    hipLaunchKernelGGL((lbm_init<float, 19>), dim3(g), dim3(kBlock), 0, st, n, (float*)f, rho, u0, u1, u2);
-  else if (prm->q == 15 && prm->precision == MPF_F64)
-    hipLaunchKernelGGL((lbm_init<double, 15>), dim3(g), dim3(kBlock), 0, st, n, (double*)f, rho, u0, u1, u2);
-  else if (prm->q == 15 && prm->precision == MPF_F32)
-    hipLaunchKernelGGL((lbm_init<float, 15>), dim3(g), dim3(kBlock), 0, st, n, (float*)f, rho, u0, u1, u2);
-  else
-    return MPF_ERR_ARG;
-  MPF_LAUNCH_CHECK();
-  return MPF_OK;
+  return with_q(prm->q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    return with_state<Q>(prm->precision, [&](auto t) {
+      using T = decltype(t);
+      hipLaunchKernelGGL((lbm_init<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (T*)f, rho, u0, u1, u2);
+      MPF_LAUNCH_CHECK();
+      return MPF_OK;
+    });
+  });
+}
+
+extern "C" int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const double* v, const double* p,
+                                   double vel_scale, void* f, void* stream) {
+  using namespace mpf;
+  if (!prm || !f || !v || !p || n < 1 || !(vel_scale > 0.0)) return MPF_ERR_ARG;
+  hipStream_t st = as_stream(stream);
+  const unsigned g = grid_for(n, kBlock);
+  return with_q(prm->q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    return with_state<Q>(prm->precision, [&](auto t) {
+      using T = decltype(t);
+      hipLaunchKernelGGL((lbm_init_fields<T, Q>), dim3(g), dim3(kBlock), 0, st, n, v, p, vel_scale, (T*)f);
+      MPF_LAUNCH_CHECK();
+      return MPF_OK;
+    });
+  });
 }
 
 extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
@@ -319,17 +372,20 @@ extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, 
     return MPF_ERR_ARG;
   if (n > n_int && !nrm) return MPF_ERR_ARG;
   if (!(prm->tau_plus > 0.5) || !(prm->tau_minus > 0.5)) return MPF_ERR_ARG;
+  if (prm->precision != MPF_F64 && prm->precision != MPF_F32 && prm->precision != MPF_MIXED) return MPF_ERR_ARG;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);
-  if (prm->q == 19 && prm->precision == MPF_F64)
-    return run<double, 19>(prm, n, n_int, nl, sten, (const double*)W, nrm, (double*)f, (double*)f_tmp, n_steps, st);
-  if (prm->q == 19 && prm->precision == MPF_F32)
-    return run<float, 19>(prm, n, n_int, nl, sten, (const float*)W, nrm, (float*)f, (float*)f_tmp, n_steps, st);
-  if (prm->q == 15 && prm->precision == MPF_F64)
-    return run<double, 15>(prm, n, n_int, nl, sten, (const double*)W, nrm, (double*)f, (double*)f_tmp, n_steps, st);
-  if (prm->q == 15 && prm->precision == MPF_F32)
-    return run<float, 15>(prm, n, n_int, nl, sten, (const float*)W, nrm, (float*)f, (float*)f_tmp, n_steps, st);
-  return MPF_ERR_ARG;
+  return with_q(prm->q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    if (prm->precision == MPF_F64)
+      return run<double, double, Q>(prm, n, n_int, nl, sten, (const double*)W, nrm, (double*)f, (double*)f_tmp,
+                                    n_steps, st);
+    if (prm->precision == MPF_MIXED)
+      return run<float, double, Q>(prm, n, n_int, nl, sten, (const float*)W, nrm, (double*)f, (double*)f_tmp,
+                                   n_steps, st);
+    return run<float, float, Q>(prm, n, n_int, nl, sten, (const float*)W, nrm, (float*)f, (float*)f_tmp, n_steps,
+                                st);
+  });
 }
 
 extern "C" int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double vel_scale, double* v,
@@ -338,16 +394,13 @@ extern "C" int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void*
   if (!prm || !f || !v || n < 1) return MPF_ERR_ARG;
   hipStream_t st = as_stream(stream);
   const unsigned g = grid_for(n, kBlock);
-  if (prm->q == 19 && prm->precision == MPF_F64)
-    hipLaunchKernelGGL((lbm_moments<double, 19>), dim3(g), dim3(kBlock), 0, st, n, (const double*)f, vel_scale, v, p);
-  else if (prm->q == 19 && prm->precision == MPF_F32)
-    hipLaunchKernelGGL((lbm_moments<float, 19>), dim3(g), dim3(kBlock), 0, st, n, (const float*)f, vel_scale, v, p);
-  else if (prm->q == 15 && prm->precision == MPF_F64)
-    hipLaunchKernelGGL((lbm_moments<double, 15>), dim3(g), dim3(kBlock), 0, st, n, (const double*)f, vel_scale, v, p);
-  else if (prm->q == 15 && prm->precision == MPF_F32)
-    hipLaunchKernelGGL((lbm_moments<float, 15>), dim3(g), dim3(kBlock), 0, st, n, (const float*)f, vel_scale, v, p);
-  else
-    return MPF_ERR_ARG;
-  MPF_LAUNCH_CHECK();
-  return MPF_OK;
+  return with_q(prm->q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    return with_state<Q>(prm->precision, [&](auto t) {
+      using T = decltype(t);
+      hipLaunchKernelGGL((lbm_moments<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, vel_scale, v, p);
+      MPF_LAUNCH_CHECK();
+      return MPF_OK;
+    });
+  });
 }

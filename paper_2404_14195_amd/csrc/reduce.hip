@@ -108,12 +108,12 @@ extern "C" int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const d
                                int precision, int64_t n_all, double* q_out, void* ws, size_t ws_bytes,
                                void* stream) {
   if (!q_out || ns < 0 || n_all < 1 || nl < 1 || (ns > 0 && (!s_idx || !s_w || !vx))) return MPF_ERR_ARG;
-  if (precision != MPF_F64 && precision != MPF_F32) return MPF_ERR_ARG;
+  if (precision != MPF_F64 && precision != MPF_F32 && precision != MPF_MIXED) return MPF_ERR_ARG;
   if (!ws || ws_bytes < mpf_reduce_workspace(ns)) return MPF_ERR_WORKSPACE;
   hipStream_t st = as_stream(stream);
   double* part = reinterpret_cast<double*>(ws);
   const unsigned g = grid_for(ns, kRBlock);
-  if (precision == MPF_F64)
+  if (precision != MPF_F32)
     hipLaunchKernelGGL(flux_partial<double>, dim3(g), dim3(kRBlock), 0, st, ns, nl, s_idx, s_w, (const double*)vx,
                        part);
   else
@@ -129,7 +129,7 @@ extern "C" int mpf_drag(int64_t n, const void* v, const void* p, int precision, 
                         const int32_t* sb, const double* wg, const double* nrm, double rho, double nu, double dA,
                         double* F_out, void* ws, size_t ws_bytes, void* stream) {
   if (!v || !p || !F_out || n < 1 || nb < 0 || nl < 1 || (nb > 0 && (!sb || !wg || !nrm))) return MPF_ERR_ARG;
-  if (precision != MPF_F64 && precision != MPF_F32) return MPF_ERR_ARG;
+  if (precision != MPF_F64 && precision != MPF_F32 && precision != MPF_MIXED) return MPF_ERR_ARG;
   if (!ws || ws_bytes < mpf_reduce_workspace(n > nb ? n : nb)) return MPF_ERR_WORKSPACE;
   hipStream_t st = as_stream(stream);
   double* part = reinterpret_cast<double*>(ws);
@@ -138,7 +138,7 @@ extern "C" int mpf_drag(int64_t n, const void* v, const void* p, int precision, 
   double* pmean = part + 3 * cap;
   // node mean of p
   const unsigned gn = grid_for(n, kRBlock);
-  if (precision == MPF_F64)
+  if (precision != MPF_F32)
     hipLaunchKernelGGL(sum_partial<double>, dim3(gn), dim3(kRBlock), 0, st, n, (const double*)p, part);
   else
     hipLaunchKernelGGL(sum_partial<float>, dim3(gn), dim3(kRBlock), 0, st, n, (const float*)p, part);
@@ -146,7 +146,7 @@ extern "C" int mpf_drag(int64_t n, const void* v, const void* p, int precision, 
                      pmean);
   // tractions
   const unsigned gb = grid_for(nb, kRBlock);
-  if (precision == MPF_F64)
+  if (precision != MPF_F32)
     hipLaunchKernelGGL(drag_partial<double>, dim3(gb), dim3(kRBlock), 0, st, n, (const double*)v, (const double*)p,
                        nb, nl, sb, wg, nrm, (const double*)pmean, rho * nu, part, (int64_t)gb);
   else

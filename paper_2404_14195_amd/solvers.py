@@ -13,9 +13,10 @@ import torch
 import nodecloud
 
 from . import api
-from ._lib import MPF_F32, MPF_F64, AcmParams, LbmParams
+from ._lib import MPF_F32, MPF_F64, MPF_MIXED, AcmParams, LbmParams
 
-_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32}
+# state element type per precision (MPF_MIXED: FP32 weights, FP64 state)
+_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64}
 
 
 class Discretization:
@@ -57,9 +58,9 @@ class ACMSolver:
                              precision=precision, lanes=lanes)
         self.g = tuple(g)
         w64, w32, info = api.rbffd_weights(disc.pos, disc.sten, [("dx",), ("dy",), ("dz",), ("lap",)],
-                                           want64=True, want32=precision == MPF_F32)
+                                           want64=True, want32=precision != MPF_F64)
         wn64, wn32, infon = api.rbffd_weights(disc.pos, disc.sn, [("dn",)], rowvec=disc.nrm, want64=True,
-                                              want32=precision == MPF_F32) if disc.nb else (None, None, None)
+                                              want32=precision != MPF_F64) if disc.nb else (None, None, None)
         self.info = info
         self.w64 = w64
         self.w = w64 if precision == MPF_F64 else w32
@@ -146,7 +147,7 @@ class MLBMSolver:
         if W is None:
             ops = [("shift", tuple(-u["dx"] * x for x in e[k])) for k in range(1, q)]
             w64, w32, self.info = api.rbffd_weights(disc.pos, disc.sten, ops, want64=precision == MPF_F64,
-                                                    want32=precision == MPF_F32)
+                                                    want32=precision != MPF_F64)
             W = w64 if precision == MPF_F64 else w32
         self.W = W
         dtp = _DT[precision]
@@ -157,6 +158,12 @@ class MLBMSolver:
         self._v = torch.empty((3, disc.n), dtype=torch.float64, device=disc.device)
         self._p = torch.empty(disc.n, dtype=torch.float64, device=disc.device)
         self._wg = None
+
+    def set_fields(self, v, p):
+        """Start from the equilibrium of fields v [3][n], p [n] (device double,
+        physical units): a warm start."""
+        api.lbm_init_fields(self.prm, self.f, v, p, self.units["vel_scale"])
+        self.steps = 0
 
     def run(self, n_steps: int):
         api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.d.nrm, self.f, self.f_tmp, n_steps)

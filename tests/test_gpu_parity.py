@@ -143,6 +143,19 @@ def test_acm_fp32_error_vs_fp64(api, disc_small):
     assert k32 == pytest.approx(q_o, rel=1e-4)
 
 
+def test_acm_mixed_error_vs_fp64(api, disc_small):
+    """FP32 weights with FP64 state and arithmetic: only the weights are
+    rounded, so the permeability after 500 steps stays within 1e-6 of the
+    FP64 oracle."""
+    g, o = acm_pair(api, disc_small, 2, 500)
+    assert g.v.dtype == torch.float64 and g.w.dtype == torch.float32
+    pp = disc_small.plan
+    q_o = O.flux(pp.idx, O.plane_weights(disc_small.cloud.pos, pp.idx, pp.shift), o.v[:, 0], disc_small.n_all)
+    k = g.permeability()
+    print(f"[acm mixed] k={k:.12e} k64={q_o:.12e} rel={abs(k / q_o - 1):.3e}", flush=True)
+    assert k == pytest.approx(q_o, rel=1e-6)
+
+
 def test_acm_zero_steps_and_rest(api, disc_small):
     from paper_2404_14195_amd.solvers import ACMSolver
     g = ACMSolver(disc_small, g=(0.0, 0.0, 0.0))
@@ -241,6 +254,47 @@ def test_lbm_fp32_shifted_error(api, disc_small):
     k_g = g.permeability()
     print(f"[lbm fp32] k32={k_g:.9e} k64={k_o:.9e} rel={abs(k_g / k_o - 1):.3e}", flush=True)
     assert k_g == pytest.approx(k_o, rel=1e-4)
+
+
+def test_lbm_mixed_error(api, disc_small):
+    """FP32 interpolation weights, FP64 populations: 200 steps within 1e-6
+    of the FP64 oracle's permeability."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    c = disc_small.cloud
+    g = MLBMSolver(disc_small, q=19, precision=2)
+    assert g.f.dtype == torch.float64 and g.W.dtype == torch.float32
+    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=19, h_min=c.h_min)
+    g.run(200)
+    o.run(200)
+    v_o, _ = o.macros()
+    pp = disc_small.plan
+    k_o = O.flux(pp.idx, O.plane_weights(c.pos, pp.idx, pp.shift), v_o[:, 0], disc_small.n_all)
+    k_g = g.permeability()
+    print(f"[lbm mixed] k={k_g:.12e} k64={k_o:.12e} rel={abs(k_g / k_o - 1):.3e}", flush=True)
+    assert k_g == pytest.approx(k_o, rel=1e-6)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_lbm_init_from_fields(api, disc_small, precision):
+    """Equilibrium start from given (v, p): the populations are the oracle's
+    equilibrium of rho = 1 + 3 p / U^2, u = v / U, and the moments give the
+    fields back."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    c = disc_small.cloud
+    g = MLBMSolver(disc_small, q=19, precision=precision)
+    U = g.units["vel_scale"]
+    rng = np.random.default_rng(11)
+    v = 0.01 * U * rng.normal(size=(3, c.n))
+    p = 0.003 * U * U * rng.normal(size=c.n)
+    g.set_fields(dev(v, torch.float64), dev(p, torch.float64))
+    rho, u = 1.0 + 3.0 * p / U ** 2, v.T / U
+    f_o = np.concatenate([O.equilibrium(19, 1, rho[i], u[i]) for i in range(c.n)])
+    tol = 1e-14 if precision != 1 else 1e-7
+    assert np.abs(g.populations() - f_o).max() <= tol * np.abs(f_o).max()
+    vg, pg = g.macros()
+    tol = 1e-12 if precision != 1 else 1e-4
+    assert np.abs(vg.cpu().numpy() - v).max() <= tol * np.abs(v).max()
+    assert np.abs(pg.cpu().numpy() - p).max() <= tol * np.abs(p).max()
 
 
 # ----------------------------------------------------------------- reductions

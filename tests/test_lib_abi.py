@@ -83,3 +83,26 @@ def test_host_argument_checks(lib):
     assert lib.mpf_drag(10, fake, fake, 0, 2, 30, fake, fake, fake, 1.0, 1.0, 0.1, fake, fake, 8, None) == -4
     assert lib.mpf_acm_workspace(1000, 0) >= 3 * 1000 * 8
     assert lib.mpf_acm_workspace(1000, 1) >= 3 * 1000 * 4
+
+
+def test_mlp_host_queries_and_checks(lib):
+    from paper_2404_14195_amd._lib import MlpDesc
+    d = MlpDesc(5, 128, 4, 4)
+    assert lib.mpf_mlp_param_count(ctypes.byref(d)) == 34308
+    assert lib.mpf_mlp_packed_count(ctypes.byref(d)) > 34308 - 128 * 3  # padded copies of W and W^T
+    bad = MlpDesc(5, 64, 4, 4)
+    assert lib.mpf_mlp_param_count(ctypes.byref(bad)) == -1
+    assert lib.mpf_mlp_workspace(ctypes.byref(bad), 100, 1) == 0
+    assert lib.mpf_mlp_workspace(ctypes.byref(d), 0, 1) == 0
+    # training needs more than inference; both grow with the batch
+    w_inf = lib.mpf_mlp_workspace(ctypes.byref(d), 1000, 0)
+    w_tr = lib.mpf_mlp_workspace(ctypes.byref(d), 1000, 1)
+    assert 0 < w_inf < w_tr < lib.mpf_mlp_workspace(ctypes.byref(d), 100000, 1)
+    fake = ctypes.c_void_p(256)
+    assert lib.mpf_mlp_forward(ctypes.byref(bad), fake, fake, fake, None, fake, 10, 0, fake, 1 << 30, None) == -3
+    assert lib.mpf_mlp_forward(ctypes.byref(d), fake, fake, fake, None, fake, 10, 1, fake, 64, None) == -4
+    assert lib.mpf_mlp_forward(ctypes.byref(d), None, fake, fake, None, fake, 10, 0, fake, 1 << 30, None) == -1
+    assert lib.mpf_adam_step(10, fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.mpf_adam_step(10, fake, fake, fake, fake, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -1
+    assert lib.mpf_gemm_bf16(4, 4, 40, fake, 40, fake, 40, fake, 4, None) == -1  # K not a multiple of 32
+    assert lib.mpf_mlp_to_state(10, 11, fake, 1.0, 1.0, 0, fake, fake, None, fake, 1 << 20, None) == -1
