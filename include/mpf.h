@@ -145,7 +145,8 @@ int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, i
  * tune:  host pointer to the tile shape, or NULL for the shape that
  *        mpf_weights_autotune last chose for (device, nl, n_ops, solve), or a
  *        default (4 waves per block, 1 row per wave).
- * The geometry table is copied into ws with hipMemcpyAsync on the stream. */
+ * The geometry table is copied into ws on the stream, and the call waits for
+ * that copy (one stream synchronisation) before it launches the solve. */
 #define MPF_SOLVE_FP64 0
 #define MPF_SOLVE_FP32_IR 1
 

@@ -8,7 +8,8 @@ reductions):
   radius r centred in it (paper Sec. 2.4), h-refined towards the grain with a
   linear target spacing h(dist) = min(h0 + slope*dist, hmax);
 * stencils: the N_L nearest nodes under the minimum-image convention, the node
-  itself first (Sec. 2.1);
+  itself first (Sec. 2.1); surface nodes take their N_L - 1 nearest interior
+  nodes instead (solver_stencils);
 * the plane-sample plan used for the permeability (Eq. k_definition): midpoint
   samples on the five planes x in {0, .2, .4, .6, .8}, each fluid sample with
   its own N_L-nearest stencil and the offset from its nearest node;
@@ -214,6 +215,24 @@ def neumann_stencils(cloud: Cloud, nl: int) -> np.ndarray:
     _, idx = tree.query(np.asarray(cloud.pos[cloud.n_int:]) % 1.0, k=nl - 1)
     idx = np.asarray(idx, dtype=np.int64).reshape(cloud.n_bnd, nl - 1)
     return np.ascontiguousarray(np.concatenate([own, idx], 1).astype(np.int32))
+
+
+def solver_stencils(cloud: Cloud, nl: int) -> np.ndarray:
+    """Stencils of every node for the solvers: the nl nearest nodes for
+    interior nodes, and for surface nodes the node itself followed by its nl-1
+    nearest interior nodes (the stencils of neumann_stencils).
+
+    On the sphere x^2 + y^2 + z^2 is constant, so a surface node whose nearest
+    neighbours are mostly other surface nodes (typically two thirds of them)
+    gets a nearly singular quadratic block in its saddle system: its
+    interpolation weights reach sum |w| ~ 40 on some clouds, and the MLBM
+    step, which applies them every step, grows without bound from there.
+    Interior neighbours keep sum |w| of those rows near that of interior
+    nodes (<= ~5)."""
+    sten = stencils(cloud.pos, nl)
+    if cloud.n_bnd:
+        sten[cloud.n_int:] = neumann_stencils(cloud, nl)
+    return sten
 
 
 @dataclass

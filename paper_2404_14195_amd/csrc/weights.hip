@@ -518,9 +518,13 @@ extern "C" size_t mpf_weights_workspace(void) { return kWorkspaceBytes; }
 
 
 namespace {
+// The table lives in the caller's stack frame (pageable memory), and an
+// asynchronous copy from pageable memory may read its source after the call
+// has returned; wait for the copy so the frame outlives it.
 int upload_table(const BatchArg& B, void* ws, hipStream_t st) {
   MPF_HIP(hipMemcpyAsync(reinterpret_cast<char*>(ws) + kTableOffset, B.g, sizeof(GeomArg) * B.n_geoms,
                          hipMemcpyHostToDevice, st));
+  MPF_HIP(hipStreamSynchronize(st));
   return MPF_OK;
 }
 }  // namespace

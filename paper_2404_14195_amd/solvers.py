@@ -30,7 +30,7 @@ class Discretization:
         self.device = torch.device(device)
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)
         self.pos = t(cloud.pos.T, torch.float64)
-        self.sten_host = nodecloud.stencils(cloud.pos, nl)
+        self.sten_host = nodecloud.solver_stencils(cloud, nl)
         self.sten = t(self.sten_host.T, torch.int32)
         self.nrm = t(cloud.nrm.T, torch.float64) if self.nb else torch.zeros((3, 0), dtype=torch.float64,
                                                                                device=self.device)

@@ -1,0 +1,261 @@
+"""Learned warm start: a network trained on the solvers' own steady fields
+predicts the steady velocity and pressure of a new cell, and the explicit
+iteration starts from that prediction instead of rest.
+
+This is an addition to the paper's method.  The cold-started solver remains
+the reference: a warm-started run converges to the same steady state (the
+steady state does not depend on the initial condition), so the prediction
+only moves the starting point, and its error is measured against the cold
+run's k.
+
+Split of the prediction:
+* the field shape comes from the MLP of ``mpf_mlp_*``: per-node features
+  (offset from the grain centre, signed distance to the surface, porosity)
+  -> (v / U, (p - <p>) / P);
+* the magnitudes U = k(r) |g| / nu and P (the spread of p) of a cell come from
+  a monotone cubic interpolation of log U and log P over the training radii,
+  so every target the network sees is O(1) whatever the porosity.
+
+Everything on the device runs in libmpf kernels; this module only holds the
+parameters, shuffles sample indices and moves a few scalars.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import api
+from ._lib import MPF_F32, MPF_MIXED
+
+
+def _init_params(seed: int) -> np.ndarray:
+    """U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for every weight and bias."""
+    rng = np.random.default_rng(seed)
+    sizes = (5, 128, 128, 128, 4)
+    parts = []
+    for i, o in zip(sizes[:-1], sizes[1:]):
+        a = 1.0 / math.sqrt(i)
+        parts += [rng.uniform(-a, a, o * i), rng.uniform(-a, a, o)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class _Pchip:
+    """Monotone piecewise-cubic interpolation (Fritsch-Carlson slopes) of
+    y(x) over sorted knots; linear extrapolation beyond the end knots."""
+
+    def __init__(self, x, y):
+        o = np.argsort(x)
+        self.x = np.asarray(x, np.float64)[o]
+        self.y = np.asarray(y, np.float64)[o]
+        h = np.diff(self.x)
+        d = np.diff(self.y) / h
+        m = np.zeros_like(self.y)
+        if len(self.x) == 2:
+            m[:] = d[0]
+        else:
+            for i in range(1, len(self.x) - 1):
+                if d[i - 1] * d[i] > 0:
+                    w1, w2 = 2 * h[i] + h[i - 1], h[i] + 2 * h[i - 1]
+                    m[i] = (w1 + w2) / (w1 / d[i - 1] + w2 / d[i])
+            m[0], m[-1] = d[0], d[-1]
+        self.m = m
+
+    def __call__(self, x):
+        x = float(x)
+        xs, ys, ms = self.x, self.y, self.m
+        if x <= xs[0]:
+            return ys[0] + ms[0] * (x - xs[0])
+        if x >= xs[-1]:
+            return ys[-1] + ms[-1] * (x - xs[-1])
+        i = int(np.searchsorted(xs, x)) - 1
+        h = xs[i + 1] - xs[i]
+        t = (x - xs[i]) / h
+        h00, h10 = 2 * t ** 3 - 3 * t ** 2 + 1, t ** 3 - 2 * t ** 2 + t
+        h01, h11 = -2 * t ** 3 + 3 * t ** 2, t ** 3 - t ** 2
+        return h00 * ys[i] + h10 * h * ms[i] + h01 * ys[i + 1] + h11 * h * ms[i + 1]
+
+
+def steady_fields(solver, check=500, tol=1e-6, max_steps=1_000_000, log=None, log_every=20.0):
+    """Run a solver until k changes by less than tol (relative) over two
+    successive checks; returns (k, steps).  Raises FloatingPointError if k
+    stops being finite and RuntimeError if max_steps pass first."""
+    ks = []
+    t_log = time.perf_counter()
+    while solver.steps < max_steps:
+        solver.run(check)
+        ks.append(solver.permeability())
+        if not math.isfinite(ks[-1]):
+            raise FloatingPointError(f"k is {ks[-1]} after {solver.steps} steps")
+        if len(ks) > 2 and all(abs(ks[-i] - ks[-i - 1]) <= tol * abs(ks[-1]) for i in (1, 2)):
+            return ks[-1], solver.steps
+        if log and time.perf_counter() - t_log > log_every:
+            log(f"steady: {solver.steps} steps, k = {ks[-1]:.8e}")
+            t_log = time.perf_counter()
+    raise RuntimeError(f"k not steady after {solver.steps} steps (last {ks[-3:]})")
+
+
+class WarmStart:
+    """The network, its optimiser state and the training set on the device."""
+
+    def __init__(self, seed: int = 0, device="cuda"):
+        self.device = torch.device(device)
+        self.master = torch.as_tensor(_init_params(seed), device=self.device)
+        self.packed = torch.empty(api.mlp_packed_count(), dtype=torch.bfloat16, device=self.device)
+        api.mlp_pack(self.master, self.packed)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grad = torch.empty_like(self.master)
+        self.step = 0
+        self._x, self._t = [], []
+        self.radii, self.logU, self.logP = [], [], []
+        self.X = self.T = None
+
+    # ------------------------------------------------------------ data
+    def add_cell(self, disc, v, p, k, g_abs=1.0, nu=1.0):
+        """Add the steady state (v [3][n], p [n], device double, physical
+        units) of one cell with permeability k as training samples."""
+        c = disc.cloud
+        U = k * g_abs / nu
+        pc = p.double().cpu().numpy()
+        pc = pc - pc.mean()
+        P = float(np.sqrt((pc * pc).mean()))
+        vh = v.double().cpu().numpy()
+        t = np.empty((c.n, 4), dtype=np.float32)
+        t[:, :3] = vh.T / U
+        t[c.n_int:, :3] = 0.0  # no slip on the grain, as the state mapping imposes
+        t[:, 3] = pc / P
+        self._x.append(api.mlp_features(disc.pos, c.r, disc.phi))
+        self._t.append(torch.as_tensor(t, device=self.device))
+        self.radii.append(c.r)
+        self.logU.append(math.log(U))
+        self.logP.append(math.log(P))
+        self.X = self.T = None
+
+    def scales(self, r):
+        """(U, P) of a cell of radius r, interpolated over the training cells."""
+        return math.exp(_Pchip(self.radii, self.logU)(r)), math.exp(_Pchip(self.radii, self.logP)(r))
+
+    @property
+    def n_samples(self) -> int:
+        return sum(x.shape[0] for x in self._x)
+
+    # ------------------------------------------------------------ training
+    def fit(self, epochs: int, batch: int = 8192, lr: float = 2e-3, lr_end: float = 1e-4, seed: int = 0,
+            log=None):
+        """Adam over shuffled minibatches, learning rate decayed
+        geometrically from lr to lr_end.  Returns the mean loss per epoch (one
+        host read per epoch)."""
+        if self.X is None:
+            self.X = torch.cat(self._x).contiguous()
+            self.T = torch.cat(self._t).contiguous()
+        N = self.X.shape[0]
+        ws = api.mlp_workspace(batch, True, self.device)
+        rws = api.reduce_workspace(4 * batch, self.device)
+        y = torch.empty((batch, 4), dtype=torch.float32, device=self.device)
+        dy = torch.empty_like(y)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        acc = torch.zeros(1, dtype=torch.float64, device=self.device)
+        gen = torch.Generator().manual_seed(seed)
+        per_epoch = max(1, N // batch)
+        total = epochs * per_epoch
+
+        def shuffled():  # host permutation, uploaded from pinned memory
+            return torch.randperm(N, generator=gen)[:per_epoch * batch].pin_memory().to(self.device,
+                                                                                       non_blocking=True)
+
+        hist = []
+        t0 = time.perf_counter()
+        perm = shuffled()
+        for ep in range(epochs):
+            acc.zero_()
+            for b in range(per_epoch):
+                self.step += 1
+                frac = (ep * per_epoch + b) / max(1, total - 1)
+                rate = lr * (lr_end / lr) ** frac
+                rows = perm[b * batch:(b + 1) * batch]
+                api.mlp_forward(self.master, self.packed, self.X, y, ws, rows=rows, train=True)
+                api.mlp_mse(y, self.T, dy, loss, rws, rows=rows)
+                api.mlp_backward(self.packed, dy, self.grad, ws)
+                api.adam_step(self.master, self.grad, self.m, self.v, self.step, rate)
+                api.mlp_pack(self.master, self.packed)
+                acc.add_(loss)
+            # the next permutation is drawn on the host while the device works
+            nxt = shuffled() if ep + 1 < epochs else None
+            hist.append(acc.item() / per_epoch)
+            perm = nxt
+            if log:
+                log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f}s)")
+        return hist
+
+    # ------------------------------------------------------------ inference
+    def predict(self, disc, ws=None):
+        """Network outputs y [n][4] for the nodes of a cell."""
+        c = disc.cloud
+        x = api.mlp_features(disc.pos, c.r, disc.phi)
+        y = torch.empty((c.n, 4), dtype=torch.float32, device=self.device)
+        if ws is None:
+            ws = api.mlp_workspace(c.n, False, self.device)
+        api.mlp_forward(self.master, self.packed, x, y, ws)
+        return y
+
+    def state(self, disc, v, p, vmax=None):
+        """Predicted state of a cell into v [3][n], p [n] (and max |v|).
+
+        The network gives the shape of the field and the interpolation over
+        the training radii its magnitude; the velocity is then rescaled so that
+        its flux through the permeability planes equals U = k(r) |g| / nu
+        exactly.  The flux is the slowest-decaying part of the iteration's
+        error, so it is the part worth pinning to the best estimate."""
+        U, P = self.scales(disc.cloud.r)
+        y = self.predict(disc)
+        api.mlp_to_state(y, disc.n_int, U, P, v, p, vmax, disc.red_ws)
+        q = float(api.flux_planes(disc.s_idx, disc.s_w, v[0], disc.n_all, ws=disc.red_ws).item())
+        if q > 0.0 and math.isfinite(q):
+            api.mlp_to_state(y, disc.n_int, U * U / q, P, v, p, vmax, disc.red_ws)
+
+    def load_acm(self, solver):
+        """Warm-start an ACMSolver in place (v, p and the running max |v|)."""
+        self.state(solver.d, solver.v, solver.p, solver.vmax)
+        solver.steps = 0
+
+    def load_mlbm(self, solver):
+        """Warm-start an MLBMSolver: equilibrium populations of the predicted
+        fields."""
+        d = solver.d
+        v = torch.empty((3, d.n), dtype=torch.float64, device=self.device)
+        p = torch.empty(d.n, dtype=torch.float64, device=self.device)
+        self.state(d, v, p)
+        solver.set_fields(v, p)
+
+    # ------------------------------------------------------------ persistence
+    def state_dict(self):
+        return {"master": self.master.cpu().numpy(), "radii": np.array(self.radii), "logU": np.array(self.logU),
+                "logP": np.array(self.logP)}
+
+    def load_state_dict(self, sd):
+        self.master.copy_(torch.as_tensor(np.asarray(sd["master"], np.float32)))
+        api.mlp_pack(self.master, self.packed)
+        self.radii, self.logU, self.logP = list(sd["radii"]), list(sd["logU"]), list(sd["logP"])
+
+
+def training_radii(n: int, seed: int = 5, lo: float = 0.15, hi: float = 0.48, held_out=(0.18, 0.3, 0.33, 0.47),
+                   gap: float = 0.01):
+    """n radii in [lo, hi], one uniform draw in each of n equal strata
+    (seeded), none within gap of a held-out radius.  The upper end stays
+    below 1/2, where neighbouring grains of the simple-cubic array touch."""
+    rng = np.random.default_rng(seed)
+    w = (hi - lo) / n
+    out = []
+    for i in range(n):
+        while True:
+            r = float(lo + (i + rng.uniform()) * w)
+            if all(abs(r - h) > gap for h in held_out):
+                break
+        out.append(r)
+    return out
+
+
+__all__ = ["WarmStart", "steady_fields", "training_radii", "MPF_F32", "MPF_MIXED"]

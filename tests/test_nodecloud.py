@@ -67,3 +67,27 @@ def test_plane_plan(small_cloud):
     d = nc.min_image(pp.pts[:, None, :] - small_cloud.pos[pp.idx])
     dist = np.sqrt((d * d).sum(-1))
     assert (np.diff(dist, axis=1) >= -1e-15).all()
+
+
+def test_solver_stencils_keep_surface_rows_well_conditioned():
+    """Surface nodes take their nearest interior nodes: on a cloud where the
+    plain nearest-node stencil of one surface node is two thirds co-spherical
+    and its MLBM shift weights reach sum |w| ~ 40, the solver stencil keeps
+    every shift row below 8."""
+    import oracle as O
+    from paper_2404_14195_amd.solvers import lattice_vectors, lbm_units
+    c = nc.sphere_cloud(0.39746601474643417, 0.008, 0.16, 0.04, seed=105)
+    S = nc.solver_stencils(c, 30)
+    P = nc.stencils(c.pos, 30)
+    assert np.array_equal(S[:c.n_int], P[:c.n_int])
+    b = np.arange(c.n_int, c.n)
+    assert np.array_equal(S[c.n_int:, 0], b) and (S[c.n_int:, 1:] < c.n_int).all()
+    u = lbm_units(c.h_min, 1.0, 1.0, (1, 0, 0), 0.25)
+    e = lattice_vectors(19)
+    ops = [("shift", tuple(-u["dx"] * x for x in e[k])) for k in range(1, 19)]
+    node = 108720  # the worst surface row of this cloud under plain stencils
+    assert node >= c.n_int and (P[node] >= c.n_int).sum() >= 20
+    W_plain, _ = O.weights(c.pos, P[node:node + 1], ops)
+    W_solver, _ = O.weights(c.pos, S[node:node + 1], ops)
+    assert np.abs(W_plain).sum(-1).max() > 30
+    assert np.abs(W_solver).sum(-1).max() < 8
