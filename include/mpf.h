@@ -350,6 +350,23 @@ int mpf_mlp_features(int64_t n, const double* pos, double r, double phi, float* 
  * mpf_reduce_workspace(n) bytes. */
 int mpf_mlp_to_state(int64_t n, int64_t n_int, const float* y, double U, double P, int precision, void* v, void* p,
                      double* vmax, void* ws, size_t ws_bytes, void* stream);
+/* n_batches Adam steps on consecutive minibatches, all launched from one host
+ * call: batch i uses rows[i B .. (i+1) B) of x and t, Adam step number
+ * step0 + i + 1 and learning rate lr0 lr_ratio^i; each step is forward (train),
+ * MSE, backward, Adam and pack, exactly as the separate calls do them.
+ * loss_sum (dev double[1]) receives the sum of the n_batches losses.  m, v,
+ * grad dev float [param_count]; rows dev int64 [n_batches B]; ws:
+ * mpf_mlp_train_workspace(B) bytes. */
+size_t mpf_mlp_train_workspace(const mpf_mlp_desc* d, int64_t B);
+int mpf_mlp_train(const mpf_mlp_desc* d, float* master, void* packed, float* m, float* v, float* grad, const float* x,
+                  const float* t, const int64_t* rows, int64_t n_batches, int64_t B, int step0, float lr0,
+                  float lr_ratio, float b1, float b2, float eps, double* loss_sum, void* ws, size_t ws_bytes,
+                  void* stream);
+/* rows[i] = pi(i) for i < count, pi a permutation of [0, n) fixed by seed
+ * (a Feistel network with cycle walking, evaluated pointwise): the minibatch
+ * order of an epoch without a host-side shuffle.  rows dev int64 [count];
+ * count <= n. */
+int mpf_shuffle_rows(int64_t n, int64_t count, uint64_t seed, int64_t* rows, void* stream);
 /* The library's BF16 product on its own: C[m][n] = sum_k A[m][k] Bt[n][k]
  * with FP32 accumulation.  A dev BF16 [M][lda], Bt dev BF16 [N][ldb] (16-byte
  * aligned, lda and ldb multiples of 8), C dev float [M][ldc]; K a multiple of

@@ -113,6 +113,10 @@ def _load():
         "mpf_mlp_features": (i32, [i64, vp, dbl, dbl, vp, vp]),
         "mpf_mlp_to_state": (i32, [i64, i64, vp, dbl, dbl, i32, vp, vp, vp, vp, sz, vp]),
         "mpf_gemm_bf16": (i32, [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp]),
+        "mpf_mlp_train_workspace": (sz, [vp, i64]),
+        "mpf_shuffle_rows": (i32, [i64, i64, ctypes.c_uint64, vp, vp]),
+        "mpf_mlp_train": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i32, flt, flt, flt, flt, flt, vp, vp,
+                                sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -137,7 +141,8 @@ EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace
             "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_moments", "mpf_reduce_workspace",
             "mpf_flux_planes", "mpf_drag", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
             "mpf_mlp_pack", "mpf_mlp_forward", "mpf_mlp_backward", "mpf_mlp_mse", "mpf_adam_step",
-            "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16"]
+            "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16", "mpf_mlp_train_workspace", "mpf_mlp_train",
+            "mpf_shuffle_rows"]
 
 
 def check(rc: int, what: str):

@@ -326,3 +326,37 @@ def gemm_bf16(A, Bt, C=None, K=None):
     _need(C, torch.float32, name="C")
     check(lib().mpf_gemm_bf16(M, N, K, _p(A), lda, _p(Bt), ldb, _p(C), C.shape[1], _stream()), "mpf_gemm_bf16")
     return C
+
+
+def mlp_train_workspace(batch: int, device="cuda") -> torch.Tensor:
+    nbytes = lib().mpf_mlp_train_workspace(ctypes.byref(MLP_DESC), int(batch))
+    if nbytes == 0:
+        raise ValueError(f"unsupported MLP batch {batch}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def mlp_train(master, packed, m, v, grad, x, t, rows, batch: int, step0: int, lr0: float, lr_ratio: float, loss_sum,
+              ws, b1=0.9, b2=0.999, eps=1e-8):
+    """len(rows) // batch Adam steps in one call; loss_sum [1] f64 gets the sum
+    of their losses."""
+    n = mlp_param_count()
+    for a, name in ((master, "master"), (m, "m"), (v, "v"), (grad, "grad")):
+        _need(a, torch.float32, (n,), name)
+    _need(x, torch.float32, name="x")
+    _need(t, torch.float32, name="t")
+    _need(rows, torch.int64, name="rows")
+    _need(loss_sum, torch.float64, (1,), "loss_sum")
+    nb = rows.numel() // batch
+    check(lib().mpf_mlp_train(ctypes.byref(MLP_DESC), _p(master), _p(packed), _p(m), _p(v), _p(grad), _p(x), _p(t),
+                              _p(rows), nb, int(batch), int(step0), float(lr0), float(lr_ratio), float(b1), float(b2),
+                              float(eps), _p(loss_sum), _p(ws), ws.numel(), _stream()), "mpf_mlp_train")
+
+
+def shuffle_rows(n: int, count: int, seed: int, rows=None, device="cuda"):
+    """rows [count] int64: the first count entries of a seeded permutation of [0, n)."""
+    if rows is None:
+        rows = torch.empty(count, dtype=torch.int64, device=device)
+    _need(rows, torch.int64, (count,), "rows")
+    check(lib().mpf_shuffle_rows(int(n), int(count), int(seed) & (2 ** 64 - 1), _p(rows), _stream()),
+          "mpf_shuffle_rows")
+    return rows

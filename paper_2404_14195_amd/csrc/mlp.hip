@@ -28,6 +28,9 @@
 // sums, so training is bitwise reproducible.  The layered form is bound by
 // HBM traffic of the activations (about 12 bytes per 256 flops of a hidden
 // layer), far below the MFMA ridge.
+#include <algorithm>
+#include <cmath>
+
 #include "common.hpp"
 
 namespace mpf {
@@ -98,21 +101,40 @@ __global__ __launch_bounds__(kBlock) void gemm_tn(int64_t M, int N, int64_t K, i
   const int64_t am = m0 + r;
   const bool a_ok = am < M;
   const u16* ap = A + (a_ok ? am : 0) * lda + 8 * g;
-  const u16* bp[NT];
-  bool b_ok[NT];
+  // row n0 + 16 t + r of Bt sits 16 t ldb elements past this lane's base row
+  const u16* bb = Bt + (int64_t)(n0 + r) * ldb + 8 * g;
+  const int64_t bstep = 16 * ldb;
+  // two k-steps per iteration: all eighteen fragment loads are in flight
+  // before the first product waits on them
+  int64_t k0 = kb;
+  for (; k0 + 32 < ke; k0 += 64) {
+    bf16x8 fa0 = {}, fa1 = {};
+    if (a_ok) {
+      fa0 = *reinterpret_cast<const bf16x8*>(ap + k0);
+      fa1 = *reinterpret_cast<const bf16x8*>(ap + k0 + 32);
+    }
+    bf16x8 fb0[NT], fb1[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int bn = n0 + 16 * t + r;
-    b_ok[t] = bn < N;
-    bp[t] = Bt + (int64_t)(b_ok[t] ? bn : 0) * ldb + 8 * g;
+    for (int t = 0; t < NT; ++t) {
+      fb0[t] = bf16x8{};
+      fb1[t] = bf16x8{};
+      if (n0 + 16 * t + r < N) {
+        fb0[t] = *reinterpret_cast<const bf16x8*>(bb + t * bstep + k0);
+        fb1[t] = *reinterpret_cast<const bf16x8*>(bb + t * bstep + k0 + 32);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa0, fb0[t], acc[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa1, fb1[t], acc[t], 0, 0, 0);
   }
-  for (int64_t k0 = kb; k0 < ke; k0 += 32) {
+  if (k0 < ke) {
     bf16x8 fa = {};
     if (a_ok) fa = *reinterpret_cast<const bf16x8*>(ap + k0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       bf16x8 fb = {};
-      if (b_ok[t]) fb = *reinterpret_cast<const bf16x8*>(bp[t] + k0);
+      if (n0 + 16 * t + r < N) fb = *reinterpret_cast<const bf16x8*>(bb + t * bstep + k0);
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[t], 0, 0, 0);
     }
   }
@@ -198,13 +220,19 @@ __global__ __launch_bounds__(kBlock) void gemm_tn(int64_t M, int N, int64_t K, i
   }
 }
 
-// out[i] = sum_z part[z * n + i], z ascending
-__global__ void sum_parts(const float* __restrict__ part, int64_t parts, int64_t n, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+// out[g * n + i] = sum of part[z * n + i] over z in [g G, min(parts, (g+1) G)),
+// z ascending.  Two rounds (G ~ sqrt(parts)) turn any number of partials into
+// one sum per element in a fixed order, with every round spread over the chip.
+__global__ void group_sums(const float* __restrict__ part, int64_t parts, int64_t n, int64_t G,
+                           float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t groups = (parts + G - 1) / G;
+  if (t >= groups * n) return;
+  const int64_t g = t / n, i = t % n;
+  const int64_t z1 = min(parts, (g + 1) * G);
   float s = 0.f;
-  for (int64_t z = 0; z < parts; ++z) s += part[z * n + i];
-  out[i] = s;
+  for (int64_t z = g * G; z < z1; ++z) s += part[z * n + i];
+  out[t] = s;
 }
 
 // inputs: x [B][5] FP32 (row b of the batch = x[rows ? rows[b] : b]) ->
@@ -233,37 +261,46 @@ __global__ void pack_inputs(int64_t B, int64_t Bp, const float* __restrict__ x, 
     for (int j = 0; j < 8; ++j) xbT[j * Bp + b] = h[j];
 }
 
-// dL/dy [B][4] FP32 -> dyb [Bp][32] BF16 and dyT [4][Bp] BF16 (padding zero)
-__global__ void pack_dy(int64_t B, int64_t Bp, const float* __restrict__ dy, u16* __restrict__ dyb,
-                        u16* __restrict__ dyT) {
+// dL/dy [B][4] FP32 -> dyb [Bp][32] BF16 and dyT [4][Bp] BF16 (padding zero),
+// plus each block's column sums of dy (FP32 tree over its 256 rows) for the
+// output bias gradient
+__global__ __launch_bounds__(kBlock) void pack_dy(int64_t B, int64_t Bp, const float* __restrict__ dy,
+                                                  u16* __restrict__ dyb, u16* __restrict__ dyT,
+                                                  float* __restrict__ colpart) {
+  __shared__ float red[kOut][kBlock];
   const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (b >= Bp) return;
   const bool live = b < B;
-  u16 h[kOut];
+  float d[kOut];
 #pragma unroll
-  for (int j = 0; j < kOut; ++j) h[j] = live ? to_bf16(dy[b * kOut + j]) : (u16)0;
-  uint4* dst = reinterpret_cast<uint4*>(dyb + b * kK1);
-  uint4 q;
-  q.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
-  q.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
-  q.z = 0u;
-  q.w = 0u;
-  dst[0] = q;
-  q.x = q.y = 0u;
+  for (int j = 0; j < kOut; ++j) {
+    d[j] = live ? dy[b * kOut + j] : 0.f;
+    red[j][threadIdx.x] = d[j];
+  }
+  if (b < Bp) {
+    u16 h[kOut];
 #pragma unroll
-  for (int v = 1; v < kK1 / 8; ++v) dst[v] = q;
+    for (int j = 0; j < kOut; ++j) h[j] = to_bf16(d[j]);
+    uint4* dst = reinterpret_cast<uint4*>(dyb + b * kK1);
+    uint4 q;
+    q.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
+    q.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+    q.z = 0u;
+    q.w = 0u;
+    dst[0] = q;
+    q.x = q.y = 0u;
 #pragma unroll
-  for (int j = 0; j < kOut; ++j) dyT[j * Bp + b] = h[j];
-}
-
-// column sums of dy [B][4] (FP32, fixed order): one block per column
-__global__ __launch_bounds__(kBlock) void colsum_dy(int64_t B, const float* __restrict__ dy, float* __restrict__ db) {
-  __shared__ double lds[kBlock];
-  const int j = blockIdx.x;
-  double s = 0.0;
-  for (int64_t b = threadIdx.x; b < B; b += kBlock) s += (double)dy[b * kOut + j];
-  const double t = block_sum<kBlock>(s, lds);
-  if (threadIdx.x == 0) db[j] = (float)t;
+    for (int v = 1; v < kK1 / 8; ++v) dst[v] = q;
+#pragma unroll
+    for (int j = 0; j < kOut; ++j) dyT[j * Bp + b] = h[j];
+  }
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int j = 0; j < kOut; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < kOut) colpart[(int64_t)blockIdx.x * kOut + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // master -> packed BF16 (see the layout above)
@@ -384,9 +421,65 @@ __global__ __launch_bounds__(kBlock) void to_state_kernel(int64_t n, int64_t n_i
   }
 }
 
+// A seeded permutation of [0, n) evaluated pointwise: a 4-round balanced
+// Feistel network on 2h-bit integers (2^(2h) >= n), whose round function is
+// a 32-bit integer hash of the right half and a round key, made a permutation
+// of [0, n) by cycle walking (re-applying the network until the value falls
+// below n; the walk ends because the network is a bijection of [0, 2^(2h))).
+__device__ __forceinline__ unsigned mix32(unsigned x) {  // integer hash (xorshift-multiply)
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ void shuffle_kernel(int64_t n, int64_t count, int h, unsigned long long seed, int64_t* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
+  const unsigned long long mask = (1ull << h) - 1;
+  unsigned k[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) k[r] = mix32((unsigned)(seed >> (16 * r)) ^ (0x9e3779b9u * (r + 1)) ^ (unsigned)(seed >> 32));
+  unsigned long long x = (unsigned long long)i;
+  do {
+    unsigned long long L = x >> h, R = x & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const unsigned long long F = (unsigned long long)mix32((unsigned)R ^ k[r] ^ (unsigned)(R >> 32)) & mask;
+      const unsigned long long nl = R;
+      R = L ^ F;
+      L = nl;
+    }
+    x = (L << h) | R;
+  } while (x >= (unsigned long long)n);
+  rows[i] = (int64_t)x;
+}
+
 __global__ void zero_double(double* x) { *x = 0.0; }
+__global__ void add_double(const double* x, double* sum) { *sum += *x; }
 
 // ------------------------------------------------------------------ host side
+
+inline int64_t isqrt_ceil(int64_t x) {
+  int64_t r = (int64_t)std::sqrt((double)x);
+  while (r * r < x) ++r;
+  return r < 1 ? 1 : r;
+}
+
+// out[i] = sum_z part[z][i] for i < n, z < parts, in a fixed order (two rounds
+// of group sums through tmp)
+void reduce_parts(hipStream_t st, const float* part, int64_t parts, int64_t n, float* out, float* tmp) {
+  if (parts <= 32) {
+    hipLaunchKernelGGL(group_sums, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, part, parts, n, parts, out);
+    return;
+  }
+  const int64_t G = isqrt_ceil(parts), groups = (parts + G - 1) / G;
+  hipLaunchKernelGGL(group_sums, dim3(grid_for(groups * n, kBlock)), dim3(kBlock), 0, st, part, parts, n, G, tmp);
+  hipLaunchKernelGGL(group_sums, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, (const float*)tmp, groups, n,
+                     groups, out);
+}
 
 inline int64_t pad_batch(int64_t B) { return (B + kRowsPerBlock - 1) / kRowsPerBlock * kRowsPerBlock; }
 
@@ -400,7 +493,7 @@ inline int64_t grad_chunk(int64_t Bp) {
 
 struct Ws {
   u16 *xb, *xbT, *a[3], *aT[3], *dyb, *dyT, *dz[2], *dzT[2];
-  float *z[3], *wpart, *bpart;
+  float *z[3], *wpart, *bpart, *tree;
   double* red;
 };
 
@@ -434,6 +527,9 @@ size_t carve(void* base, int64_t B, bool train, Ws* w) {
     }
     t.wpart = (float*)take(4 * (size_t)chunks * kW * kW);
     t.bpart = (float*)take(4 * (size_t)(Bp / kRowsPerBlock) * kW);
+    // first-round group sums: at most ceil(sqrt(parts)) + 1 rows of any reduction
+    const int64_t rows = std::max(isqrt_ceil(chunks) * kW * kW, isqrt_ceil(Bp / kRowsPerBlock) * kW);
+    t.tree = (float*)take(4 * (size_t)(rows + kW * kW));
   }
   if (w) *w = t;
   return at;
@@ -461,8 +557,7 @@ void weight_grad(hipStream_t st, const Ws& w, int64_t Bp, int M, int N, const u1
     launch_gemm<8, kPartial>(st, M, N, Bp, kc, A, Bp, Bt, Bp, e);
   else
     launch_gemm<1, kPartial>(st, M, N, Bp, kc, A, Bp, Bt, Bp, e);
-  hipLaunchKernelGGL(sum_parts, dim3(grid_for((int64_t)M * N, kBlock)), dim3(kBlock), 0, st, (const float*)w.wpart,
-                     chunks, (int64_t)M * N, out);
+  reduce_parts(st, w.wpart, chunks, (int64_t)M * N, out, w.tree);
 }
 
 bool shape_ok(const mpf_mlp_desc* d) {
@@ -538,8 +633,9 @@ extern "C" int mpf_mlp_backward(const mpf_mlp_desc* d, const void* packed, const
   const int64_t Bp = pad_batch(B);
   const int64_t nblk = Bp / kRowsPerBlock;
   const u16* P = (const u16*)packed;
-  hipLaunchKernelGGL(pack_dy, dim3(grid_for(Bp, kBlock)), dim3(kBlock), 0, st, B, Bp, dy, w.dyb, w.dyT);
-  hipLaunchKernelGGL(colsum_dy, dim3(kOut), dim3(kBlock), 0, st, B, dy, grad + ob4);
+  const unsigned gdy = grid_for(Bp, kBlock);
+  hipLaunchKernelGGL(pack_dy, dim3(gdy), dim3(kBlock), 0, st, B, Bp, dy, w.dyb, w.dyT, w.bpart);
+  reduce_parts(st, w.bpart, gdy, kOut, grad + ob4, w.tree);
   // layer 4: dW4 = dy^T a3
   weight_grad(st, w, Bp, kOut, kW, w.dyT, w.aT[2], grad + oW4);
   // down through the hidden layers: dZ_l = (dZ_{l+1} W_{l+1}) * silu'(Z_l)
@@ -556,8 +652,7 @@ extern "C" int mpf_mlp_backward(const mpf_mlp_desc* d, const void* packed, const
     e.ldT = Bp;
     e.colpart = w.bpart;
     launch_gemm<8, kHiddenBwd>(st, Bp, kW, k_in, k_in, dz_in, k_in, wt[l], k_in, e);
-    hipLaunchKernelGGL(sum_parts, dim3(1), dim3(kBlock), 0, st, (const float*)w.bpart, nblk, (int64_t)kW,
-                       grad + ob[l]);
+    reduce_parts(st, w.bpart, nblk, kW, grad + ob[l], w.tree);
     if (l > 0)
       weight_grad(st, w, Bp, kW, kW, w.dzT[s], w.aT[l - 1], grad + ow[l]);
     else
@@ -640,6 +735,69 @@ extern "C" int mpf_gemm_bf16(int64_t M, int N, int64_t K, const void* A, int64_t
     launch_gemm<8, kPartial>(st, M, N, K, K, (const u16*)A, lda, (const u16*)Bt, ldb, e);
   else
     launch_gemm<1, kPartial>(st, M, N, K, K, (const u16*)A, lda, (const u16*)Bt, ldb, e);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+// Fused loop of training steps: everything a step launches, for n_batches
+// consecutive minibatches, from one host call (a step is about 25 launches;
+// issued from Python they cost more host time than the device needs for a
+// 64k-sample batch).  Layout of ws: the training workspace of B, then y, dy
+// [B][4] float, the loss, and the MSE partials.
+static size_t train_extra(int64_t B) {
+  const size_t yb = align256(4 * (size_t)B * kOut);
+  return 2 * yb + 256 + align256(mpf_reduce_workspace(B * kOut));
+}
+
+extern "C" size_t mpf_mlp_train_workspace(const mpf_mlp_desc* d, int64_t B) {
+  const size_t base = mpf_mlp_workspace(d, B, 1);
+  return base ? base + train_extra(B) : 0;
+}
+
+extern "C" int mpf_mlp_train(const mpf_mlp_desc* d, float* master, void* packed, float* m, float* v, float* grad,
+                             const float* x, const float* t, const int64_t* rows, int64_t n_batches, int64_t B,
+                             int step0, float lr0, float lr_ratio, float b1, float b2, float eps, double* loss_sum,
+                             void* ws, size_t ws_bytes, void* stream) {
+  if (!shape_ok(d)) return MPF_ERR_UNSUPPORTED;
+  if (!master || !packed || !m || !v || !grad || !x || !t || !rows || !loss_sum || n_batches < 1 || B < 1 ||
+      B > kMaxBatch || step0 < 0 || !(lr0 > 0.f) || !(lr_ratio > 0.f))
+    return MPF_ERR_ARG;
+  if (!ws || ws_bytes < mpf_mlp_train_workspace(d, B)) return MPF_ERR_WORKSPACE;
+  hipStream_t st = as_stream(stream);
+  const size_t base = mpf_mlp_workspace(d, B, 1);
+  char* extra = reinterpret_cast<char*>(ws) + base;
+  const size_t yb = align256(4 * (size_t)B * kOut);
+  float* y = reinterpret_cast<float*>(extra);
+  float* dy = reinterpret_cast<float*>(extra + yb);
+  double* loss = reinterpret_cast<double*>(extra + 2 * yb);
+  void* red = extra + 2 * yb + 256;
+  const size_t red_bytes = ws_bytes - base - 2 * yb - 256;
+  hipLaunchKernelGGL(zero_double, dim3(1), dim3(1), 0, st, loss_sum);
+  double lr = lr0;
+  for (int64_t i = 0; i < n_batches; ++i) {
+    const int64_t* r = rows + i * B;
+    int rc = mpf_mlp_forward(d, master, packed, x, r, y, B, 1, ws, base, stream);
+    if (!rc) rc = mpf_mlp_mse(B, y, t, r, dy, loss, red, red_bytes, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(add_double, dim3(1), dim3(1), 0, st, (const double*)loss, loss_sum);
+    rc = mpf_mlp_backward(d, packed, dy, grad, B, ws, base, stream);
+    if (!rc) rc = mpf_adam_step(kParams, master, grad, m, v, (int)(step0 + i + 1), (float)lr, b1, b2, eps, stream);
+    if (!rc) rc = mpf_mlp_pack(d, master, packed, stream);
+    if (rc) return rc;
+    lr *= lr_ratio;
+  }
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+extern "C" int mpf_shuffle_rows(int64_t n, int64_t count, uint64_t seed, int64_t* rows, void* stream) {
+  if (!rows || n < 1 || count < 0 || count > n || n > (int64_t(1) << 60)) return MPF_ERR_ARG;
+  if (count == 0) return MPF_OK;
+  int bits = 1;
+  while ((int64_t(1) << bits) < n) ++bits;
+  const int h = (bits + 1) / 2;
+  hipLaunchKernelGGL(shuffle_kernel, dim3(grid_for(count, kBlock)), dim3(kBlock), 0, as_stream(stream), n, count, h,
+                     (unsigned long long)seed, rows);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }

@@ -109,6 +109,7 @@ class WarmStart:
         self.v = torch.zeros_like(self.master)
         self.grad = torch.empty_like(self.master)
         self.step = 0
+        self.epochs_done = 0
         self._x, self._t = [], []
         self.radii, self.logU, self.logP = [], [], []
         self.X = self.T = None
@@ -152,40 +153,22 @@ class WarmStart:
             self.X = torch.cat(self._x).contiguous()
             self.T = torch.cat(self._t).contiguous()
         N = self.X.shape[0]
-        ws = api.mlp_workspace(batch, True, self.device)
-        rws = api.reduce_workspace(4 * batch, self.device)
-        y = torch.empty((batch, 4), dtype=torch.float32, device=self.device)
-        dy = torch.empty_like(y)
-        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
-        acc = torch.zeros(1, dtype=torch.float64, device=self.device)
-        gen = torch.Generator().manual_seed(seed)
+        ws = api.mlp_train_workspace(batch, self.device)
+        loss_sum = torch.zeros(1, dtype=torch.float64, device=self.device)
         per_epoch = max(1, N // batch)
         total = epochs * per_epoch
-
-        def shuffled():  # host permutation, uploaded from pinned memory
-            return torch.randperm(N, generator=gen)[:per_epoch * batch].pin_memory().to(self.device,
-                                                                                       non_blocking=True)
-
+        ratio = (lr_end / lr) ** (1.0 / max(1, total - 1))
+        perm = torch.empty(per_epoch * batch, dtype=torch.int64, device=self.device)
         hist = []
         t0 = time.perf_counter()
-        perm = shuffled()
         for ep in range(epochs):
-            acc.zero_()
-            for b in range(per_epoch):
-                self.step += 1
-                frac = (ep * per_epoch + b) / max(1, total - 1)
-                rate = lr * (lr_end / lr) ** frac
-                rows = perm[b * batch:(b + 1) * batch]
-                api.mlp_forward(self.master, self.packed, self.X, y, ws, rows=rows, train=True)
-                api.mlp_mse(y, self.T, dy, loss, rws, rows=rows)
-                api.mlp_backward(self.packed, dy, self.grad, ws)
-                api.adam_step(self.master, self.grad, self.m, self.v, self.step, rate)
-                api.mlp_pack(self.master, self.packed)
-                acc.add_(loss)
-            # the next permutation is drawn on the host while the device works
-            nxt = shuffled() if ep + 1 < epochs else None
-            hist.append(acc.item() / per_epoch)
-            perm = nxt
+            api.shuffle_rows(N, per_epoch * batch, (seed << 32) + self.epochs_done, perm)
+            self.epochs_done += 1
+            rate = lr * ratio ** (ep * per_epoch)
+            api.mlp_train(self.master, self.packed, self.m, self.v, self.grad, self.X, self.T, perm, batch,
+                          self.step, rate, ratio, loss_sum, ws)
+            self.step += per_epoch
+            hist.append(loss_sum.item() / per_epoch)
             if log:
                 log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f}s)")
         return hist

@@ -243,3 +243,50 @@ def test_mlp_argument_errors(api):
         api.mlp_forward(net.master, net.packed, x, y, small)
     with pytest.raises(MPFError):
         api.adam_step(net.master, net.master, net.master, net.master, 0, 1e-3)  # step must be >= 1
+
+
+def test_fused_training_loop_matches_separate_calls(api):
+    """mpf_mlp_train runs exactly the kernels of the separate calls in the same
+    order, so three steps through it and through the separate calls give
+    identical parameters, moments and loss."""
+    rng = np.random.default_rng(13)
+    N, B = 3000, 256
+    x = dev(rng.normal(size=(N, 5)).astype(np.float32), torch.float32)
+    t = dev(rng.normal(size=(N, 4)).astype(np.float32), torch.float32)
+    rows = dev(rng.permutation(N)[:3 * B], torch.int64)
+    theta = init_theta(14)
+    a, b = Net(api, theta, B), Net(api, theta, B)
+    ma, va, ga = (torch.zeros(theta.size, device="cuda") for _ in range(3))
+    mb, vb, gb = (torch.zeros(theta.size, device="cuda") for _ in range(3))
+    y = torch.empty((B, 4), dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rws = api.reduce_workspace(4 * B, "cuda")
+    total = 0.0
+    lr, ratio = 1e-3, 1.0  # a constant rate: both sides then pass the same float
+    for i in range(3):
+        r = rows[i * B:(i + 1) * B]
+        api.mlp_forward(a.master, a.packed, x, y, a.ws, rows=r, train=True)
+        api.mlp_mse(y, t, dy, loss, rws, rows=r)
+        total += loss.item()
+        api.mlp_backward(a.packed, dy, ga, a.ws)
+        api.adam_step(a.master, ga, ma, va, i + 1, lr * ratio ** i)
+        api.mlp_pack(a.master, a.packed)
+    loss_sum = torch.zeros(1, dtype=torch.float64, device="cuda")
+    api.mlp_train(b.master, b.packed, mb, vb, gb, x, t, rows, B, 0, lr, ratio, loss_sum, api.mlp_train_workspace(B))
+    assert torch.equal(a.master, b.master) and torch.equal(ma, mb) and torch.equal(va, vb)
+    assert torch.equal(a.packed, b.packed)
+    assert loss_sum.item() == pytest.approx(total, rel=1e-15)
+
+
+@pytest.mark.parametrize("n,count", [(1, 1), (1000, 1000), (4097, 4097), (12_800_000, 12_800_000), (300, 129)])
+def test_shuffle_rows_is_a_seeded_permutation(api, n, count):
+    a = api.shuffle_rows(n, count, 7).cpu().numpy()
+    b = api.shuffle_rows(n, count, 7).cpu().numpy()
+    c = api.shuffle_rows(n, count, 8).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert len(np.unique(a)) == count and a.min() >= 0 and a.max() < n
+    if count == n:
+        assert np.array_equal(np.sort(a), np.arange(n))
+    if n > 1:
+        assert not np.array_equal(a, c)
