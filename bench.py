@@ -118,6 +118,26 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
     return out
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Achievable HBM bandwidth: best of reps device-to-device copies of mib
+    MiB (read + write bytes over time)."""
+    src = torch.ones(mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        best = min(best, ev0.elapsed_time(ev1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * mib * 2 ** 20 / (best * 1e-3) / 1e9
+
+
 def train_warm_start(torch, nc, n_cells=16, h0=0.016, epochs=200, batch=8192):
     """The learned warm start used by the time-to-steady runs.  Training set:
     steady MLBM fields (FP32 weights, FP64 state, k settled to 1e-6 per 500
@@ -197,6 +217,51 @@ def mlp_training_throughput(torch, api, samples=12_800_000, batch=65536, epochs=
            "mfma_bf16_peak_frac": flops / sec / 1e12 / BF16_PEAK_TFLOPS, "loss_last_epoch": hist[-1]}
     print(f"[bench] mlp training: {seen / sec:.3e} samples/s, {flops / sec / 1e12:.1f} TFLOP/s", file=sys.stderr,
           flush=True)
+    return out
+
+
+def _sweep_cell(args):
+    import nodecloud as nc
+    r, = args
+    c = nc.sphere_cloud(r, 0.002, 0.3, 0.008, seed=3)
+    return c
+
+
+def acm_sweep(torch, cells, steps=2000):
+    """ACM on the large cells across porosity: r in {0.2, 0.3, 0.4, 0.5, 0.55,
+    0.6} (grains overlap their images above 1/2), h(d) = min(0.002 + 0.3 d,
+    0.008), N_L = 30: node-steps/s per precision and the permeability error of
+    FP32 and mixed against FP64 after the same steps."""
+    from paper_2404_14195_amd import MPF_F32, MPF_F64, MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization
+    out = []
+    for c in cells:
+        t0 = time.perf_counter()
+        disc = Discretization(c, nl=30, M=64)
+        rec = {"r": c.r, "n": c.n, "n_boundary": c.n_bnd, "phi": disc.phi, "steps": steps}
+        for name, prec in (("fp64", MPF_F64), ("fp32", MPF_F32), ("mixed", MPF_MIXED)):
+            s = ACMSolver(disc, precision=prec)
+            s.run(20)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            s.run(steps - 20)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            rec[name] = {"us_per_step": ms * 1e3 / (steps - 20), "node_steps_per_s": c.n * (steps - 20) / (ms * 1e-3),
+                         "k": s.permeability()}
+            del s
+        for name in ("fp32", "mixed"):
+            rec[name]["k_rel_err_vs_fp64"] = abs(rec[name]["k"] / rec["fp64"]["k"] - 1.0)
+        print(f"[bench] acm sweep r={c.r}: n={c.n} fp64 {rec['fp64']['us_per_step']:.0f} us/step, fp32 "
+              f"{rec['fp32']['us_per_step']:.0f}, mixed {rec['mixed']['us_per_step']:.0f}; k64={rec['fp64']['k']:.6e} "
+              f"err32={rec['fp32']['k_rel_err_vs_fp64']:.1e} errmix={rec['mixed']['k_rel_err_vs_fp64']:.1e} "
+              f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+        out.append(rec)
+        del disc
+        torch.cuda.empty_cache()
     return out
 
 
@@ -349,6 +414,7 @@ def main():
     ap.add_argument("--no-steady", action="store_true", help="skip the time-to-steady measurement")
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
+    ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--weights-batch", action="store_true",
                     help="only measure the batched weight solve of 8 cells (about 18M rows) and exit")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -366,6 +432,16 @@ def main():
     from paper_2404_14195_amd import MPF_F32, MPF_F64, MPF_MIXED, api
     from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
 
+    if args.acm_sweep:
+        import multiprocessing as mp
+        # node clouds are filled in worker processes before this process
+        # touches the GPU
+        with mp.get_context("fork").Pool(6) as pool:
+            cells = pool.map(_sweep_cell, [(r,) for r in (0.2, 0.3, 0.4, 0.5, 0.55, 0.6)])
+        print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
+        torch.cuda.set_device(0)
+        print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
+        return
     if args.mlp:
         torch.cuda.set_device(0)
         print(json.dumps({"mlp_training": mlp_training_throughput(torch, api)}))
@@ -441,9 +517,10 @@ def main():
     traffic = measured_traffic()
     bpn = bytes_per_node_step(19, 30, 4, 4)
     achieved = bpn * disc.n / (f32["step_kernel_ms"] * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "kernel": "lbm_step<float,float,19,true>", "bytes_per_node_step": bpn,
-            "launch_ms": f32["step_kernel_ms"]}
+            "launch_ms": f32["step_kernel_ms"], "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
     cpu = None
     if not args.no_cpu_baseline:
