@@ -400,7 +400,40 @@ def acm_and_weights(torch, nc, api):
         out[name] = rec
         del disc
         torch.cuda.empty_cache()
+    out["lbm_large"] = lbm_large(torch, nc)
     return out
+
+
+def lbm_large(torch, nc, steps=300):
+    """The MLBM step on a cell whose weights (2.8 GB FP32) cannot sit in the
+    256 MB Infinity Cache: r = 0.3, h(d) = min(0.003 + 0.16 d, 0.015), seed 2."""
+    from paper_2404_14195_amd import MPF_F32, MPF_F64, MPF_MIXED
+    from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
+    t0 = time.perf_counter()
+    cloud = nc.sphere_cloud(0.3, 0.003, 0.16, 0.015, seed=2)
+    disc = Discretization(cloud, nl=30, M=64)
+    print(f"[bench] lbm_large: {cloud.n} nodes, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    rec = {"n_nodes": cloud.n, "n_boundary": cloud.n_bnd, "steps": steps}
+    for name, prec, sw, sf in (("fp32", MPF_F32, 4, 4), ("mixed", MPF_MIXED, 4, 8), ("fp64", MPF_F64, 8, 8)):
+        s = MLBMSolver(disc, q=19, precision=prec)
+        s.run(20)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        s.run(steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        bpn = bytes_per_node_step(19, 30, sw, sf)
+        rec[name] = {"us_per_step": ms * 1e3, "node_steps_per_s": cloud.n / (ms * 1e-3),
+                     "hbm_frac": bpn * cloud.n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "k": s.permeability()}
+        print(f"[bench] lbm_large {name}: {ms * 1e3:.1f} us/step, {rec[name]['node_steps_per_s']:.3e} node-steps/s, "
+              f"{rec[name]['hbm_frac']:.2f} of HBM", file=sys.stderr, flush=True)
+        del s
+        torch.cuda.empty_cache()
+    del disc
+    return rec
 
 
 def main():

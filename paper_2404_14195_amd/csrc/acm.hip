@@ -33,6 +33,22 @@ __device__ __forceinline__ T group_sum(T x) {
   return x;
 }
 
+// body(j) for the columns j = j0 + sl, j0 + sl + LPN, ... below nl, in
+// ascending order; fully unrolled when the stencil size is a compile-time
+// constant, so every lane issues all its index, weight and gather loads early.
+template <int LPN, int NLC, typename Body>
+__device__ __forceinline__ void columns(int nl, int j0, int sl, Body&& body) {
+  if constexpr (NLC > 0) {
+#pragma unroll
+    for (int t = 0; t < (NLC + LPN - 1) / LPN; ++t) {
+      const int j = j0 + sl + t * LPN;
+      if (j < NLC) body(j);
+    }
+  } else {
+    for (int j = j0 + sl; j < nl; j += LPN) body(j);
+  }
+}
+
 template <typename T, typename TW>
 struct Fields {
   int64_t n, n_int, nb;
@@ -49,15 +65,16 @@ struct Fields {
   double dtd, rho, beta, v_ref;
 };
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i, int sl) {
-  const int64_t n = F.n, os = (int64_t)F.nl * n;
+  const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
+  const int64_t n = F.n, os = (int64_t)nl * n;
   T d[3][4];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int o = 0; o < 4; ++o) d[a][o] = T(0);
-  for (int j = sl; j < F.nl; j += LPN) {
+  columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
     const int s = F.sten[at];
     const T wx = (T)F.w[at], wy = (T)F.w[os + at], wz = (T)F.w[2 * os + at], wl = (T)F.w[3 * os + at];
@@ -69,7 +86,7 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
       d[a][2] += wz * u[a];
       d[a][3] += wl * u[a];
     }
-  }
+  });
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -85,43 +102,46 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
   }
 }
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* __restrict__ vsrc, T coef, int64_t i,
                                               int sl) {
-  const int64_t n = F.n, os = (int64_t)F.nl * n;
+  const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
+  const int64_t n = F.n, os = (int64_t)nl * n;
   T div = T(0);
-  for (int j = sl; j < F.nl; j += LPN) {
+  columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
     const int s = F.sten[at];
     div += (T)F.w[at] * vsrc[s] + (T)F.w[os + at] * vsrc[n + s] + (T)F.w[2 * os + at] * vsrc[2 * n + s];
-  }
+  });
   div = group_sum<LPN>(div);
   if (sl == 0) F.p[i] -= coef * div;
 }
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __device__ __forceinline__ void neumann_node(const Fields<T, TW>& F, int64_t b, int sl) {
+  const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   T s = T(0);
-  for (int j = 1 + sl; j < F.nl; j += LPN) {
+  columns<LPN, NLC>(nl, 1, sl, [&](int j) {
     const int64_t at = (int64_t)j * F.nb + b;
     s += (T)F.wn[at] * F.p[F.sn[at]];
-  }
+  });
   s = group_sum<LPN>(s);
   if (sl == 0) F.p[F.n_int + b] = -s / (T)F.wn[b];
 }
 
 // returns |v_i| (valid in every lane of the node's group)
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, int64_t i, int sl) {
-  const int64_t n = F.n, os = (int64_t)F.nl * n;
+  const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
+  const int64_t n = F.n, os = (int64_t)nl * n;
   T gp[3] = {T(0), T(0), T(0)};
-  for (int j = sl; j < F.nl; j += LPN) {
+  columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
     const T ps = F.p[F.sten[at]];
     gp[0] += (T)F.w[at] * ps;
     gp[1] += (T)F.w[os + at] * ps;
     gp[2] += (T)F.w[2 * os + at] * ps;
-  }
+  });
   double m2 = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -157,38 +177,38 @@ __device__ __forceinline__ void block_max_into(double mag, double* lds, double* 
 
 // ---------------------------------------------------------------- one launch per pass
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __global__ __launch_bounds__(kBlock) void k_predictor(Fields<T, TW> F) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;  // whole LPN groups exit together
-  predictor_node<T, TW, LPN>(F, i, (int)(g % LPN));
+  predictor_node<T, TW, LPN, NLC>(F, i, (int)(g % LPN));
 }
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __global__ __launch_bounds__(kBlock) void k_pressure(Fields<T, TW> F, const T* __restrict__ vsrc) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_node<T, TW, LPN>(F, vsrc, coupling_coef(F), i, (int)(g % LPN));
+  pressure_node<T, TW, LPN, NLC>(F, vsrc, coupling_coef(F), i, (int)(g % LPN));
 }
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __global__ __launch_bounds__(kBlock) void k_neumann(Fields<T, TW> F) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g == 0) *F.vmax = 0.0;  // the pressure pass has consumed it; the velocity pass rebuilds it
   const int64_t b = g / LPN;
   if (b >= F.nb) return;
-  neumann_node<T, TW, LPN>(F, b, (int)(g % LPN));
+  neumann_node<T, TW, LPN, NLC>(F, b, (int)(g % LPN));
 }
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 __global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F) {
   __shared__ double red[kBlock / kWave];
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   double mag = 0.0;
-  if (i < F.n_int) mag = velocity_node<T, TW, LPN>(F, i, (int)(g % LPN));
+  if (i < F.n_int) mag = velocity_node<T, TW, LPN, NLC>(F, i, (int)(g % LPN));
   block_max_into(mag, red, F.vmax);
 }
 
@@ -202,19 +222,26 @@ __global__ void fill_zero(T* __restrict__ x, int64_t n) {
 // the chain of dependent gathers of one node: split each stencil 8 ways
 constexpr int64_t kFewNodes = 200000;
 
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, int NLC>
 int run_launches(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   for (int s = 0; s < n_steps; ++s) {
-    hipLaunchKernelGGL((k_predictor<T, TW, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
+    hipLaunchKernelGGL((k_predictor<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
     for (int it = 0; it < n_p; ++it) {
-      hipLaunchKernelGGL((k_pressure<T, TW, LPN>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.vp : F.v));
-      hipLaunchKernelGGL((k_neumann<T, TW, LPN>), dim3(gb), dim3(kBlock), 0, st, F);
-      hipLaunchKernelGGL((k_velocity<T, TW, LPN>), dim3(gi), dim3(kBlock), 0, st, F);
+      hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.vp : F.v));
+      hipLaunchKernelGGL((k_neumann<T, TW, LPN, NLC>), dim3(gb), dim3(kBlock), 0, st, F);
+      hipLaunchKernelGGL((k_velocity<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
     }
   }
   MPF_LAUNCH_CHECK();
   return MPF_OK;
+}
+
+// stencils of 30 nodes (the measured size) get fully unrolled column loops,
+// which lets every lane issue all its index, weight and gather loads early
+template <typename T, typename TW, int LPN>
+int launch_nl(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
+  return F.nl == 30 ? run_launches<T, TW, LPN, 30>(F, n_steps, n_p, st) : run_launches<T, TW, LPN, 0>(F, n_steps, n_p, st);
 }
 
 template <typename T, typename TW>
@@ -235,11 +262,11 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   int lanes = prm->lanes;
   if (lanes == 0) lanes = n_int <= kFewNodes ? 8 : 2;
   switch (lanes) {
-    case 1: return run_launches<T, TW, 1>(F, n_steps, prm->n_p, st);
-    case 2: return run_launches<T, TW, 2>(F, n_steps, prm->n_p, st);
-    case 4: return run_launches<T, TW, 4>(F, n_steps, prm->n_p, st);
-    case 8: return run_launches<T, TW, 8>(F, n_steps, prm->n_p, st);
-    default: return run_launches<T, TW, 16>(F, n_steps, prm->n_p, st);
+    case 1: return launch_nl<T, TW, 1>(F, n_steps, prm->n_p, st);
+    case 2: return launch_nl<T, TW, 2>(F, n_steps, prm->n_p, st);
+    case 4: return launch_nl<T, TW, 4>(F, n_steps, prm->n_p, st);
+    case 8: return launch_nl<T, TW, 8>(F, n_steps, prm->n_p, st);
+    default: return launch_nl<T, TW, 16>(F, n_steps, prm->n_p, st);
   }
 }
 

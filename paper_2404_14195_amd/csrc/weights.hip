@@ -121,6 +121,29 @@ __device__ __forceinline__ double rhs_entry(int kind, const double* vec, const d
   return l == 1 ? e0 * id : (l == 2 ? e1 * id : (l == 3 ? e2 * id : 0.0));
 }
 
+// Wave-wide maximum of an unsigned key: butterflies inside each row of 16
+// lanes on DPP (quad permutes, half-row and row mirrors; register-to-register,
+// no LDS crossbar), then the four row maxima through readlane.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
+  x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false));  // row_mirror
+  const unsigned r0 = __builtin_amdgcn_readlane(x, 0), r1 = __builtin_amdgcn_readlane(x, 16);
+  const unsigned r2 = __builtin_amdgcn_readlane(x, 32), r3 = __builtin_amdgcn_readlane(x, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// Pivot of column c: the lowest lane whose key equals the wave maximum, or -1
+// if every key is zero.  Keys order candidates by magnitude: the high word of
+// a non-negative double (exponent and 20 leading significand bits), so the
+// pivot is within 2^-20 of the largest |a| (partial pivoting needs no more).
+__device__ __forceinline__ int pivot_lane(unsigned key) {
+  const unsigned mx = wave_max_u32(key);
+  if (mx == 0u) return -1;
+  return __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(key == mx)));
+}
+
 __device__ __forceinline__ float bcastf(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
@@ -163,29 +186,20 @@ __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, i
   // --- LU with partial pivoting, rows in place
   int pcol = (lane < N) ? 1 << 20 : -1;  // column at which this lane became pivot
   int bad = 0;
+  double dinv = 0.0;  // 1 / pivot, kept by the lane that holds the pivot row
 #pragma unroll
   for (int c = 0; c < N; ++c) {
-    double cand = (pcol > c) ? fabs(a[c]) : -1.0;
-    int cl = lane;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      double ov = __shfl_xor(cand, off);
-      int ol = __shfl_xor(cl, off);
-      if (ov > cand || (ov == cand && ol < cl)) { cand = ov; cl = ol; }
-    }
-    const int p = __builtin_amdgcn_readfirstlane(cl);
-    const double best = bcast(cand, 0);
-    if (!(best > 0.0)) { bad = c + 1; break; }
-    const double pv = bcast(a[c], p);
+    const unsigned key = (pcol > c) ? (unsigned)__double2hiint(fabs(a[c])) : 0u;
+    const int p = pivot_lane(key);
+    if (p < 0 || !(fabs(bcast(a[c], p)) > 0.0)) { bad = c + 1; break; }
+    const double inv = 1.0 / bcast(a[c], p);
     const bool act = pcol > c && lane != p;
-    if (lane == p) pcol = c;
-    const double l = act ? a[c] / pv : 0.0;
+    if (lane == p) { pcol = c; dinv = inv; }
+    // rows that are not eliminated here get a zero multiplier: fma(-0, u, a) = a
+    const double l = act ? a[c] * inv : 0.0;
     if (act) a[c] = l;
 #pragma unroll
-    for (int k = c + 1; k < N; ++k) {
-      double pk = bcast(a[k], p);
-      if (act) a[k] = fma(-l, pk, a[k]);
-    }
+    for (int k = c + 1; k < N; ++k) a[k] = fma(-l, bcast(a[k], p), a[k]);
   }
 
   double rvv[3] = {0.0, 0.0, 0.0};
@@ -207,23 +221,20 @@ __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, i
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(pcol == c)));
-        const bool act = pcol > c;
+        const double mc = pcol > c ? a[c] : 0.0;
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          double y = bcast(b[r], p);
-          if (act) b[r] = fma(-a[c], y, b[r]);
-        }
+        for (int r = 0; r < RB; ++r) b[r] = fma(-mc, bcast(b[r], p), b[r]);
       }
       // back substitution; lane c keeps unknown c
 #pragma unroll
       for (int c = N - 1; c >= 0; --c) {
         const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(pcol == c)));
-        const bool act = pcol < c;
+        const double uc = pcol < c ? a[c] : 0.0;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          double xc = bcast(b[r] / a[c], p);
+          const double xc = bcast(b[r] * dinv, p);
           if (lane == c) x[r] = xc;
-          if (act) b[r] = fma(-a[c], xc, b[r]);
+          b[r] = fma(-uc, xc, b[r]);
         }
       }
     } else {
@@ -285,28 +296,19 @@ __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int
 #pragma unroll
   for (int l = 0; l < 10; ++l) a[NL + l] = (float)(lane < NL ? mono(l, xi0, xi1, xi2) : 0.0);
   int pcol = (lane < N) ? 1 << 20 : -1;
+  float dinv = 0.0f;
 #pragma unroll
   for (int c = 0; c < N; ++c) {
-    float cand = (pcol > c) ? fabsf(a[c]) : -1.0f;
-    int cl = lane;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      float ov = __shfl_xor(cand, off);
-      int ol = __shfl_xor(cl, off);
-      if (ov > cand || (ov == cand && ol < cl)) { cand = ov; cl = ol; }
-    }
-    const int p = __builtin_amdgcn_readfirstlane(cl);
-    if (!(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(cand), 0)) > 0.0f)) return false;
-    const float pv = bcastf(a[c], p);
+    const unsigned key = (pcol > c) ? __float_as_uint(fabsf(a[c])) : 0u;  // exact order for floats
+    const int p = pivot_lane(key);
+    if (p < 0) return false;
+    const float inv = 1.0f / bcastf(a[c], p);
     const bool act = pcol > c && lane != p;
-    if (lane == p) pcol = c;
-    const float l = act ? a[c] / pv : 0.0f;
+    if (lane == p) { pcol = c; dinv = inv; }
+    const float l = act ? a[c] * inv : 0.0f;
     if (act) a[c] = l;
 #pragma unroll
-    for (int k = c + 1; k < N; ++k) {
-      const float pk = bcastf(a[k], p);
-      if (act) a[k] = fmaf(-l, pk, a[k]);
-    }
+    for (int k = c + 1; k < N; ++k) a[k] = fmaf(-l, bcastf(a[k], p), a[k]);
   }
   double rvv[3] = {0.0, 0.0, 0.0};
   if (rowvec) { rvv[0] = rowvec[row]; rvv[1] = rowvec[m + row]; rvv[2] = rowvec[2 * m + row]; }
@@ -350,12 +352,9 @@ __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(pcol == c)));
-        const bool act = pcol > c;
+        const float mc = pcol > c ? a[c] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const float y = bcastf(rf[r], p);
-          if (act) rf[r] = fmaf(-a[c], y, rf[r]);
-        }
+        for (int r = 0; r < RB; ++r) rf[r] = fmaf(-mc, bcastf(rf[r], p), rf[r]);
       }
       float d[RB];
 #pragma unroll
@@ -363,12 +362,12 @@ __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int
 #pragma unroll
       for (int c = N - 1; c >= 0; --c) {
         const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(pcol == c)));
-        const bool act = pcol < c;
+        const float uc = pcol < c ? a[c] : 0.0f;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const float xc = bcastf(rf[r] / a[c], p);
+          const float xc = bcastf(rf[r] * dinv, p);
           if (lane == c) d[r] = xc;
-          if (act) rf[r] = fmaf(-a[c], xc, rf[r]);
+          rf[r] = fmaf(-uc, xc, rf[r]);
         }
       }
       double dmax = 0.0, xmax = 0.0;
