@@ -448,6 +448,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
+    ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
     ap.add_argument("--weights-batch", action="store_true",
                     help="only measure the batched weight solve of 8 cells (about 18M rows) and exit")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -469,8 +470,11 @@ def main():
         import multiprocessing as mp
         # node clouds are filled in worker processes before this process
         # touches the GPU
-        with mp.get_context("fork").Pool(6) as pool:
-            cells = pool.map(_sweep_cell, [(r,) for r in (0.2, 0.3, 0.4, 0.5, 0.55, 0.6)])
+        if len(args.acm_sweep_radii) == 1:  # one cell: no worker processes (profiler runs)
+            cells = [_sweep_cell((args.acm_sweep_radii[0],))]
+        else:
+            with mp.get_context("fork").Pool(min(6, len(args.acm_sweep_radii))) as pool:
+                cells = pool.map(_sweep_cell, [(r,) for r in args.acm_sweep_radii])
         print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
         torch.cuda.set_device(0)
         print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
