@@ -1,6 +1,6 @@
 """The learned warm start end to end on small cells: train the MLP on steady
 MLBM fields of ten cells, then start both solvers on a held-out cell from its
-prediction.  The cold-started solver is the judge: both runs must settle on
+prediction.  The cold-started solver is the reference: both runs must settle on
 the same k, and the warm run must enter the 1e-3 band around it in far fewer
 steps."""
 import sys
