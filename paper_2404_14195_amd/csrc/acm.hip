@@ -3,7 +3,8 @@
 //
 // Every pass is a stencil apply: weights and stencil indices are stored
 // [op][j][node], field values are gathered through the caches (nodes are
-// Morton ordered).  A step is 1 + 3 n_p dependent passes:
+// Morton ordered; a run keeps v and v' as node records [n][4], so a gathered
+// velocity is one record).  A step is 1 + 3 n_p dependent passes:
 //   predictor  (interior)     v' from v: 4 operators x 3 components
 //   n_p x { pressure (interior)  p -= dt C^2 rho div v
 //           neumann  (boundary)  p_b from dp/dn = 0, in place (its stencil
@@ -49,6 +50,51 @@ __device__ __forceinline__ void columns(int nl, int j0, int sl, Body&& body) {
   }
 }
 
+// Velocity records [n][4] = (x, y, z, 0): a gathered neighbour costs one
+// 16-byte (FP32) or two 16-byte (FP64) loads from one line instead of three
+// loads from three lines of a [3][n] layout.
+template <typename T>
+struct Rec;
+template <>
+struct Rec<float> {
+  using type = float4;
+};
+template <>
+struct Rec<double> {
+  using type = double4;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Rec<T>::type load4(const T* __restrict__ R, int64_t i) {
+  return reinterpret_cast<const typename Rec<T>::type*>(R)[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T* __restrict__ R, int64_t i, T x, T y, T z) {
+  typename Rec<T>::type r;
+  r.x = x;
+  r.y = y;
+  r.z = z;
+  r.w = T(0);
+  reinterpret_cast<typename Rec<T>::type*>(R)[i] = r;
+}
+
+template <typename T>
+__global__ void to_records(int64_t n, const T* __restrict__ v, T* __restrict__ R) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) store4(R, i, v[i], v[n + i], v[2 * n + i]);
+}
+
+template <typename T>
+__global__ void from_records(int64_t n, const T* __restrict__ R, T* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const auto r = load4(R, i);
+  v[i] = r.x;
+  v[n + i] = r.y;
+  v[2 * n + i] = r.z;
+}
+
 template <typename T, typename TW>
 struct Fields {
   int64_t n, n_int, nb;
@@ -57,9 +103,9 @@ struct Fields {
   const TW* w;  // [4][nl][n]
   const int32_t* sn;
   const TW* wn;  // [nl][nb]
-  T* v;         // [3][n]
+  T* V;         // [n][4] velocity records (x, y, z, 0), the run's working copy of v
   T* p;         // [n]
-  T* vp;        // [3][n]
+  T* VP;        // [n][4] v' records
   double* vmax;
   T nu, dt, dt_rho, g0, g1, g2;
   double dtd, rho, beta, v_ref;
@@ -78,7 +124,8 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
     const int64_t at = (int64_t)j * n + i;
     const int s = F.sten[at];
     const T wx = (T)F.w[at], wy = (T)F.w[os + at], wz = (T)F.w[2 * os + at], wl = (T)F.w[3 * os + at];
-    const T u[3] = {F.v[s], F.v[n + s], F.v[2 * n + s]};
+    const auto r = load4(F.V, s);  // one node's velocity: one record, one or two vector loads
+    const T u[3] = {r.x, r.y, r.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       d[a][0] += wx * u[a];
@@ -92,13 +139,16 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
 #pragma unroll
     for (int o = 0; o < 4; ++o) d[a][o] = group_sum<LPN>(d[a][o]);
   if (sl == 0) {
-    const T vi[3] = {F.v[i], F.v[n + i], F.v[2 * n + i]};
+    const auto ri = load4(F.V, i);
+    const T vi[3] = {ri.x, ri.y, ri.z};
     const T g[3] = {F.g0, F.g1, F.g2};
+    T out[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const T adv = vi[0] * d[a][0] + vi[1] * d[a][1] + vi[2] * d[a][2];
-      F.vp[a * n + i] = vi[a] + F.dt * (F.nu * d[a][3] - adv + g[a]);
+      out[a] = vi[a] + F.dt * (F.nu * d[a][3] - adv + g[a]);
     }
+    store4(F.VP, i, out[0], out[1], out[2]);
   }
 }
 
@@ -110,8 +160,8 @@ __device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* _
   T div = T(0);
   columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
-    const int s = F.sten[at];
-    div += (T)F.w[at] * vsrc[s] + (T)F.w[os + at] * vsrc[n + s] + (T)F.w[2 * os + at] * vsrc[2 * n + s];
+    const auto r = load4(vsrc, F.sten[at]);
+    div += (T)F.w[at] * r.x + (T)F.w[os + at] * r.y + (T)F.w[2 * os + at] * r.z;
   });
   div = group_sum<LPN>(div);
   if (sl == 0) F.p[i] -= coef * div;
@@ -143,13 +193,16 @@ __device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, int64_t 
     gp[2] += (T)F.w[2 * os + at] * ps;
   });
   double m2 = 0.0;
+  const auto rp = load4(F.VP, i);
+  const T vpi[3] = {rp.x, rp.y, rp.z};
+  T va[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     gp[a] = group_sum<LPN>(gp[a]);
-    const T va = F.vp[a * n + i] - F.dt_rho * gp[a];
-    if (sl == 0) F.v[a * n + i] = va;
-    m2 += (double)va * (double)va;
+    va[a] = vpi[a] - F.dt_rho * gp[a];
+    m2 += (double)va[a] * (double)va[a];
   }
+  if (sl == 0) store4(F.V, i, va[0], va[1], va[2]);
   return sqrt(m2);
 }
 
@@ -228,7 +281,7 @@ int run_launches(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
   for (int s = 0; s < n_steps; ++s) {
     hipLaunchKernelGGL((k_predictor<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
     for (int it = 0; it < n_p; ++it) {
-      hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.vp : F.v));
+      hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.VP : F.V));
       hipLaunchKernelGGL((k_neumann<T, TW, LPN, NLC>), dim3(gb), dim3(kBlock), 0, st, F);
       hipLaunchKernelGGL((k_velocity<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
     }
@@ -249,25 +302,32 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
         const int32_t* sn, const TW* wn, T* v, T* p, double* vmax, int n_steps, void* ws, hipStream_t st) {
   Fields<T, TW> F;
   F.n = n; F.n_int = n_int; F.nb = n - n_int; F.nl = nl;
-  F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.v = v; F.p = p;
-  F.vp = reinterpret_cast<T*>(ws);
+  F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.p = p;
+  F.V = reinterpret_cast<T*>(ws);
+  F.VP = F.V + 4 * n;
   F.vmax = vmax;
   F.nu = (T)prm->nu; F.dt = (T)prm->dt; F.dt_rho = (T)(prm->dt / prm->rho);
   F.g0 = (T)prm->g[0]; F.g1 = (T)prm->g[1]; F.g2 = (T)prm->g[2];
   F.dtd = prm->dt; F.rho = prm->rho; F.beta = prm->beta; F.v_ref = prm->v_ref;
-  // v' is zero on the boundary for the whole run
-  if (F.nb > 0)
-    for (int a = 0; a < 3; ++a)
-      hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(F.nb, kBlock)), dim3(kBlock), 0, st, F.vp + a * n + n_int, F.nb);
+  // the run works on node records: v [3][n] -> V [n][4] now and back at the
+  // end; v' is zero on the boundary for the whole run
+  const unsigned gn = grid_for(n, kBlock);
+  hipLaunchKernelGGL(to_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)v, F.V);
+  hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(4 * n, kBlock)), dim3(kBlock), 0, st, F.VP, 4 * n);
   int lanes = prm->lanes;
   if (lanes == 0) lanes = n_int <= kFewNodes ? 8 : 2;
+  int rc;
   switch (lanes) {
-    case 1: return launch_nl<T, TW, 1>(F, n_steps, prm->n_p, st);
-    case 2: return launch_nl<T, TW, 2>(F, n_steps, prm->n_p, st);
-    case 4: return launch_nl<T, TW, 4>(F, n_steps, prm->n_p, st);
-    case 8: return launch_nl<T, TW, 8>(F, n_steps, prm->n_p, st);
-    default: return launch_nl<T, TW, 16>(F, n_steps, prm->n_p, st);
+    case 1: rc = launch_nl<T, TW, 1>(F, n_steps, prm->n_p, st); break;
+    case 2: rc = launch_nl<T, TW, 2>(F, n_steps, prm->n_p, st); break;
+    case 4: rc = launch_nl<T, TW, 4>(F, n_steps, prm->n_p, st); break;
+    case 8: rc = launch_nl<T, TW, 8>(F, n_steps, prm->n_p, st); break;
+    default: rc = launch_nl<T, TW, 16>(F, n_steps, prm->n_p, st); break;
   }
+  if (rc) return rc;
+  hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.V, v);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
 }
 
 }  // namespace
@@ -275,7 +335,7 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
 
 extern "C" size_t mpf_acm_workspace(int64_t n, int precision) {
   const size_t es = precision == MPF_F32 ? sizeof(float) : sizeof(double);
-  return n > 0 ? 3 * (size_t)n * es + 256 : 256;
+  return n > 0 ? 8 * (size_t)n * es + 256 : 256;  // V and V' records [n][4]
 }
 
 extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
