@@ -71,25 +71,30 @@ __device__ __forceinline__ void collide(T (&f)[Q], const Prm<T>& pr) {
   const T u0 = j0 * ir, u1 = j1 * ir, u2 = j2 * ir;
   const T uu = u0 * u0 + u1 * u1 + u2 * u2;
   const T F0 = rho * pr.g0, F1 = rho * pr.g1, F2 = rho * pr.g2;
-  T feq[Q], Fk[Q];
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    const T eu = T(L::ex[k]) * u0 + T(L::ey[k]) * u1 + T(L::ez[k]) * u2;
-    const T wk = (T)lat_w<Q>(k);
-    // f^eq_k - w_k = w_k (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu))
-    feq[k] = wk * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu));
-    Fk[k] = T(3) * wk * (T(L::ex[k]) * F0 + T(L::ey[k]) * F1 + T(L::ez[k]) * F2);
-  }
-  T out[Q];
+  // each opposite pair (k, kb) is relaxed together and in place: the TRT
+  // update of f_k involves only f_k and f_kb, so no full f^eq, F or output
+  // arrays stay live (fewer registers for the FP64 state)
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int kb = lat_opp(k);
-    const T fp = T(0.5) * (f[k] + f[kb]), fm = T(0.5) * (f[k] - f[kb]);
-    const T ep = T(0.5) * (feq[k] + feq[kb]), em = T(0.5) * (feq[k] - feq[kb]);
-    out[k] = f[k] - (fp - ep) * pr.itp - (fm - em) * pr.itm + Fk[k];
+    if (kb < k) continue;
+    const T wk = (T)lat_w<Q>(k);
+    const T eu = T(L::ex[k]) * u0 + T(L::ey[k]) * u1 + T(L::ez[k]) * u2;
+    const T ebu = T(L::ex[kb]) * u0 + T(L::ey[kb]) * u1 + T(L::ez[kb]) * u2;
+    // f^eq_k - w_k = w_k (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu))
+    const T feq = wk * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu));
+    const T feqb = wk * (drho + rho * (T(3) * ebu + T(4.5) * ebu * ebu - T(1.5) * uu));
+    const T Fk = T(3) * wk * (T(L::ex[k]) * F0 + T(L::ey[k]) * F1 + T(L::ez[k]) * F2);
+    const T Fkb = T(3) * wk * (T(L::ex[kb]) * F0 + T(L::ey[kb]) * F1 + T(L::ez[kb]) * F2);
+    const T fk = f[k], fb = f[kb];
+    const T fp = T(0.5) * (fk + fb), fm = T(0.5) * (fk - fb);
+    const T ep = T(0.5) * (feq + feqb), em = T(0.5) * (feq - feqb);
+    f[k] = fk - (fp - ep) * pr.itp - (fm - em) * pr.itm + Fk;
+    if (kb != k) {
+      const T fmb = T(0.5) * (fb - fk), emb = T(0.5) * (feqb - feq);
+      f[kb] = fb - (fp - ep) * pr.itp - (fmb - emb) * pr.itm + Fkb;
+    }
   }
-#pragma unroll
-  for (int k = 0; k < Q; ++k) f[k] = out[k];
 }
 
 // src may equal dst: each thread reads and writes only its own node
