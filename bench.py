@@ -265,6 +265,55 @@ def acm_sweep(torch, cells, steps=2000):
     return out
 
 
+def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
+    """The paper's comparison of the two solvers on identical nodes: the
+    71k-node cell, MLBM and ACM (both FP32 weights, FP64 state) started from
+    the learned prediction and run until k changes by < 1e-8 relative per
+    check; reports k, drag K and the field differences."""
+    import numpy as np
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver
+    say = lambda m: print(f"[bench] cross-validation: {m}", file=sys.stderr, flush=True)
+    disc = Discretization(nc.config_cloud("lbm_mid"), nl=30, M=64)
+    out = {}
+    for name, make, check in (("mlbm", lambda: MLBMSolver(disc, q=19, precision=MPF_MIXED), 500),
+                              ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED), 5000)):
+        s = make()
+        (ws_model.load_mlbm if name == "mlbm" else ws_model.load_acm)(s)
+        t0 = time.perf_counter()
+        ks = []
+        while s.steps < max_acm_steps:
+            s.run(check)
+            ks.append(s.permeability())
+            if len(ks) > 2 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1]):
+                break
+            if len(ks) % 40 == 0:
+                say(f"{name} {s.steps} steps, k = {ks[-1]:.8e}")
+        F, K = s.drag()
+        if name == "mlbm":
+            v, p = s.macros()
+            v = v.clone()
+            p = p.clone()
+        else:
+            v, p = s.v.double().clone(), s.p.double().clone()
+        out[name] = {"k": ks[-1], "K": float(K), "steps": s.steps, "seconds": time.perf_counter() - t0,
+                     "settled": len(ks) > 2 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1]),
+                     "_v": v.cpu().numpy(), "_p": p.cpu().numpy()}
+        say(f"{name}: k = {ks[-1]:.8e}, K = {float(K):.6f} after {s.steps} steps ({out[name]['seconds']:.1f}s)")
+        del s
+    n_int = disc.n_int
+    vm, va = out["mlbm"].pop("_v")[:, :n_int], out["acm"].pop("_v")[:, :n_int]
+    pm, pa = out["mlbm"].pop("_p"), out["acm"].pop("_p")
+    pm, pa = pm - pm.mean(), pa - pa.mean()
+    out["k_rel_diff"] = abs(out["mlbm"]["k"] / out["acm"]["k"] - 1)
+    out["K_rel_diff"] = abs(out["mlbm"]["K"] / out["acm"]["K"] - 1)
+    out["v_rel_l2_diff"] = float(np.linalg.norm(vm - va) / np.linalg.norm(va))
+    out["v_max_diff_over_max_v"] = float(np.abs(vm - va).max() / np.abs(va).max())
+    out["p_rel_l2_diff"] = float(np.linalg.norm(pm - pa) / np.linalg.norm(pa))
+    say(json.dumps(out))
+    return out
+
+
 def _batch_cell(args):
     import nodecloud as nc
     r, h0, seed = args
@@ -447,6 +496,7 @@ def main():
     ap.add_argument("--no-steady", action="store_true", help="skip the time-to-steady measurement")
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
+    ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
     ap.add_argument("--weights-batch", action="store_true",
@@ -478,6 +528,11 @@ def main():
         print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
         torch.cuda.set_device(0)
         print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
+        return
+    if args.cross_validate:
+        torch.cuda.set_device(0)
+        ws_model, info = train_warm_start(torch, nc)
+        print(json.dumps({"cross_validation": cross_validate(torch, nc, ws_model), "warm_start_training": info}))
         return
     if args.mlp:
         torch.cuda.set_device(0)
