@@ -66,10 +66,10 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
         t0 = time.perf_counter()
         ks, ts, ns = [], [], []
         if init is not None:
-            init(s)  # the prediction is checked before any step
+            init(s)  # the prediction (and its burn-in) is checked before further steps
             ks.append(s.permeability())
             ts.append(time.perf_counter() - t0)
-            ns.append(0)
+            ns.append(s.steps)
         while s.steps < max_steps:
             s.run(check)
             k = s.permeability()  # one device-to-host double per check
@@ -109,7 +109,7 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
                      "first_entry_steps": None if entry is None else ns[entry],
                      "max_rel_err_after_entry": None if entry is None else max(abs(k / k_inf - 1) for k in ks[entry:]),
                      "settled_after_steps": ns[-1], "settled_k": ks[-1],
-                     "settled_rel_err": abs(ks[-1] - k_inf) / abs(k_inf), "initial_k": ks[0] if ns[0] == 0 else 0.0}
+                     "settled_rel_err": abs(ks[-1] - k_inf) / abs(k_inf), "initial_k": ks[0] if name.endswith("_warm") else 0.0}
     base = out["fp64"]["seconds"]
     for name in runs:
         if name != "fp64" and out[name]["seconds"]:

@@ -272,6 +272,9 @@ int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double 
  * q_out dev double[1].  The sum is a fixed-order FP64 tree, so results are
  * bitwise reproducible. */
 size_t mpf_reduce_workspace(int64_t n_items);
+/* x[i] *= c for i < n; x dev, double (MPF_F64) or float (MPF_F32).  Used to
+ * rescale a velocity field to a target flux (the warm start's flux match). */
+int mpf_scale(int64_t n, void* x, int precision, double c, void* stream);
 int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx, int precision,
                     int64_t n_all, double* q_out, void* ws, size_t ws_bytes, void* stream);
 

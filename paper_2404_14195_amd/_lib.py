@@ -115,6 +115,7 @@ def _load():
         "mpf_gemm_bf16": (i32, [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp]),
         "mpf_mlp_train_workspace": (sz, [vp, i64]),
         "mpf_shuffle_rows": (i32, [i64, i64, ctypes.c_uint64, vp, vp]),
+        "mpf_scale": (i32, [i64, vp, i32, dbl, vp]),
         "mpf_mlp_train": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i32, flt, flt, flt, flt, flt, vp, vp,
                                 sz, vp]),
     }
@@ -142,7 +143,7 @@ EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace
             "mpf_flux_planes", "mpf_drag", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
             "mpf_mlp_pack", "mpf_mlp_forward", "mpf_mlp_backward", "mpf_mlp_mse", "mpf_adam_step",
             "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16", "mpf_mlp_train_workspace", "mpf_mlp_train",
-            "mpf_shuffle_rows"]
+            "mpf_shuffle_rows", "mpf_scale"]
 
 
 def check(rc: int, what: str):

@@ -360,3 +360,8 @@ def shuffle_rows(n: int, count: int, seed: int, rows=None, device="cuda"):
     check(lib().mpf_shuffle_rows(int(n), int(count), int(seed) & (2 ** 64 - 1), _p(rows), _stream()),
           "mpf_shuffle_rows")
     return rows
+
+
+def scale(x, c: float):
+    """x *= c in place (float32 or float64, any shape, contiguous)."""
+    check(lib().mpf_scale(x.numel(), _p(x), precision_of(x.dtype), float(c), _stream()), "mpf_scale")

@@ -104,6 +104,30 @@ extern "C" size_t mpf_reduce_workspace(int64_t n_items) {
   return (size_t)(3 * nblk + 8) * sizeof(double) + 256;
 }
 
+namespace mpf {
+namespace {
+template <typename T>
+__global__ void scale_kernel(int64_t n, T* __restrict__ x, T c) {
+  const int64_t i = (int64_t)blockIdx.x * kRBlock + threadIdx.x;
+  if (i < n) x[i] *= c;
+}
+}  // namespace
+}  // namespace mpf
+
+extern "C" int mpf_scale(int64_t n, void* x, int precision, double c, void* stream) {
+  using namespace mpf;
+  if (!x || n < 0) return MPF_ERR_ARG;
+  if (precision != MPF_F64 && precision != MPF_F32) return MPF_ERR_ARG;
+  if (n == 0) return MPF_OK;
+  hipStream_t st = as_stream(stream);
+  if (precision == MPF_F64)
+    hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(n, kRBlock)), dim3(kRBlock), 0, st, n, (double*)x, c);
+  else
+    hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n, kRBlock)), dim3(kRBlock), 0, st, n, (float*)x, (float)c);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
 extern "C" int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx,
                                int precision, int64_t n_all, double* q_out, void* ws, size_t ws_bytes,
                                void* stream) {

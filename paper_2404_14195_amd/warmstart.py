@@ -199,19 +199,48 @@ class WarmStart:
         if q > 0.0 and math.isfinite(q):
             api.mlp_to_state(y, disc.n_int, U * U / q, P, v, p, vmax, disc.red_ws)
 
-    def load_acm(self, solver):
-        """Warm-start an ACMSolver in place (v, p and the running max |v|)."""
+    def _flux_factor(self, disc, vx):
+        """U / q for the current x-velocity, or None if q is not usable."""
+        U, _ = self.scales(disc.cloud.r)
+        q = float(api.flux_planes(disc.s_idx, disc.s_w, vx, disc.n_all, ws=disc.red_ws).item())
+        return U / q if q > 0.0 and math.isfinite(q) else None
+
+    def load_acm(self, solver, burn_in: int = 1000):
+        """Warm-start an ACMSolver in place (v, p and the running max |v|).
+
+        After burn_in steps the velocity is rescaled once more so that its
+        flux equals U: the prediction's shape error relaxes through fast modes
+        in those steps and shifts the flux, and the slowest mode of the
+        approach to steady state has the shape of the steady flow itself, so a
+        uniform rescaling removes what the shift left in it.  solver.steps
+        counts the burn-in."""
         self.state(solver.d, solver.v, solver.p, solver.vmax)
         solver.steps = 0
+        if burn_in > 0:
+            solver.run(burn_in)
+            c = self._flux_factor(solver.d, solver.v[0])
+            if c is not None:
+                api.scale(solver.v, c)
+                api.scale(solver.vmax, c)
 
-    def load_mlbm(self, solver):
+    def load_mlbm(self, solver, burn_in: int = 1000):
         """Warm-start an MLBMSolver: equilibrium populations of the predicted
-        fields."""
+        fields, then after burn_in steps the same flux match as load_acm (the
+        populations are rebuilt as the equilibrium of the rescaled
+        velocity and the current pressure).  solver.steps counts the burn-in."""
         d = solver.d
         v = torch.empty((3, d.n), dtype=torch.float64, device=self.device)
         p = torch.empty(d.n, dtype=torch.float64, device=self.device)
         self.state(d, v, p)
         solver.set_fields(v, p)
+        if burn_in > 0:
+            solver.run(burn_in)
+            v, p = solver.macros()
+            c = self._flux_factor(d, v[0])
+            if c is not None:
+                api.scale(v, c)
+                solver.set_fields(v, p)
+            solver.steps = burn_in
 
     # ------------------------------------------------------------ persistence
     def state_dict(self):

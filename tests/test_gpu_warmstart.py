@@ -31,7 +31,7 @@ def announce(request):
 
 def trajectory(solver, stop_rel=1e-7, check=500, max_steps=400_000):
     """(steps, k) per check, from the current state until k settles."""
-    ns, ks = [0], [solver.permeability()]
+    ns, ks = [solver.steps], [solver.permeability()]
     while solver.steps < max_steps:
         solver.run(check)
         ns.append(solver.steps)
@@ -82,7 +82,10 @@ def test_warm_start_mlbm(trained, held_out):
     cold = MLBMSolver(held_out, q=19, precision=MPF_MIXED)
     nc_, kc = trajectory(cold)
     warm = MLBMSolver(held_out, q=19, precision=MPF_MIXED)
-    trained.load_mlbm(warm)
+    trained.load_mlbm(warm)  # prediction, 1000 steps, flux matched again
+    assert warm.steps == 1000
+    U, _ = trained.scales(HELD_OUT_R)
+    assert warm.permeability() == pytest.approx(U, rel=1e-9)  # nu = |g| = 1: k equals the target flux
     nw, kw = trajectory(warm)
     k_ref = kc[-1]
     sc, sw = steps_to_band(nc_, kc, k_ref), steps_to_band(nw, kw, k_ref)
@@ -110,7 +113,7 @@ def test_warm_start_acm(trained, held_out):
     trained.load_acm(warm)
     assert warm.vmax.item() > 0 and not warm.v[:, held_out.n_int:].any()
     k_w0 = warm.permeability()
-    warm.run(20_000)
+    warm.run(20_000 - warm.steps)  # the burn-in of the warm start counts
     k_w20 = warm.permeability()
     print(f"[warm-start acm] k(200k cold)={k_ref:.8e}; at 20k steps: cold {k_c20:.8e} (rel {abs(k_c20 / k_ref - 1):.2e})"
           f", warm {k_w20:.8e} (rel {abs(k_w20 / k_ref - 1):.2e}); warm initial {k_w0:.8e}", flush=True)

@@ -106,3 +106,10 @@ def test_mlp_host_queries_and_checks(lib):
     assert lib.mpf_adam_step(10, fake, fake, fake, fake, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -1
     assert lib.mpf_gemm_bf16(4, 4, 40, fake, 40, fake, 40, fake, 4, None) == -1  # K not a multiple of 32
     assert lib.mpf_mlp_to_state(10, 11, fake, 1.0, 1.0, 0, fake, fake, None, fake, 1 << 20, None) == -1
+
+
+def test_scale_host_checks(lib):
+    fake = ctypes.c_void_p(256)
+    assert lib.mpf_scale(10, None, 0, 2.0, None) == -1
+    assert lib.mpf_scale(10, fake, 2, 2.0, None) == -1  # only FP64 or FP32 arrays
+    assert lib.mpf_scale(0, fake, 0, 2.0, None) == 0    # nothing to do, nothing launched
