@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libmpf_oracle.so")
 _lib = None
 
-OPS = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shift_row": 7}
+OPS = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shift_row": 7, "taylor": 8}
 
 
 def build(force: bool = True) -> str:
@@ -55,6 +55,8 @@ def _load():
         lib.mpfo_lbm_moments.argtypes = [i32, i64, vp, vp, vp]
         lib.mpfo_lbm_run.restype = i32
         lib.mpfo_lbm_run.argtypes = [i32, i64, i64, i32, vp, vp, vp, dbl, dbl, vp, vp, i32]
+        lib.mpfo_lbm_unknown.restype = i32
+        lib.mpfo_lbm_unknown.argtypes = [i32, i64, vp, vp, i32, dbl, dbl, vp]
         lib.mpfo_flux.restype = dbl
         lib.mpfo_flux.argtypes = [i64, i32, vp, vp, vp, i64]
         lib.mpfo_drag.restype = None
@@ -167,11 +169,33 @@ def lbm_units(h_min: float, nu: float, tau_plus: float, g, magic: float):
     return dict(dx=dx, dt=dt, nu_lb=nu_lb, g_lb=g_lb, tau_minus=tau_minus)
 
 
+UNKNOWN_RULES = {"normal": 0, "solid": 1}
+
+
+def lbm_unknown(q, pos_b, nrm, rule="normal", dx=0.0, r=0.0):
+    """Bit mask [nb] of the unknown populations of each boundary node: by the
+    local normal (Sec. 2.2) or by testing the departure point against the
+    solid (Sec. 3.3, the touching limit)."""
+    pos_b = _c(pos_b, np.float64).reshape(-1, 3)
+    nrm = _c(nrm, np.float64).reshape(-1, 3)
+    mask = np.zeros(len(pos_b), dtype=np.uint32)
+    if len(mask) and _load().mpfo_lbm_unknown(q, len(mask), pos_b.ctypes.data, nrm.ctypes.data, UNKNOWN_RULES[rule],
+                                              float(dx), float(r), mask.ctypes.data):
+        raise ValueError("mpfo_lbm_unknown: bad q, rule or dx")
+    return mask
+
+
 class MLBM:
-    """Meshless TRT LBM state on one node cloud."""
+    """Meshless TRT LBM state on one node cloud.
+
+    streaming "shift" interpolates each population at its departure point
+    x_i - dx e_k (Eq. LBM_streaming, L = 1); "taylor" takes the first-order
+    estimate f - dx e_k . grad f there instead.  rule picks the unknown
+    populations of boundary nodes (lbm_unknown); "solid" needs the grain
+    radius r."""
 
     def __init__(self, pos, n_int, sten, nrm, q=19, h_min=None, nu=1.0, tau_plus=1.0, magic=0.25, g=(1.0, 0.0, 0.0),
-                 dx=None):
+                 dx=None, streaming="shift", rule="normal", r=None):
         self.pos, self.n_int, self.sten, self.nrm = _c(pos, np.float64), int(n_int), _c(sten, np.int32), _c(nrm, np.float64)
         self.n, self.nl = self.sten.shape
         self.q = q
@@ -179,17 +203,22 @@ class MLBM:
         self.units = u
         self.tau_plus, self.tau_minus, self.g_lb = tau_plus, u["tau_minus"], u["g_lb"]
         e, _, _ = lattice(q)
+        if streaming not in ("shift", "taylor"):
+            raise ValueError(streaming)
         # departure point of population k: x_i - dx e_k
-        ops = [("shift", tuple(-u["dx"] * e[k])) for k in range(q)]
+        ops = [(streaming, tuple(-u["dx"] * e[k])) for k in range(q)]
         W, info = weights(self.pos, self.sten, ops)
         if info.any():
             raise ValueError("singular weight system")
         self.W = W
+        if rule == "solid" and r is None:
+            raise ValueError("the solid rule needs the grain radius r")
+        self.unknown = lbm_unknown(q, self.pos[self.n_int:], self.nrm, rule, u["dx"], r or 0.0)
         self.f = equilibrium(q, self.n, 1.0, (0.0, 0.0, 0.0))
 
     def run(self, n_steps: int):
         rc = _load().mpfo_lbm_run(self.q, self.n, self.n_int, self.nl, self.sten.ctypes.data, self.W.ctypes.data,
-                                  self.nrm.ctypes.data if len(self.nrm) else None, self.tau_plus, self.tau_minus,
+                                  self.unknown.ctypes.data, self.tau_plus, self.tau_minus,
                                   _c(self.g_lb, np.float64).ctypes.data, self.f.ctypes.data, int(n_steps))
         if rc != 0:
             raise RuntimeError("mpfo_lbm_run failed")
@@ -217,13 +246,15 @@ def moments(q, f):
     return rho, u
 
 
-def lbm_run(q, n_int, sten, W, nrm, tau_p, tau_m, g_lb, f, n_steps):
+def lbm_run(q, n_int, sten, W, unknown, tau_p, tau_m, g_lb, f, n_steps):
     sten = _c(sten, np.int32)
     W = _c(W, np.float64)
-    nrm = _c(nrm, np.float64)
+    unknown = _c(unknown, np.uint32)
+    if len(unknown) != sten.shape[0] - int(n_int):
+        raise ValueError("one mask per boundary node")
     rc = _load().mpfo_lbm_run(q, sten.shape[0], int(n_int), sten.shape[1], sten.ctypes.data, W.ctypes.data,
-                              nrm.ctypes.data if len(nrm) else None, tau_p, tau_m,
-                              _c(g_lb, np.float64).ctypes.data, f.ctypes.data, int(n_steps))
+                              unknown.ctypes.data, tau_p, tau_m, _c(g_lb, np.float64).ctypes.data, f.ctypes.data,
+                              int(n_steps))
     if rc != 0:
         raise RuntimeError("mpfo_lbm_run failed")
 

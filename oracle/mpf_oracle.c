@@ -59,7 +59,7 @@ double mpfo_area(double r) {
 
 /* ------------------------------------------------------------------ weights */
 
-enum { OP_DX = 0, OP_DY = 1, OP_DZ = 2, OP_LAP = 3, OP_DIR = 4, OP_SHIFT = 5, OP_DN = 6, OP_SHIFT_ROW = 7 };
+enum { OP_DX = 0, OP_DY = 1, OP_DZ = 2, OP_LAP = 3, OP_DIR = 4, OP_SHIFT = 5, OP_DN = 6, OP_SHIFT_ROW = 7, OP_TAYLOR = 8 };
 
 #define NP 10 /* monomials 1, x, y, z, x^2, xy, xz, y^2, yz, z^2 (m = 2, D = 3) */
 
@@ -123,6 +123,8 @@ static int solve_gepp(int n, int k, double* M, double* B) {
  *   OP_DX/DY/DZ  d/dx_a          OP_LAP     Laplacian
  *   OP_DIR       vec . grad      OP_DN      rowvec_i . grad (row normal)
  *   OP_SHIFT     value at x_i + vec         OP_SHIFT_ROW value at x_i + rowvec_i
+ *   OP_TAYLOR    value at x_i plus vec . grad (the first-order Taylor
+ *                estimate of the value at x_i + vec)
  * Output w[(i*n_ops + o)*nl + j]; info[i] = 0 or 1 + zero-pivot column. */
 int mpfo_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_t m, int nl, int n_ops,
                  const int32_t* kind, const double* vec, const double* rowvec, double* w, int32_t* info) {
@@ -184,6 +186,11 @@ int mpfo_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_
         case OP_DN:
           if (!rv) { bad = 2; break; }
           for (int a = 0; a < 3; ++a) rhs_axis(a, nl, xi, rho, delta, rv[a], col);
+          break;
+        case OP_TAYLOR: /* value at the centre (xi = 0) plus the directional derivative */
+          for (int j = 0; j < nl; ++j) col[j] = rho[j] * rho[j] * rho[j];
+          col[nl] = 1.0;
+          for (int a = 0; a < 3; ++a) rhs_axis(a, nl, xi, rho, delta, v[a], col);
           break;
         case OP_SHIFT: case OP_SHIFT_ROW: {
           const double* s = kind[o] == OP_SHIFT ? v : rv;
@@ -384,21 +391,62 @@ static void collide(int q, const double* e, const double* wk, const int32_t* opp
   }
 }
 
+/* Which populations of boundary node b are unknown after streaming, as a bit
+ * mask (bit k for population k; the rest population is never unknown).
+ *   rule 0 (Sec. 2.2, Eq. interpolated_bounceback_mlbm): the local normal
+ *     decides, e_k . n_b > 0 with n_b [nb][3] pointing into the fluid: the
+ *     departure point x_b - dx e_k is on the solid side of the tangent plane.
+ *   rule 1 (Sec. 3.3, the touching limit): the departure point itself is
+ *     tested, unknown when it lies inside the solid.  The solid is the union
+ *     of the balls of radius r centred at (1/2, 1/2, 1/2) + Z^3; for a point of
+ *     the unit cell moved by less than 1/2 the nearest centres are the 27
+ *     images with offsets in {-1, 0, 1}^3, and all of them are tested.
+ * pos_b [nb][3] boundary positions in the unit cell. */
+int mpfo_lbm_unknown(int q, int64_t nb, const double* pos_b, const double* nrm, int rule, double dx, double r,
+                     uint32_t* unknown) {
+  double e[3 * 19], wk[19];
+  int32_t opp[19];
+  if (mpfo_lattice(q, e, wk, opp) || rule < 0 || rule > 1) return -1;
+  if (rule == 1 && !(dx > 0.0 && dx < 0.5)) return -1;
+  for (int64_t b = 0; b < nb; ++b) {
+    uint32_t mask = 0;
+    for (int k = 1; k < q; ++k) {
+      int out = 0;
+      if (rule == 0) {
+        const double* nv = nrm + 3 * b;
+        out = e[3 * k] * nv[0] + e[3 * k + 1] * nv[1] + e[3 * k + 2] * nv[2] > 0.0;
+      } else {
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = pos_b[3 * b + a] - dx * e[3 * k + a];
+        for (int i = -1; i <= 1 && !out; ++i)
+          for (int j = -1; j <= 1 && !out; ++j)
+            for (int l = -1; l <= 1 && !out; ++l) {
+              double d0 = p[0] - (0.5 + i), d1 = p[1] - (0.5 + j), d2 = p[2] - (0.5 + l);
+              out = d0 * d0 + d1 * d1 + d2 * d2 < r * r;
+            }
+      }
+      if (out) mask |= 1u << k;
+    }
+    unknown[b] = mask;
+  }
+  return 0;
+}
+
 /* Meshless LBM (Sec. 2.2, MLBM algorithm of Appendix A), n_steps steps.
  *
  * f [n][q] holds the populations at the start of a step.  W[(i*q + k)*nl + j]
  * are, for each moving population k >= 1, the weights that interpolate a
  * field at the departure point of node i for that population (row k = 0 is
- * not read: the rest population does not move).  Boundary nodes
- * [n_int, n) carry normals nrm [nb][3] pointing into the fluid.
+ * not read: the rest population does not move).  Boundary nodes are
+ * [n_int, n); bit k of unknown[b] marks population k of boundary node
+ * n_int + b as unknown (mpfo_lbm_unknown gives the two rules).
  * Per step: collide on every node; stream each moving population by
  * interpolating its post-collision field at the departure point (Eq.
- * LBM_streaming with Eq. operatorApprox, L = 1); at boundary nodes a
- * population whose departure point lies on the solid side (e_k . n > 0) is
- * unknown and takes the value of its opposite (Eq.
+ * LBM_streaming with Eq. operatorApprox, L = 1); at boundary nodes an unknown
+ * population takes the value of its opposite (Eq.
  * interpolated_bounceback_mlbm). */
 int mpfo_lbm_run(int q, int64_t n, int64_t n_int, int nl, const int32_t* sten, const double* W,
-                 const double* nrm, double tau_p, double tau_m, const double* g_lb, double* f, int n_steps) {
+                 const uint32_t* unknown, double tau_p, double tau_m, const double* g_lb, double* f, int n_steps) {
   double e[3 * 19], wk[19];
   int32_t opp[19];
   if (mpfo_lattice(q, e, wk, opp)) return -1;
@@ -416,11 +464,9 @@ int mpfo_lbm_run(int q, int64_t n, int64_t n_int, int nl, const int32_t* sten, c
       }
     }
     for (int64_t i = n_int; i < n; ++i) {
-      const double* nb = nrm + 3 * (i - n_int);
-      for (int k = 1; k < q; ++k) {
-        double en = e[3 * k] * nb[0] + e[3 * k + 1] * nb[1] + e[3 * k + 2] * nb[2];
-        if (en > 0.0) f[i * q + k] = f[i * q + opp[k]];
-      }
+      const uint32_t mask = unknown[i - n_int];
+      for (int k = 1; k < q; ++k)
+        if (mask >> k & 1u) f[i * q + k] = f[i * q + opp[k]];
     }
   }
   free(fpost);

@@ -138,3 +138,98 @@ def test_rest_state_preserved_with_grain(small_cloud, small_stencils):
     f0 = m.f.copy()
     m.run(5)
     assert np.abs(m.f - f0).max() < 1e-14
+
+
+# --- unknown populations at boundary nodes (Sec. 2.2; Sec. 3.3 touching limit)
+
+def unknown_set(mask_b, q):
+    return [k for k in range(q) if mask_b >> k & 1]
+
+
+@pytest.mark.parametrize("q, n_diag, n_zero", [(19, 6, 6), (15, 7, 0)])
+def test_unknown_normal_rule_hand_cases(q, n_diag, n_zero):
+    """Counted by hand from the velocity sets: along +x the five velocities
+    with e_x = 1 leave from the solid side (one axis and four diagonals in
+    both lattices).  Along the cube diagonal the ones with e_x + e_y + e_z > 0
+    do: D3Q19 has 3 axes + 3 face diagonals, and 6 face diagonals with zero
+    sum that stay known in both directions; D3Q15 has 3 axes + 4 corners."""
+    e, _, opp = O.lattice(q)
+    nrm = np.array([[1.0, 0.0, 0.0], [1.0, 1.0, 1.0]]) / np.array([[1.0], [np.sqrt(3.0)]])
+    m = O.lbm_unknown(q, np.zeros((2, 3)), nrm, "normal")
+    ks = unknown_set(int(m[0]), q)
+    assert len(ks) == 5 and all(e[k, 0] == 1 for k in ks)
+    ks = unknown_set(int(m[1]), q)
+    assert len(ks) == n_diag and all(e[k].sum() > 0 for k in ks)
+    zero = [k for k in range(1, q) if not (m[1] >> k & 1) and not (m[1] >> opp[k] & 1)]
+    assert len(zero) == n_zero
+
+
+@pytest.mark.parametrize("q", [15, 19])
+def test_unknown_normal_rule_one_of_each_pair(small_cloud, q):
+    """For a generic normal exactly one population of each opposite pair
+    departs from the solid side, and the rest population never does."""
+    c = small_cloud
+    _, _, opp = O.lattice(q)
+    m = O.lbm_unknown(q, c.pos[c.n_int:], c.nrm, "normal")
+    assert not (m & 1).any()
+    for k in range(1, q):
+        assert ((m >> k & 1) ^ (m >> opp[k] & 1)).all()
+
+
+def test_unknown_solid_rule_single_grain_closed_form(small_cloud):
+    """A node x on the sphere |x - c| = r with outward normal n: |x - dx e - c|^2
+    = r^2 - 2 dx r (e . n) + dx^2 |e|^2, so the departure point is inside the
+    grain iff e . n > dx |e|^2 / (2 r).  Below r = 1/2 no other image reaches
+    the cell, so this must be the whole solid rule."""
+    c = small_cloud
+    assert c.r < 0.5
+    dx = 0.013
+    e, _, _ = O.lattice(19)
+    m = O.lbm_unknown(19, c.pos[c.n_int:], c.nrm, "solid", dx, c.r)
+    en = c.nrm @ e.T  # [nb][q]
+    thr = dx * (e * e).sum(1) / (2 * c.r)
+    decided = np.abs(en - thr) > 1e-9
+    expect = (en > thr)
+    got = (m[:, None] >> np.arange(19)[None, :] & 1).astype(bool)
+    assert decided[:, 1:].mean() > 0.99
+    assert (got == expect)[decided].all()
+    # and the two rules differ only at near-tangent velocities, 0 < e . n <= thr
+    mn = O.lbm_unknown(19, c.pos[c.n_int:], c.nrm, "normal")
+    diff = ((m ^ mn)[:, None] >> np.arange(19)[None, :] & 1).astype(bool)
+    assert diff.any() and ((en > 0) & (en <= thr + 1e-9))[diff].all()
+
+
+def test_unknown_solid_rule_overlapping_grains_against_kdtree():
+    """For r > 1/2 the neighbouring images of the grain reach into the cell.
+    The periodic distance from the departure point to the nearest grain centre,
+    from scipy's periodic k-d tree, decides independently; and some departure
+    points of the overlapping cell fall into a neighbouring image while their
+    own normal says fluid side (the case the rule is for)."""
+    from scipy.spatial import cKDTree
+    r, dx = 0.52, 0.02
+    c = nc.sphere_cloud(r, 0.04, 0.3, 0.08, seed=7)
+    e, _, _ = O.lattice(19)
+    pb = c.pos[c.n_int:]
+    m = O.lbm_unknown(19, pb, c.nrm, "solid", dx, r)
+    tree = cKDTree(np.array([[0.5, 0.5, 0.5]]), boxsize=1.0)
+    got = (m[:, None] >> np.arange(19)[None, :] & 1).astype(bool)
+    dep = pb[:, None, :] - dx * e[None, :, :]  # [nb][q][3]
+    d, _ = tree.query(np.mod(dep.reshape(-1, 3), 1.0))
+    d = d.reshape(len(pb), 19)
+    decided = np.abs(d - r) > 1e-12
+    decided[:, 0] = True
+    expect = d < r
+    expect[:, 0] = False
+    assert (got == expect)[decided].all()
+    en = c.nrm @ e.T
+    assert (got & (en < 0)).any()
+
+
+def test_rest_state_preserved_with_solid_rule():
+    """Bounce-back swaps equal populations at rest under either rule."""
+    c = nc.sphere_cloud(0.52, 0.04, 0.3, 0.08, seed=7)
+    S = nc.solver_stencils(c, 30)
+    m = O.MLBM(c.pos, c.n_int, S, c.nrm, q=15, h_min=c.h_min, magic=1.0, g=(0, 0, 0), rule="solid", r=c.r)
+    f0 = m.f.copy()
+    m.run(3)
+    assert np.abs(m.f - f0).max() < 1e-14

@@ -25,6 +25,8 @@ def target(op, vec):
     if op in ("shift", "shift_row"):
         s = np.asarray(vec, dtype=float)
         return np.array([f(s[0], s[1], s[2]) for f in MONO])
+    if op == "taylor":  # p(0) + vec . grad p(0): the constant and the linear monomials only
+        return np.array([1, vec[0], vec[1], vec[2], 0, 0, 0, 0, 0, 0.0])
     raise ValueError(op)
 
 
@@ -49,7 +51,8 @@ def test_monomial_exactness_all_operators(small_cloud, small_stencils):
     rng = np.random.default_rng(0)
     rowvec = rng.normal(size=(len(rows), 3)) * 0.01
     e = np.array([0.3, -0.5, 0.8])
-    ops = [("dx",), ("dy",), ("dz",), ("lap",), ("dir", e), ("shift", (0.004, -0.003, 0.0)), ("dn",)]
+    ops = [("dx",), ("dy",), ("dz",), ("lap",), ("dir", e), ("shift", (0.004, -0.003, 0.0)), ("dn",),
+           ("taylor", (0.004, -0.003, 0.002))]
     w, info = O.weights(c.pos, Sr, ops, rowvec=rowvec)
     assert not info.any()
     check_exact(c.pos, Sr, w, ops, rowvec=rowvec)
@@ -67,6 +70,19 @@ def test_shift_to_nodes_is_kronecker(small_cloud, small_stencils):
         expect = np.zeros(30)
         expect[j] = 1.0
         assert np.abs(w[:, 0, :] - expect).max() < 1e-9
+
+
+def test_taylor_is_identity_plus_directional_derivative(small_cloud, small_stencils):
+    """The first-order Taylor row is linear in its functional: the weights of
+    value-at-x_i (the unit vector e_1) plus those of s . grad."""
+    c, S = small_cloud, small_stencils
+    Sr = S[::53]
+    s = (-0.003, 0.002, 0.004)
+    w, info = O.weights(c.pos, Sr, [("taylor", s), ("dir", s)])
+    assert not info.any()
+    expect = w[:, 1, :].copy()
+    expect[:, 0] += 1.0
+    assert np.abs(w[:, 0, :] - expect).max() < 1e-10 * np.abs(expect).max()
 
 
 def local_cluster(seed=0, n=60, spread=0.05):
