@@ -443,8 +443,9 @@ int mpfo_lbm_unknown(int q, int64_t nb, const double* pos_b, const double* nrm, 
  * Per step: collide on every node; stream each moving population by
  * interpolating its post-collision field at the departure point (Eq.
  * LBM_streaming with Eq. operatorApprox, L = 1); at boundary nodes an unknown
- * population takes the value of its opposite (Eq.
- * interpolated_bounceback_mlbm). */
+ * population takes the streamed value of its opposite (Eq.
+ * interpolated_bounceback_mlbm).  When both members of a pair are unknown
+ * (the solid rule allows it) each takes the other's streamed value. */
 int mpfo_lbm_run(int q, int64_t n, int64_t n_int, int nl, const int32_t* sten, const double* W,
                  const uint32_t* unknown, double tau_p, double tau_m, const double* g_lb, double* f, int n_steps) {
   double e[3 * 19], wk[19];
@@ -465,8 +466,10 @@ int mpfo_lbm_run(int q, int64_t n, int64_t n_int, int nl, const int32_t* sten, c
     }
     for (int64_t i = n_int; i < n; ++i) {
       const uint32_t mask = unknown[i - n_int];
+      double streamed[19];
+      for (int k = 0; k < q; ++k) streamed[k] = f[i * q + k];
       for (int k = 1; k < q; ++k)
-        if (mask >> k & 1u) f[i * q + k] = f[i * q + opp[k]];
+        if (mask >> k & 1u) f[i * q + k] = streamed[opp[k]];
     }
   }
   free(fpost);

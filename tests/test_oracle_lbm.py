@@ -233,3 +233,38 @@ def test_rest_state_preserved_with_solid_rule():
     f0 = m.f.copy()
     m.run(3)
     assert np.abs(m.f - f0).max() < 1e-14
+
+
+def test_bounce_back_reads_streamed_values():
+    """On a periodic lattice the shift rows are Kronecker deltas, so streaming
+    is exact lattice streaming: f_k(x) = f_k^post(x - dx e_k).  A node-wise
+    equilibrium state without force is its own post-collision state.  At a
+    node marked with both k and opp(k) unknown, each takes the other's
+    streamed value: f_k(b) = f_opp^0(b + dx e_k) and f_opp(b) =
+    f_k^0(b - dx e_k); a one-sided copy would put the first value in both."""
+    n = 6
+    c = nc.lattice_cloud(n)
+    S = nc.stencils(c.pos, 30)
+    q = 19
+    e, _, opp = O.lattice(q)
+    W, info = O.weights(c.pos, S, [("shift", tuple(-e[k] / n)) for k in range(q)])
+    assert not info.any()
+    rng = np.random.default_rng(2)
+    f0 = np.concatenate([O.equilibrium(q, 1, 1.0 + 0.01 * rng.normal(), 0.02 * rng.normal(size=3))
+                         for _ in range(c.n)])
+    b = c.n - 1  # the last node plays a boundary node
+    k = 7
+    kb = int(opp[k])
+    mask = np.array([(1 << k) | (1 << kb)], dtype=np.uint32)
+    f = f0.copy()
+    O.lbm_run(q, c.n - 1, S, W, mask, 1.0, 1.0, np.zeros(3), f, 1)
+
+    def node_at(x):
+        d = nc.min_image(c.pos - x)
+        return int(np.argmin((d * d).sum(1)))
+
+    up = node_at(c.pos[b] + e[k] / n)
+    down = node_at(c.pos[b] - e[k] / n)
+    assert f[b, k] == pytest.approx(f0[up, kb], abs=1e-15)
+    assert f[b, kb] == pytest.approx(f0[down, k], abs=1e-15)
+    assert abs(f0[up, kb] - f0[down, k]) > 1e-4  # the two readings differ here
