@@ -95,6 +95,9 @@ int mpf_sc_cell(double r, double* porosity_host, double* area_host);
  *   MPF_OP_SHIFT          value at c + vec          (L = 1 at a shifted point)
  *   MPF_OP_DN             rowvec_i . grad           (rowvec: dev [3][m])
  *   MPF_OP_SHIFT_ROW      value at c + rowvec_i
+ *   MPF_OP_TAYLOR         value at c plus vec . grad: the first-order estimate
+ *                         of the value at c + vec (the e . grad form of
+ *                         streaming, Sec. 2.2, with vec = -dx e_k)
  *
  * pos      dev [3][n_nodes] double, in the unit periodic cell (displacements
  *          use the minimum image)
@@ -104,7 +107,8 @@ int mpf_sc_cell(double r, double* porosity_host, double* area_host);
  * w64      dev [n_ops][nl][m] double, or NULL
  * w32      dev [n_ops][nl][m] float, or NULL: the FP32 copy; its self weight
  *          (column 0) is replaced so that the row sums, computed in FP64, equal
- *          the exact ones (1 for the two shift kinds, 0 for derivatives)
+ *          the exact ones (1 for the two shift kinds and the Taylor row,
+ *          0 for derivatives)
  * info     dev [m] int32: 0; 1 + the column of a zero pivot (weights of that
  *          row are then NaN); -1 if FP32 refinement did not settle and the
  *          row was re-solved in FP64 (batched call with MPF_SOLVE_FP32_IR)
@@ -119,6 +123,7 @@ int mpf_sc_cell(double r, double* porosity_host, double* area_host);
 #define MPF_OP_SHIFT 5
 #define MPF_OP_DN 6
 #define MPF_OP_SHIFT_ROW 7
+#define MPF_OP_TAYLOR 8
 
 typedef struct {
   int32_t kind;
@@ -233,10 +238,12 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  *     feq, F_k = 3 w_k e_k . (rho g_lb), TRT relaxation with tau+ and tau-;
  *   stream: f_k(i) = sum_j W_k[j][i] f^post_k(sten[j][i]) for k >= 1 (W_k
  *     interpolates at the departure point of population k), f_0 = f^post_0;
- *   bounce-back at boundary node b: where e_k . n_b > 0, f_k = f_{opp(k)}.
- * W     dev [q-1][nl][n] (population k uses slice k - 1): double for
- *       MPF_F64, float for MPF_F32 and MPF_MIXED
- * nrm   dev [3][nb] double
+ *   bounce-back at boundary node b (Eq. interpolated_bounceback_mlbm): where
+ *     bit k of unknown[b] is set, f_k = f_{opp(k)}.
+ * W       dev [q-1][nl][n] (population k uses slice k - 1): double for
+ *         MPF_F64, float for MPF_F32 and MPF_MIXED
+ * unknown dev [nb] uint32 bit masks from mpf_lbm_unknown (nb = n - n_int;
+ *         may be NULL when nb = 0)
  * f     dev [n][qp] state, updated in place; f_tmp dev [n][qp] scratch:
  *       double for MPF_F64 and MPF_MIXED, float for MPF_F32
  * q is 15 or 19. */
@@ -256,7 +263,21 @@ int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, const double*
 int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const double* v, const double* p, double vel_scale,
                         void* f, void* stream);
 int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* W,
-                const double* nrm, void* f, void* f_tmp, int n_steps, void* stream);
+                const uint32_t* unknown, void* f, void* f_tmp, int n_steps, void* stream);
+/* Which populations of each boundary node n_int + b are unknown after
+ * streaming, as bit masks unknown[b] (bit k for population k, bit 0 never set):
+ *   MPF_UNKNOWN_NORMAL (Sec. 2.2): e_k . n_b > 0, with nrm dev [3][nb] double
+ *     pointing from the solid into the fluid; pos, dx and r are not read.
+ *   MPF_UNKNOWN_SOLID (Sec. 3.3, the rule of the touching limit): the
+ *     departure point x_b - dx e_k lies inside the solid, the union of the
+ *     balls of radius r > 0 centred at (1/2, 1/2, 1/2) + Z^3 (the simple-cubic
+ *     cell, grains may overlap).  pos dev [3][n] double in the unit cell,
+ *     0 < dx < 1/2; nrm is not read.
+ * Written once per geometry; MPF_ERR_ARG for a bad rule, q or argument. */
+#define MPF_UNKNOWN_NORMAL 0
+#define MPF_UNKNOWN_SOLID 1
+int mpf_lbm_unknown(int q, int64_t n, int64_t n_int, const double* pos, const double* nrm, int rule, double dx,
+                    double r, uint32_t* unknown, void* stream);
 /* Macroscopic fields in physical units (Eq. conversion_factors): v[3][n] =
  * vel_scale * u_lb, p[n] = vel_scale^2 (rho - 1) / 3 (not centred: the drag
  * reduction subtracts the node mean).  Outputs are double. */

@@ -171,16 +171,34 @@ def lbm_init_fields(prm: LbmParams, f, v, p, vel_scale: float):
           "mpf_lbm_init_fields")
 
 
-def lbm_run(prm: LbmParams, n_int: int, sten, W, nrm, f, f_tmp, n_steps: int):
+def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int):
+    """unknown: [n - n_int] int32 bit masks from lbm_unknown."""
     dt = _ST[prm.precision]
     nl, n = sten.shape
     _need(W, _WT[prm.precision], (prm.q - 1, nl, n), "W")
     _need(f, dt, (n, record_len(prm.q)), "f")
     _need(f_tmp, dt, (n, record_len(prm.q)), "f_tmp")
     if n > n_int:
-        _need(nrm, torch.float64, (3, n - n_int), "nrm")
-    check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(nrm), _p(f), _p(f_tmp), int(n_steps),
-                          _stream()), "mpf_lbm_run")
+        _need(unknown, torch.int32, (n - n_int,), "unknown")
+    check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(unknown), _p(f), _p(f_tmp),
+                            int(n_steps), _stream()), "mpf_lbm_run")
+
+
+def lbm_unknown(q: int, pos, n_int: int, nrm=None, rule: str = "normal", dx: float = 0.0, r: float = 0.0):
+    """Bit masks [n - n_int] (int32 holding the uint32 pattern) of the unknown
+    populations of the boundary nodes: rule "normal" reads nrm [3][nb],
+    "solid" tests the departure points x_b - dx e_k against the grains of
+    radius r."""
+    _need(pos, torch.float64, name="pos")
+    n = pos.shape[1]
+    nb = n - int(n_int)
+    if rule == "normal":
+        _need(nrm, torch.float64, (3, nb), "nrm")
+    out = torch.empty(nb, dtype=torch.int32, device=pos.device)
+    check(lib().mpf_lbm_unknown(int(q), n, int(n_int), _p(pos), _p(nrm) if rule == "normal" else None,
+                                _lib.UNKNOWN_RULE[rule], float(dx), float(r), _p(out) if nb else None, _stream()),
+          "mpf_lbm_unknown")
+    return out
 
 
 def lbm_moments(prm: LbmParams, f, vel_scale: float, v=None, p=None):

@@ -11,7 +11,8 @@
 // A step is one fused pass per node tile: gather-stream the post-collision
 // populations of the stencil (Eq. LBM_streaming with interpolation weights of
 // Eq. operatorApprox), bounce back the unknown populations of surface nodes
-// (Eq. interpolated_bounceback_mlbm), then collide (Eqs. macro_var, feq,
+// (Eq. interpolated_bounceback_mlbm; which ones are unknown is a per-node bit
+// mask, built once by lbm_unknown), then collide (Eqs. macro_var, feq,
 // LBM_collision, force_lbm) and write the next post-collision state.  Weights
 // stream coalesced from [k][j][node].
 #include <type_traits>
@@ -140,7 +141,8 @@ inline unsigned tiles_grid(int64_t n) {
 template <typename TW, typename T, int Q, bool COLLIDE>
 __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int, int nl,
                                                        const int32_t* __restrict__ sten,
-                                                       const TW* __restrict__ W, const double* __restrict__ nrm,
+                                                       const TW* __restrict__ W,
+                                                       const uint32_t* __restrict__ unknown,
                                                        const T* __restrict__ src, T* __restrict__ dst, Prm<T> pr) {
   using L = Lattice<Q>;
   constexpr int QP = Pad<Q>::QP;
@@ -194,16 +196,13 @@ __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int,
 #pragma unroll
   for (int k = Q; k < QP; ++k) f[k] = T(0);
   if (i >= n_int) {
-    const int64_t b = i - n_int, nb = n - n_int;
-    const double nx = nrm[b], ny = nrm[nb + b], nz = nrm[2 * nb + b];
+    const uint32_t mask = unknown[i - n_int];
     T g[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) g[k] = f[k];
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      const double en = (double)L::ex[k] * nx + (double)L::ey[k] * ny + (double)L::ez[k] * nz;
-      if (en > 0.0) f[k] = g[lat_opp(k)];
-    }
+    for (int k = 1; k < Q; ++k)
+      if (mask >> k & 1u) f[k] = g[lat_opp(k)];
   }
   if (COLLIDE) {
     T c[Q];
@@ -288,9 +287,54 @@ __global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __rest
   if (p) p[i] = vs * vs * drho / 3.0;
 }
 
+// Unknown populations of boundary node b as a bit mask (bit k: population k).
+// Normal rule (Sec. 2.2): e_k . n_b > 0, the departure point lies on the solid
+// side of the tangent plane.  Solid rule (Sec. 3.3, the touching limit): the
+// departure point x_b - dx e_k itself lies inside a grain, the grain being the
+// ball of radius r around the cell centre or one of its periodic images; the
+// nearest image is taken per axis (offset rint(p - 1/2)).  The products by
+// e_k are exact (e_k in {-1, 0, 1}^3) and the squared distance is rounded
+// operation by operation, so the decision does not depend on contraction.
+template <int Q>
+__global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int64_t n_int,
+                                                      const double* __restrict__ pos,
+                                                      const double* __restrict__ nrm, int rule, double dx, double r,
+                                                      uint32_t* __restrict__ unknown) {
+  using L = Lattice<Q>;
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nb) return;
+  uint32_t mask = 0;
+  if (rule == MPF_UNKNOWN_NORMAL) {
+    const double nx = nrm[b], ny = nrm[nb + b], nz = nrm[2 * nb + b];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const double en = __dadd_rn(__dadd_rn((double)L::ex[k] * nx, (double)L::ey[k] * ny), (double)L::ez[k] * nz);
+      if (en > 0.0) mask |= 1u << k;
+    }
+  } else {
+    const int64_t i = n_int + b;
+    const double x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+    const double r2 = __dmul_rn(r, r);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const double e[3] = {(double)L::ex[k], (double)L::ey[k], (double)L::ez[k]};
+      double d2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double p = __dsub_rn(x[a], dx * e[a]);
+        const double c = 0.5 + rint(__dsub_rn(p, 0.5));
+        const double d = __dsub_rn(p, c);
+        d2 = a == 0 ? __dmul_rn(d, d) : __dadd_rn(d2, __dmul_rn(d, d));
+      }
+      if (d2 < r2) mask |= 1u << k;
+    }
+  }
+  unknown[b] = mask;
+}
+
 template <typename TW, typename T, int Q>
 int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W,
-        const double* nrm, T* f, T* ft, int n_steps, hipStream_t st) {
+        const uint32_t* unknown, T* f, T* ft, int n_steps, hipStream_t st) {
   Prm<T> pr{(T)(1.0 / prm->tau_plus), (T)(1.0 / prm->tau_minus), (T)prm->g_lb[0], (T)prm->g_lb[1],
             (T)prm->g_lb[2]};
   const unsigned g = grid_for(n, kBlock);
@@ -307,11 +351,11 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   const unsigned gt = tiles_grid(n);
   for (int s = 0; s < n_steps - 1; ++s) {
     T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<TW, T, Q, true>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, nrm,
+    hipLaunchKernelGGL((lbm_step<TW, T, Q, true>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, unknown,
                        (const T*)cur, nxt, pr);
     cur = nxt;
   }
-  hipLaunchKernelGGL((lbm_step<TW, T, Q, false>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, nrm,
+  hipLaunchKernelGGL((lbm_step<TW, T, Q, false>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, unknown,
                      (const T*)cur, f, pr);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
@@ -371,11 +415,12 @@ extern "C" int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const d
 }
 
 extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
-                           const void* W, const double* nrm, void* f, void* f_tmp, int n_steps, void* stream) {
+                           const void* W, const uint32_t* unknown, void* f, void* f_tmp, int n_steps,
+                           void* stream) {
   using namespace mpf;
   if (!prm || !sten || !W || !f || !f_tmp || n < 1 || n_int < 0 || n_int > n || nl < 1 || n_steps < 0)
     return MPF_ERR_ARG;
-  if (n > n_int && !nrm) return MPF_ERR_ARG;
+  if (n > n_int && !unknown) return MPF_ERR_ARG;
   if (!(prm->tau_plus > 0.5) || !(prm->tau_minus > 0.5)) return MPF_ERR_ARG;
   if (prm->precision != MPF_F64 && prm->precision != MPF_F32 && prm->precision != MPF_MIXED) return MPF_ERR_ARG;
   if (n_steps == 0) return MPF_OK;
@@ -383,13 +428,37 @@ extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, 
   return with_q(prm->q, [&](auto qc) {
     constexpr int Q = decltype(qc)::value;
     if (prm->precision == MPF_F64)
-      return run<double, double, Q>(prm, n, n_int, nl, sten, (const double*)W, nrm, (double*)f, (double*)f_tmp,
+      return run<double, double, Q>(prm, n, n_int, nl, sten, (const double*)W, unknown, (double*)f, (double*)f_tmp,
                                     n_steps, st);
     if (prm->precision == MPF_MIXED)
-      return run<float, double, Q>(prm, n, n_int, nl, sten, (const float*)W, nrm, (double*)f, (double*)f_tmp,
+      return run<float, double, Q>(prm, n, n_int, nl, sten, (const float*)W, unknown, (double*)f, (double*)f_tmp,
                                    n_steps, st);
-    return run<float, float, Q>(prm, n, n_int, nl, sten, (const float*)W, nrm, (float*)f, (float*)f_tmp, n_steps,
+    return run<float, float, Q>(prm, n, n_int, nl, sten, (const float*)W, unknown, (float*)f, (float*)f_tmp, n_steps,
                                 st);
+  });
+}
+
+extern "C" int mpf_lbm_unknown(int q, int64_t n, int64_t n_int, const double* pos, const double* nrm, int rule,
+                               double dx, double r, uint32_t* unknown, void* stream) {
+  using namespace mpf;
+  if (n < 1 || n_int < 0 || n_int > n) return MPF_ERR_ARG;
+  const int64_t nb = n - n_int;
+  if (nb == 0) return MPF_OK;
+  if (!unknown) return MPF_ERR_ARG;
+  if (rule == MPF_UNKNOWN_NORMAL) {
+    if (!nrm) return MPF_ERR_ARG;
+  } else if (rule == MPF_UNKNOWN_SOLID) {
+    if (!pos || !(dx > 0.0 && dx < 0.5) || !(r > 0.0)) return MPF_ERR_ARG;
+  } else {
+    return MPF_ERR_ARG;
+  }
+  hipStream_t st = as_stream(stream);
+  const unsigned g = grid_for(nb, kBlock);
+  return with_q(q, [&](auto qc) {
+    constexpr int Q = decltype(qc)::value;
+    hipLaunchKernelGGL((lbm_unknown<Q>), dim3(g), dim3(kBlock), 0, st, nb, n, n_int, pos, nrm, rule, dx, r, unknown);
+    MPF_LAUNCH_CHECK();
+    return MPF_OK;
   });
 }
 

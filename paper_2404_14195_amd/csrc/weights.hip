@@ -108,17 +108,22 @@ __device__ __forceinline__ double rhs_entry(int kind, const double* vec, const d
     int l = j - NL;
     return (l == 4 || l == 7 || l == 9) ? 2.0 * id * id : 0.0;
   }
-  // first-derivative family: e . grad with e a unit axis, vec, or rowvec
+  // first-derivative family: e . grad with e a unit axis, vec, or rowvec;
+  // the Taylor row adds the value at the centre (|xi_j|^3 and p_l(0))
   double e0, e1, e2;
   if (kind <= MPF_OP_DZ) {
     e0 = kind == MPF_OP_DX; e1 = kind == MPF_OP_DY; e2 = kind == MPF_OP_DZ;
   } else {
-    const double* e = kind == MPF_OP_DIR ? vec : rv;
+    const double* e = (kind == MPF_OP_DIR || kind == MPF_OP_TAYLOR) ? vec : rv;
     e0 = e[0]; e1 = e[1]; e2 = e[2];
   }
-  if (j < NL) return -3.0 * id * rho * (e0 * xi0 + e1 * xi1 + e2 * xi2);
+  const bool value = kind == MPF_OP_TAYLOR;
+  if (j < NL) {
+    const double d = -3.0 * id * rho * (e0 * xi0 + e1 * xi1 + e2 * xi2);
+    return value ? rho * rho * rho + d : d;
+  }
   int l = j - NL;
-  return l == 1 ? e0 * id : (l == 2 ? e1 * id : (l == 3 ? e2 * id : 0.0));
+  return l == 0 ? (value ? 1.0 : 0.0) : (l == 1 ? e0 * id : (l == 2 ? e1 * id : (l == 3 ? e2 * id : 0.0)));
 }
 
 // Wave-wide maximum of an unsigned key: butterflies inside each row of 16
@@ -253,7 +258,7 @@ __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, i
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         const int kd = ops.kind[o];
-        const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW) ? 1.0 : 0.0;
+        const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW || kd == MPF_OP_TAYLOR) ? 1.0 : 0.0;
         if (lane == 0) xf = (float)(target - part);
         if (lane < NL) w32[((int64_t)o * NL + lane) * m + row] = xf;
       }
@@ -402,7 +407,7 @@ __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
         const int kd = ops.kind[o];
-        const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW) ? 1.0 : 0.0;
+        const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW || kd == MPF_OP_TAYLOR) ? 1.0 : 0.0;
         if (lane == 0) xf = (float)(target - part);
         if (lane < NL) w32[((int64_t)o * NL + lane) * m + row] = xf;
       }
@@ -472,7 +477,7 @@ int make_ops(int n_ops, const mpf_op* ops, bool have_rowvec, OpsArg& a) {
   a.n = n_ops;
   for (int o = 0; o < n_ops; ++o) {
     int k = ops[o].kind;
-    if (k < MPF_OP_DX || k > MPF_OP_SHIFT_ROW) return MPF_ERR_ARG;
+    if (k < MPF_OP_DX || k > MPF_OP_TAYLOR) return MPF_ERR_ARG;
     if ((k == MPF_OP_DN || k == MPF_OP_SHIFT_ROW) && !have_rowvec) return MPF_ERR_ARG;
     a.kind[o] = k;
     for (int t = 0; t < 3; ++t) a.vec[o][t] = ops[o].vec[t];
@@ -625,7 +630,7 @@ extern "C" int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32
   if (!w64 && !w32) return MPF_ERR_ARG;
   if (ops_need_rowvec(n_ops, ops) && !rowvec) return MPF_ERR_ARG;
   for (int o = 0; o < n_ops; ++o)
-    if (ops[o].kind < MPF_OP_DX || ops[o].kind > MPF_OP_SHIFT_ROW) return MPF_ERR_ARG;
+    if (ops[o].kind < MPF_OP_DX || ops[o].kind > MPF_OP_TAYLOR) return MPF_ERR_ARG;
   if (!nl_supported(nl)) return MPF_ERR_UNSUPPORTED;
   if (m == 0) return MPF_OK;
   mpf_wgeom g{pos, n_nodes, sten, m, rowvec, w64, w32, info};

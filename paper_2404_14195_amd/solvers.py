@@ -133,10 +133,17 @@ def lattice_weights(q: int):
 
 
 class MLBMSolver:
-    """Meshless TRT lattice Boltzmann (Sec. 2.2) on a Discretization."""
+    """Meshless TRT lattice Boltzmann (Sec. 2.2) on a Discretization.
+
+    streaming: "shift" interpolates each population at its departure point
+    x_i - dx e_k (Eq. LBM_streaming); "taylor" uses the first-order form
+    f - dx e_k . grad f instead.  rule: the unknown populations of boundary
+    nodes come from the local normal ("normal", Sec. 2.2) or from testing the
+    departure point against the grains ("solid", the touching limit of
+    Sec. 3.3)."""
 
     def __init__(self, disc: Discretization, q=19, precision: int = MPF_F64, nu=1.0, tau_plus=1.0, magic=0.25,
-                 g=(1.0, 0.0, 0.0), dx=None, W=None):
+                 g=(1.0, 0.0, 0.0), dx=None, W=None, streaming: str = "shift", rule: str = "normal"):
         self.d, self.q, self.precision = disc, q, precision
         h = disc.cloud.h_min if dx is None else 2.0 * dx
         self.units = u = lbm_units(h, nu, tau_plus, g, magic)
@@ -144,12 +151,15 @@ class MLBMSolver:
         self.prm = LbmParams(q=q, precision=precision, tau_plus=tau_plus, tau_minus=u["tau_minus"],
                              g_lb=ctypesarr(u["g_lb"]))
         e = lattice_vectors(q)
+        if streaming not in ("shift", "taylor"):
+            raise ValueError(f"unknown streaming {streaming!r}")
         if W is None:
-            ops = [("shift", tuple(-u["dx"] * x for x in e[k])) for k in range(1, q)]
+            ops = [(streaming, tuple(-u["dx"] * x for x in e[k])) for k in range(1, q)]
             w64, w32, self.info = api.rbffd_weights(disc.pos, disc.sten, ops, want64=precision == MPF_F64,
                                                     want32=precision != MPF_F64)
             W = w64 if precision == MPF_F64 else w32
         self.W = W
+        self.unknown = api.lbm_unknown(q, disc.pos, disc.n_int, disc.nrm, rule, u["dx"], disc.cloud.r)
         dtp = _DT[precision]
         self.f = torch.empty((disc.n, api.record_len(q)), dtype=dtp, device=disc.device)
         self.f_tmp = torch.empty_like(self.f)
@@ -166,7 +176,7 @@ class MLBMSolver:
         self.steps = 0
 
     def run(self, n_steps: int):
-        api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.d.nrm, self.f, self.f_tmp, n_steps)
+        api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.unknown, self.f, self.f_tmp, n_steps)
         self.steps += n_steps
 
     def populations(self):

@@ -52,7 +52,7 @@ def test_weights_parity_fp64(api, small_cloud, small_stencils):
     rv = rng.normal(size=(c.n, 3)) * 0.01
     e19 = [(1, 0, 0), (1, 1, 0), (0, -1, 1)]
     ops = [("dx",), ("dy",), ("dz",), ("lap",), ("dir", (0.3, -0.5, 0.8)), ("dn",), ("shift_row",)] + \
-          [("shift", tuple(-0.01 * np.array(v))) for v in e19]
+          [("shift", tuple(-0.01 * np.array(v))) for v in e19] + [("taylor", (-0.01, 0.01, 0.0))]
     w_ref, info_ref = O.weights(c.pos, S, ops, rowvec=rv)
     w64, w32, info = api.rbffd_weights(dev(c.pos.T, torch.float64), dev(S.T, torch.int32), ops,
                                        rowvec=dev(rv.T, torch.float64), want64=True, want32=True)
@@ -66,6 +66,7 @@ def test_weights_parity_fp64(api, small_cloud, small_stencils):
     assert row_rel_err(w32[:, 0], w_ref[:, 0]) < 1e-6
     assert np.abs(w32[:, 0].sum(1)).max() < 1e-6 * np.abs(w_ref[:, 0]).max()
     assert np.abs(w32[:, 7].sum(1) - 1.0).max() < 1e-7
+    assert np.abs(w32[:, -1].sum(1) - 1.0).max() < 1e-7  # the Taylor row reproduces constants too
 
 
 @pytest.mark.parametrize("nl", [20, 25, 27, 35, 40, 45, 50])
@@ -295,6 +296,105 @@ def test_lbm_init_from_fields(api, disc_small, precision):
     tol = 1e-12 if precision != 1 else 1e-4
     assert np.abs(vg.cpu().numpy() - v).max() <= tol * np.abs(v).max()
     assert np.abs(pg.cpu().numpy() - p).max() <= tol * np.abs(p).max()
+
+
+# ------------------------------------- unknown populations; the paper's own MLBM configuration
+
+@pytest.fixture(scope="module")
+def disc_touching(api):
+    """Overlapping grains, r = 0.52: the neighbouring images cut into the cell."""
+    from paper_2404_14195_amd.solvers import Discretization
+    return Discretization(nc.sphere_cloud(0.52, 0.04, 0.3, 0.08, seed=7), nl=30, M=32)
+
+
+@pytest.mark.parametrize("q", [15, 19])
+@pytest.mark.parametrize("rule", ["normal", "solid"])
+@pytest.mark.parametrize("cell", ["small", "touching"])
+def test_unknown_masks_bit_exact(api, disc_small, disc_touching, q, rule, cell):
+    d = disc_small if cell == "small" else disc_touching
+    c = d.cloud
+    dx = 0.5 * c.h_min
+    m_o = O.lbm_unknown(q, c.pos[c.n_int:], c.nrm, rule, dx, c.r)
+    m_g = api.lbm_unknown(q, d.pos, d.n_int, d.nrm, rule, dx, c.r).cpu().numpy().view(np.uint32)
+    assert np.array_equal(m_g, m_o)
+
+
+def test_unknown_masks_full_size_cell(api):
+    """The 71k-node cell of the throughput workload, every boundary node."""
+    c = nc.config_cloud("lbm_mid")
+    pos, nrm = dev(c.pos.T, torch.float64), dev(c.nrm.T, torch.float64)
+    for rule in ("normal", "solid"):
+        m_o = O.lbm_unknown(19, c.pos[c.n_int:], c.nrm, rule, 0.5 * c.h_min, c.r)
+        m_g = api.lbm_unknown(19, pos, c.n_int, nrm, rule, 0.5 * c.h_min, c.r).cpu().numpy().view(np.uint32)
+        assert np.array_equal(m_g, m_o), rule
+
+
+def test_unknown_masks_argument_errors(api, disc_small):
+    d = disc_small
+    with pytest.raises(RuntimeError):
+        api.lbm_unknown(19, d.pos, d.n_int, d.nrm, "solid", 0.7, 0.3)
+    with pytest.raises(RuntimeError):
+        api.lbm_unknown(17, d.pos, d.n_int, d.nrm, "normal")
+
+
+def perturbed_state(q, n, seed):
+    rng = np.random.default_rng(seed)
+    rho0 = 1.0 + 0.01 * rng.normal(size=n)
+    u0 = 0.02 * rng.normal(size=(n, 3))
+    return np.concatenate([O.equilibrium(q, 1, rho0[i], u0[i]) for i in range(n)])
+
+
+@pytest.mark.parametrize("cell, rule", [("small", "normal"), ("touching", "solid")])
+def test_lbm_paper_configuration_parity(api, disc_small, disc_touching, cell, rule):
+    """The paper's MLBM setup: D3Q15 with tau+ = 1 and Lambda = 1, so tau- =
+    5/2 and the two relaxation rates differ; on the overlapping-grain cell with
+    the touching-limit rule for unknown populations.  Shared oracle weights,
+    perturbed state, 1 + 2 + 37 steps."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    d = disc_small if cell == "small" else disc_touching
+    c = d.cloud
+    o = O.MLBM(c.pos, c.n_int, d.sten_host, c.nrm, q=15, h_min=c.h_min, magic=1.0, rule=rule, r=c.r)
+    assert o.tau_minus == pytest.approx(2.5)
+    W = dev(o.W[:, 1:, :].transpose(1, 2, 0), torch.float64)
+    g = MLBMSolver(d, q=15, precision=0, magic=1.0, W=W, rule=rule)
+    assert np.array_equal(g.unknown.cpu().numpy().view(np.uint32), o.unknown)
+    _, wk, _ = O.lattice(15)
+    o.f[:] = perturbed_state(15, c.n, 3)
+    g.set_populations(o.f)
+    done = 0
+    for steps in (1, 2, 37):
+        g.run(steps)
+        o.run(steps)
+        done += steps
+        tol = 1e-10 * np.abs(o.f - wk).max() + oracle_floor(o.f, done)
+        err = np.abs(g.populations() - o.f).max()
+        assert err <= tol, (done, err, tol)
+
+
+def test_lbm_taylor_streaming_parity(api, disc_small):
+    """The e.grad form of streaming, W_k = I - dx e_k . grad: each side its own
+    weights (agreeing to 1e-10), then 1 + 2 + 7 steps from a perturbed state
+    (first-order explicit advection through a centred derivative grows: by
+    about 40x over 20 steps here, so the run is kept short)."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    c = disc_small.cloud
+    g = MLBMSolver(disc_small, q=19, precision=0, streaming="taylor")
+    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=19, h_min=c.h_min, streaming="taylor")
+    Wg = g.W.cpu().numpy().transpose(2, 0, 1)  # [n][q-1][nl]
+    Wo = o.W[:, 1:, :]
+    scale = np.abs(Wo).max(2, keepdims=True)
+    assert (np.abs(Wg - Wo) / scale).max() < 1e-10
+    _, wk, _ = O.lattice(19)
+    o.f[:] = perturbed_state(19, c.n, 5)
+    g.set_populations(o.f)
+    done = 0
+    for steps in (1, 2, 7):
+        g.run(steps)
+        o.run(steps)
+        done += steps
+        tol = 1e-10 * np.abs(o.f - wk).max() + oracle_floor(o.f, done)
+        err = np.abs(g.populations() - o.f).max()
+        assert err <= tol, (done, err, tol)
 
 
 # ----------------------------------------------------------------- reductions

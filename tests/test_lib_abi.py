@@ -79,6 +79,17 @@ def test_host_argument_checks(lib):
     assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, 1, None) == -1
     lp.q, lp.tau_plus = 19, 0.5
     assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, 1, None) == -1
+    lp.tau_plus = 1.0
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 8, 30, fake, fake, None, fake, fake, 1, None) == -1  # no masks
+    # unknown-population masks: rule, q, normals, dx and r are checked first
+    assert lib.mpf_lbm_unknown(19, 10, 10, None, None, 0, 0.0, 0.0, None, None) == 0  # no boundary nodes
+    assert lib.mpf_lbm_unknown(19, 10, 8, fake, None, 0, 0.0, 0.0, fake, None) == -1  # normal rule needs nrm
+    assert lib.mpf_lbm_unknown(19, 10, 8, fake, fake, 2, 0.01, 0.3, fake, None) == -1  # no such rule
+    assert lib.mpf_lbm_unknown(19, 10, 8, fake, None, 1, 0.6, 0.3, fake, None) == -1  # dx >= 1/2
+    assert lib.mpf_lbm_unknown(19, 10, 8, fake, None, 1, 0.01, 0.0, fake, None) == -1  # r <= 0
+    assert lib.mpf_lbm_unknown(19, 10, 8, None, None, 1, 0.01, 0.3, fake, None) == -1  # solid rule needs pos
+    assert lib.mpf_lbm_unknown(17, 10, 8, fake, fake, 0, 0.0, 0.0, fake, None) == -1  # q
+    assert lib.mpf_lbm_unknown(19, 10, 11, fake, fake, 0, 0.0, 0.0, fake, None) == -1  # n_int > n
     assert lib.mpf_flux_planes(5, 30, fake, fake, fake, 0, 0, fake, fake, 1 << 20, None) == -1
     assert lib.mpf_drag(10, fake, fake, 0, 2, 30, fake, fake, fake, 1.0, 1.0, 0.1, fake, fake, 8, None) == -4
     assert lib.mpf_acm_workspace(1000, 0) >= 3 * 1000 * 8
