@@ -182,16 +182,52 @@ def channel_cloud(h: float, H: float, seed: int, jitter: float = 0.25) -> Cloud:
                  meta=dict(kind="channel", h=h, H=H, seed=seed))
 
 
+def _canonical(pts: np.ndarray, q: np.ndarray, cand: np.ndarray, k: int):
+    """Order candidate neighbours by (squared minimum-image distance, index)
+    and keep the first k.  The distance is formed operation by operation
+    (t = p - q, t - rint(t), x^2 + y^2, + z^2), so exact ties are decided by
+    the index, whatever order the tree returned them in.  Also returns the rows
+    whose k-th distance equals that of the last candidate: tied neighbours may
+    lie beyond the candidates there."""
+    t = pts[cand] - q[:, None, :]
+    t = t - np.rint(t)
+    d2 = t[..., 0] * t[..., 0]
+    d2 = d2 + t[..., 1] * t[..., 1]
+    d2 = d2 + t[..., 2] * t[..., 2]
+    order = np.lexsort((cand, d2), axis=1)
+    d2 = np.take_along_axis(d2, order, 1)
+    cand = np.take_along_axis(cand, order, 1)
+    open_rows = d2[:, k - 1] == d2[:, -1] if cand.shape[1] > k else np.zeros(len(q), dtype=bool)
+    return cand[:, :k], open_rows
+
+
+def _knn(pts: np.ndarray, k: int, q: np.ndarray) -> np.ndarray:
+    """k nearest of pts to each query in the canonical order (see _canonical).
+    Rows with a tie reaching past the candidates are asked again with more."""
+    tree = cKDTree(pts, boxsize=1.0)
+    extra = min(8, len(pts) - k)
+    _, idx = tree.query(q, k=k + extra)
+    out, open_rows = _canonical(pts, q, np.asarray(idx, dtype=np.int64).reshape(len(q), k + extra), k)
+    while open_rows.any() and k + extra < len(pts):
+        extra = min(4 * extra + 8, len(pts) - k)
+        rows = np.where(open_rows)[0]
+        _, idx = tree.query(q[rows], k=k + extra)
+        sub, still = _canonical(pts, q[rows], np.asarray(idx, dtype=np.int64).reshape(len(rows), k + extra), k)
+        out[rows] = sub
+        open_rows = np.zeros(len(q), dtype=bool)
+        open_rows[rows[still]] = True
+    return out
+
+
 def stencils(pos: np.ndarray, nl: int, queries: np.ndarray | None = None) -> np.ndarray:
-    """The nl nearest nodes (minimum image) of each query point, nearest first.
+    """The nl nearest nodes (minimum image) of each query point, nearest first;
+    equal distances in index order.
 
     With queries=None the queries are the nodes themselves and column 0 is the
     node's own index."""
     pos = np.asarray(pos, dtype=np.float64) % 1.0
-    tree = cKDTree(pos, boxsize=1.0)
     q = pos if queries is None else (np.asarray(queries, dtype=np.float64) % 1.0)
-    _, idx = tree.query(q, k=nl)
-    idx = np.asarray(idx, dtype=np.int64).reshape(len(q), nl)
+    idx = _knn(pos, nl, q)
     if queries is None:
         own = np.arange(len(pos))
         bad = idx[:, 0] != own
@@ -211,9 +247,7 @@ def neumann_stencils(cloud: Cloud, nl: int) -> np.ndarray:
     own = np.arange(cloud.n_int, cloud.n, dtype=np.int64)[:, None]
     if cloud.n_bnd == 0:
         return np.zeros((0, nl), dtype=np.int32)
-    tree = cKDTree(np.asarray(cloud.pos[:cloud.n_int]) % 1.0, boxsize=1.0)
-    _, idx = tree.query(np.asarray(cloud.pos[cloud.n_int:]) % 1.0, k=nl - 1)
-    idx = np.asarray(idx, dtype=np.int64).reshape(cloud.n_bnd, nl - 1)
+    idx = _knn(np.asarray(cloud.pos[:cloud.n_int]) % 1.0, nl - 1, np.asarray(cloud.pos[cloud.n_int:]) % 1.0)
     return np.ascontiguousarray(np.concatenate([own, idx], 1).astype(np.int32))
 
 

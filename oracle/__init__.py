@@ -55,6 +55,8 @@ def _load():
         lib.mpfo_lbm_moments.argtypes = [i32, i64, vp, vp, vp]
         lib.mpfo_lbm_run.restype = i32
         lib.mpfo_lbm_run.argtypes = [i32, i64, i64, i32, vp, vp, vp, dbl, dbl, vp, vp, i32]
+        lib.mpfo_knn.restype = i32
+        lib.mpfo_knn.argtypes = [vp, i64, vp, i64, i32, vp]
         lib.mpfo_lbm_unknown.restype = i32
         lib.mpfo_lbm_unknown.argtypes = [i32, i64, vp, vp, i32, dbl, dbl, vp]
         lib.mpfo_flux.restype = dbl
@@ -77,6 +79,33 @@ def porosity(r: float) -> float:
 
 def area(r: float) -> float:
     return _load().mpfo_area(float(r))
+
+
+# --- stencils (Sec. 2.1) -------------------------------------------------------
+
+def knn(pts, k, queries=None):
+    """Indices [m][k] of the k nearest of pts [n][3] to each query (default:
+    the points themselves), nearest first; equal distances by index."""
+    pts = _c(pts, np.float64).reshape(-1, 3)
+    q = pts if queries is None else _c(queries, np.float64).reshape(-1, 3)
+    idx = np.zeros((len(q), k), dtype=np.int32)
+    if len(q) and _load().mpfo_knn(pts.ctypes.data, len(pts), q.ctypes.data, len(q), int(k), idx.ctypes.data):
+        raise ValueError("mpfo_knn: need 1 <= k <= number of points")
+    return idx
+
+
+def solver_stencils(pos, n_int, nl):
+    """Interior nodes: their nl nearest nodes.  Boundary nodes [n_int, n):
+    the node itself, then its nl - 1 nearest interior nodes."""
+    pos = _c(pos, np.float64)
+    n_int = int(n_int)
+    sten = np.zeros((len(pos), nl), dtype=np.int32)
+    if n_int:
+        sten[:n_int] = knn(pos, nl, pos[:n_int])
+    if len(pos) > n_int:
+        sten[n_int:, 0] = np.arange(n_int, len(pos))
+        sten[n_int:, 1:] = knn(pos[:n_int], nl - 1, pos[n_int:])
+    return sten
 
 
 # --- weights (Sec. 2.1) --------------------------------------------------------

@@ -9,6 +9,7 @@
  * library never does, and it shares no source with the HIP kernels.
  *
  * Every function follows the paper's steps in the paper's order:
+ *   - Stencils: Sec. 2.1, the N_L nearest nodes of each node, by brute force.
  *   - RBF-FD weights: Sec. 2.1, Eqs. operatorApprox, rbfScaling,
  *     augmentedSystem (PHS r^3, monomials up to degree 2, local scaling by the
  *     distance to the nearest neighbour), solved by Gaussian elimination with
@@ -55,6 +56,51 @@ double mpfo_area(double r) {
   double a = 4.0 * M_PI * r * r;
   if (r > 0.5) a -= 6.0 * 2.0 * M_PI * r * (r - 0.5);
   return a;
+}
+
+/* ------------------------------------------------------------------ stencils */
+
+/* Squared minimum-image distance from q to p: each coordinate difference
+ * t = p_a - q_a is reduced by t - nearbyint(t), and the squares are summed
+ * x, y, z, every operation rounded on its own (x86-64 SSE2 doubles, no
+ * contraction).  Fixing the operations fixes ties to the last bit. */
+static double dist2(const double* p, const double* q) {
+  double t0 = mi(p[0] - q[0]), t1 = mi(p[1] - q[1]), t2 = mi(p[2] - q[2]);
+  double s = t0 * t0;
+  s = s + t1 * t1;
+  return s + t2 * t2;
+}
+
+/* The k nearest of the n points pts [n][3] to each query qry [m][3] in the
+ * unit periodic cell, nearest first: the stencil of Sec. 2.1 ("the N_L
+ * nearest nodes").  Order: squared distance (dist2), then point index.  Brute
+ * force over every point, keeping a sorted list by insertion.  Output
+ * idx [m][k].  Returns -1 unless 1 <= k <= n. */
+int mpfo_knn(const double* pts, int64_t n, const double* qry, int64_t m, int k, int32_t* idx) {
+  if (k < 1 || (int64_t)k > n) return -1;
+  double* bd = (double*)malloc(sizeof(double) * k);
+  int32_t* bi = (int32_t*)malloc(sizeof(int32_t) * k);
+  for (int64_t j = 0; j < m; ++j) {
+    int cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      double d = dist2(pts + 3 * i, qry + 3 * j);
+      int32_t ii = (int32_t)i;
+      if (cnt == k && !(d < bd[k - 1] || (d == bd[k - 1] && ii < bi[k - 1]))) continue;
+      int p = cnt < k ? cnt : k - 1;
+      while (p > 0 && (bd[p - 1] > d || (bd[p - 1] == d && bi[p - 1] > ii))) {
+        bd[p] = bd[p - 1];
+        bi[p] = bi[p - 1];
+        --p;
+      }
+      bd[p] = d;
+      bi[p] = ii;
+      if (cnt < k) ++cnt;
+    }
+    for (int c = 0; c < k; ++c) idx[j * k + c] = bi[c];
+  }
+  free(bd);
+  free(bi);
+  return 0;
 }
 
 /* ------------------------------------------------------------------ weights */
