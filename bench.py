@@ -342,21 +342,28 @@ def weights_batch(torch, nc, api):
     print(f"[bench] 8 cells, {sum(c[1] for c in cells)} nodes, fill {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     clouds = []
-    from scipy.spatial import cKDTree
+    knn_ms = 0.0
     for pos, n in cells:
-        tree = cKDTree(pos % 1.0, boxsize=1.0)
-        _, idx = tree.query(pos % 1.0, k=30, workers=-1)
-        clouds.append((torch.as_tensor(np.ascontiguousarray(pos.T), device="cuda"),
-                       torch.as_tensor(np.ascontiguousarray(idx.T.astype(np.int32)), device="cuda"), None))
-        del tree, idx
-        print(f"[bench] stencils of a {n}-node cell, {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        p = torch.as_tensor(np.ascontiguousarray(pos.T), device="cuda")
+        api.knn(p, 30)  # warm (first launch of the kernels)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        idx = api.knn(p, 30)  # the 30 nearest nodes of every node, on the GPU
+        ev1.record()
+        torch.cuda.synchronize()
+        knn_ms += ev0.elapsed_time(ev1)
+        clouds.append((p, idx, None))
+        print(f"[bench] stencils of a {n}-node cell on the GPU, {ev0.elapsed_time(ev1):.1f} ms", file=sys.stderr,
+              flush=True)
     print(f"[bench] stencils done {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     ops = [("dx",), ("dy",), ("dz",), ("lap",)]
     rows = sum(c[1].shape[1] for c in clouds)
     n = 40
     flops = (2.0 / 3.0) * n ** 3 + 2 * n * n * len(ops)
     out = {"cells": [{"r": float(r), "n": int(c[1].shape[1])} for r, c in zip(radii, clouds)], "rows": rows,
-           "flops_per_row": flops}
+           "flops_per_row": flops, "stencils_ms": knn_ms, "stencils_nodes_per_s": rows / (knn_ms * 1e-3)}
     ref = None
     for name, solve in (("fp64", 0), ("fp32_ir", 1)):
         tune = api.weights_autotune(clouds[0][0], clouds[0][1], ops, solve=solve, sample_rows=65536)

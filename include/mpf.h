@@ -79,6 +79,33 @@ int mpf_version(void);
  * otherwise MPF_ERR_ARG. */
 int mpf_sc_cell(double r, double* porosity_host, double* area_host);
 
+/* ------------------------------------------------------------- stencils
+ * The stencil of a node is its N_L nearest nodes (Sec. 2.1), here in the unit
+ * periodic cell.  Order: squared minimum-image distance in FP64, formed
+ * operation by operation (t = p_a - q_a reduced by t - rint(t), then
+ * x^2 + y^2, + z^2, each rounded), ties by point index; nearest first.
+ * Points must be distinct.
+ *
+ * mpf_knn: the k nearest of n_pts points to each of n_qry queries.
+ *   pts    dev [3][ld_pts] double (coordinate a of point i at a * ld_pts + i)
+ *   qry    dev [3][ld_qry] double
+ *   idx    dev [k][ld_idx] int32 out (column c of query j at c * ld_idx + j)
+ *   ws     dev workspace of mpf_knn_workspace(n_pts) bytes (the cell grid)
+ *   1 <= k <= 64, k <= n_pts <= 2^31 - 1; MPF_ERR_ARG otherwise.
+ * mpf_solver_stencils: the solvers' stencils [nl][n] of n nodes, interior
+ *   first.  Interior nodes: their nl nearest nodes (the node itself first).
+ *   Surface nodes [n_int, n): the node itself, then its nl - 1 nearest
+ *   interior nodes (a surface node's nearest nodes are mostly other surface
+ *   nodes, whose coordinates satisfy x^2 + y^2 + z^2 = r^2 and make the
+ *   quadratic block of the weight system nearly singular).
+ *   pos dev [3][n] double; sten dev [nl][n] int32 out; ws of
+ *   mpf_knn_workspace(n) bytes; 2 <= nl <= 64, n_int >= nl - 1 when n > n_int. */
+size_t mpf_knn_workspace(int64_t n_pts);
+int mpf_knn(const double* pts, int64_t n_pts, int64_t ld_pts, const double* qry, int64_t n_qry, int64_t ld_qry,
+            int k, int32_t* idx, int64_t ld_idx, void* ws, size_t ws_bytes, void* stream);
+int mpf_solver_stencils(const double* pos, int64_t n, int64_t n_int, int nl, int32_t* sten, void* ws,
+                        size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------- RBF-FD weights
  * Weights w of Eq. operatorApprox for m stencil rows, from the augmented
  * polyharmonic system of Eq. augmentedSystem: PHS r^3 plus the ten monomials

@@ -26,7 +26,7 @@ OPS = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shif
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-shared", "-fPIC",
                                os.path.join(_HERE, "mpf_oracle.c"), "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO

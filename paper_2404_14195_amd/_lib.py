@@ -12,7 +12,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _INC = os.path.join(os.path.dirname(_HERE), "include")
 SO_PATH = os.path.join(_HERE, "libmpf.so")
-SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip"]
+SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip", "knn.hip"]
 
 MPF_F64, MPF_F32, MPF_MIXED = 0, 1, 2
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
@@ -100,6 +100,9 @@ def _load():
         "mpf_lbm_init_fields": (i32, [vp, i64, vp, vp, dbl, vp, vp]),
         "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, i32, vp]),
         "mpf_lbm_unknown": (i32, [i32, i64, i64, vp, vp, i32, dbl, dbl, vp, vp]),
+        "mpf_knn_workspace": (ctypes.c_size_t, [i64]),
+        "mpf_knn": (i32, [vp, i64, i64, vp, i64, i64, i32, vp, i64, vp, ctypes.c_size_t, vp]),
+        "mpf_solver_stencils": (i32, [vp, i64, i64, i32, vp, vp, ctypes.c_size_t, vp]),
         "mpf_lbm_moments": (i32, [vp, i64, vp, dbl, vp, vp, vp]),
         "mpf_reduce_workspace": (sz, [i64]),
         "mpf_flux_planes": (i32, [i64, i32, vp, vp, vp, i32, i64, vp, vp, sz, vp]),
@@ -141,7 +144,8 @@ def lib():
 
 EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",
-            "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_unknown", "mpf_lbm_moments", "mpf_reduce_workspace",
+            "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_unknown", "mpf_lbm_moments",
+            "mpf_knn_workspace", "mpf_knn", "mpf_solver_stencils", "mpf_reduce_workspace",
             "mpf_flux_planes", "mpf_drag", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
             "mpf_mlp_pack", "mpf_mlp_forward", "mpf_mlp_backward", "mpf_mlp_mse", "mpf_adam_step",
             "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16", "mpf_mlp_train_workspace", "mpf_mlp_train",

@@ -75,6 +75,36 @@ def rbffd_weights(pos, sten, ops, rowvec=None, want64=True, want32=False):
     return w64, w32, info
 
 
+def knn(pts, k: int, qry=None):
+    """Indices [k][m] (int32) of the k nearest of pts [3][n] to each query
+    qry [3][m] (default: the points themselves), nearest first, minimum image
+    in the unit cell; equal distances in index order."""
+    _need(pts, torch.float64, name="pts")
+    qry = pts if qry is None else qry
+    _need(qry, torch.float64, name="qry")
+    if pts.dim() != 2 or pts.shape[0] != 3 or qry.dim() != 2 or qry.shape[0] != 3:
+        raise ValueError("pts and qry must be [3][n]")
+    n, m = pts.shape[1], qry.shape[1]
+    idx = torch.empty((k, m), dtype=torch.int32, device=pts.device)
+    ws = torch.empty(lib().mpf_knn_workspace(n), dtype=torch.uint8, device=pts.device)
+    check(lib().mpf_knn(_p(pts), n, n, _p(qry), m, m, int(k), _p(idx), m, _p(ws), ws.numel(), _stream()), "mpf_knn")
+    return idx
+
+
+def solver_stencils(pos, n_int: int, nl: int):
+    """Stencils [nl][n] (int32): interior nodes their nl nearest nodes, surface
+    nodes themselves and then their nl - 1 nearest interior nodes."""
+    _need(pos, torch.float64, name="pos")
+    if pos.dim() != 2 or pos.shape[0] != 3:
+        raise ValueError("pos must be [3][n]")
+    n = pos.shape[1]
+    sten = torch.empty((nl, n), dtype=torch.int32, device=pos.device)
+    ws = torch.empty(lib().mpf_knn_workspace(n), dtype=torch.uint8, device=pos.device)
+    check(lib().mpf_solver_stencils(_p(pos), n, int(n_int), int(nl), _p(sten), _p(ws), ws.numel(), _stream()),
+          "mpf_solver_stencils")
+    return sten
+
+
 def weights_workspace(device) -> torch.Tensor:
     return torch.empty(lib().mpf_weights_workspace(), dtype=torch.uint8, device=device)
 

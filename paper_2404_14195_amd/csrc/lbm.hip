@@ -294,12 +294,14 @@ __global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __rest
 // ball of radius r around the cell centre or one of its periodic images; the
 // nearest image is taken per axis (offset rint(p - 1/2)).  The products by
 // e_k are exact (e_k in {-1, 0, 1}^3) and the squared distance is rounded
-// operation by operation, so the decision does not depend on contraction.
+// operation by operation (contraction into fused multiply-adds is off in this
+// kernel), so the decision matches a plain FP64 evaluation.
 template <int Q>
 __global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int64_t n_int,
                                                       const double* __restrict__ pos,
                                                       const double* __restrict__ nrm, int rule, double dx, double r,
                                                       uint32_t* __restrict__ unknown) {
+#pragma clang fp contract(off)
   using L = Lattice<Q>;
   const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (b >= nb) return;
@@ -308,23 +310,23 @@ __global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int
     const double nx = nrm[b], ny = nrm[nb + b], nz = nrm[2 * nb + b];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
-      const double en = __dadd_rn(__dadd_rn((double)L::ex[k] * nx, (double)L::ey[k] * ny), (double)L::ez[k] * nz);
+      const double en = (double)L::ex[k] * nx + (double)L::ey[k] * ny + (double)L::ez[k] * nz;
       if (en > 0.0) mask |= 1u << k;
     }
   } else {
     const int64_t i = n_int + b;
     const double x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
-    const double r2 = __dmul_rn(r, r);
+    const double r2 = r * r;
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const double e[3] = {(double)L::ex[k], (double)L::ey[k], (double)L::ez[k]};
       double d2 = 0.0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const double p = __dsub_rn(x[a], dx * e[a]);
-        const double c = 0.5 + rint(__dsub_rn(p, 0.5));
-        const double d = __dsub_rn(p, c);
-        d2 = a == 0 ? __dmul_rn(d, d) : __dadd_rn(d2, __dmul_rn(d, d));
+        const double p = x[a] - dx * e[a];
+        const double c = 0.5 + rint(p - 0.5);
+        const double d = p - c;
+        d2 = a == 0 ? d * d : d2 + d * d;
       }
       if (d2 < r2) mask |= 1u << k;
     }

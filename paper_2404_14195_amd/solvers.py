@@ -30,12 +30,14 @@ class Discretization:
         self.device = torch.device(device)
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)
         self.pos = t(cloud.pos.T, torch.float64)
-        self.sten_host = nodecloud.solver_stencils(cloud, nl)
-        self.sten = t(self.sten_host.T, torch.int32)
+        # interior rows: nl nearest nodes; surface rows: self + nl - 1 nearest interior nodes
+        self.sten = api.solver_stencils(self.pos, self.n_int, nl)
+        self._sten_host = None
         self.nrm = t(cloud.nrm.T, torch.float64) if self.nb else torch.zeros((3, 0), dtype=torch.float64,
                                                                                device=self.device)
-        self.sn = t(nodecloud.neumann_stencils(cloud, nl).T, torch.int32)
-        self.sb = self.sten[:, self.n_int:].contiguous()
+        # the Neumann rows and the drag's gradient rows use the surface stencils
+        self.sn = self.sten[:, self.n_int:].contiguous()
+        self.sb = self.sn
         if plan:
             pp = nodecloud.plane_plan(cloud, M, nl)
             self.plan = pp
@@ -45,6 +47,14 @@ class Discretization:
             self.s_w = api.rbffd_weights(self.pos, self.s_idx, [("shift_row",)], rowvec=self.s_shift)[0][0].contiguous()
         self.phi, self.area = api.sc_cell(cloud.r) if cloud.r > 0 else (1.0, 0.0)
         self.red_ws = api.reduce_workspace(max(self.n, 5 * M * M), self.device)
+
+    @property
+    def sten_host(self):
+        """The same stencils [n][nl] from the host fixture (k-d tree), for
+        checks that must not take their inputs from the GPU path."""
+        if self._sten_host is None:
+            self._sten_host = nodecloud.solver_stencils(self.cloud, self.nl)
+        return self._sten_host
 
 
 class ACMSolver:

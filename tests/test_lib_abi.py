@@ -124,3 +124,21 @@ def test_scale_host_checks(lib):
     assert lib.mpf_scale(10, None, 0, 2.0, None) == -1
     assert lib.mpf_scale(10, fake, 2, 2.0, None) == -1  # only FP64 or FP32 arrays
     assert lib.mpf_scale(0, fake, 0, 2.0, None) == 0    # nothing to do, nothing launched
+
+
+def test_knn_host_checks(lib):
+    fake = ctypes.c_void_p(0x1000)
+    ws = lib.mpf_knn_workspace(1000)
+    assert ws >= 1000 * (3 * 8 + 4 + 4)  # sorted coordinates, indices, cells
+    assert lib.mpf_knn_workspace(10 ** 7) > lib.mpf_knn_workspace(10 ** 6)
+    # k in [1, min(64, n)], strides at least the counts, a large enough workspace
+    assert lib.mpf_knn(fake, 1000, 1000, fake, 10, 10, 0, fake, 10, fake, ws, None) == -1
+    assert lib.mpf_knn(fake, 1000, 1000, fake, 10, 10, 65, fake, 10, fake, ws, None) == -1
+    assert lib.mpf_knn(fake, 20, 20, fake, 10, 10, 21, fake, 10, fake, ws, None) == -1
+    assert lib.mpf_knn(fake, 1000, 999, fake, 10, 10, 30, fake, 10, fake, ws, None) == -1
+    assert lib.mpf_knn(fake, 1000, 1000, fake, 10, 10, 30, fake, 9, fake, ws, None) == -1
+    assert lib.mpf_knn(fake, 1000, 1000, fake, 10, 10, 30, fake, 10, fake, ws - 1, None) == -1
+    assert lib.mpf_knn(fake, 1000, 1000, None, 0, 0, 30, None, 0, None, 0, None) == 0  # no queries
+    assert lib.mpf_solver_stencils(fake, 1000, 20, 30, fake, fake, ws, None) == -1  # surface rows need 29 interior
+    assert lib.mpf_solver_stencils(fake, 1000, 900, 65, fake, fake, ws, None) == -1
+    assert lib.mpf_solver_stencils(fake, 1000, 900, 30, fake, fake, 100, None) == -1
