@@ -46,7 +46,7 @@ def _load():
         lib.mpfo_weights.restype = i32
         lib.mpfo_weights.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp, vp, vp]
         lib.mpfo_acm_run.restype = i32
-        lib.mpfo_acm_run.argtypes = [i64, i64, i32, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, vp, i32, vp, vp, vp, i32]
+        lib.mpfo_acm_run.argtypes = [i64, i64, i32, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, vp, i32, vp, vp, vp, i32, i32]
         lib.mpfo_lattice.restype = i32
         lib.mpfo_lattice.argtypes = [i32, vp, vp, vp]
         lib.mpfo_lbm_equilibrium.restype = None
@@ -137,10 +137,13 @@ def acm_dt(h_min: float, nu: float) -> float:
 
 
 class ACM:
-    """ACM state and parameters on one node cloud (defaults: Sec. 2.3)."""
+    """ACM state and parameters on one node cloud (defaults: Sec. 2.3).
+    edac=True takes the entropically damped pressure equation (see
+    mpfo_acm_run)."""
 
     def __init__(self, pos, n_int, sten, nrm, sten_n=None, nu=1.0, rho=1.0, dt=None, beta=10.0, v_ref=1.0,
-                 g=(1.0, 0.0, 0.0), n_p=3, h_min=None):
+                 g=(1.0, 0.0, 0.0), n_p=3, h_min=None, edac=False):
+        self.edac = bool(edac)
         self.pos, self.n_int, self.sten, self.nrm = _c(pos, np.float64), int(n_int), _c(sten, np.int32), _c(nrm, np.float64)
         self.n, self.nl = self.sten.shape
         self.nu, self.rho, self.beta, self.v_ref, self.n_p = nu, rho, beta, v_ref, n_p
@@ -169,7 +172,7 @@ class ACM:
         rc = lib.mpfo_acm_run(self.n, self.n_int, self.nl, self.sten.ctypes.data, self.w.ctypes.data,
                               self.sn.ctypes.data, self.wn.ctypes.data, self.nu, self.rho, self.dt, self.beta, self.v_ref,
                               self.g.ctypes.data, self.n_p, self.v.ctypes.data, self.p.ctypes.data,
-                              self.C.ctypes.data, int(n_steps))
+                              self.C.ctypes.data, int(n_steps), int(self.edac))
         if rc != 0:
             raise RuntimeError("mpfo_acm_run failed")
 

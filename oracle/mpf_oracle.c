@@ -281,14 +281,20 @@ int mpfo_weights(const double* pos, int64_t n_nodes, const int32_t* sten, int64_
  *   boundary p from dp/dn = 0, solved for the node's own value with the
  *     neighbours' current values (Jacobi over boundary nodes)
  *   v_i <- v'_i - (dt/rho) (grad p)_i       (interior)
- *   C = beta * max(max_i |v_i|, |v_ref|). */
+ *   C = beta * max(max_i |v_i|, |v_ref|).
+ * edac = 1 takes the entropically damped form of the pressure equation that
+ * Sec. 2.3 names as the remedy for the pressure oscillations of Sec. 3.6,
+ * dp/dt + v . grad p = -rho C^2 div v + nu lap p, as the pressure update:
+ *   p_i <- p_i + dt (-C^2 rho (div v)_i - v_i . (grad p)_i + nu (lap p)_i)
+ * with every term from the pressure before the update (Jacobi). */
 int mpfo_acm_run(int64_t n, int64_t n_int, int nl, const int32_t* sten, const double* w, const int32_t* sn,
                  const double* wn,
                  double nu, double rho, double dt, double beta, double v_ref, const double* g, int n_p,
-                 double* v, double* p, double* C, int n_steps) {
+                 double* v, double* p, double* C, int n_steps, int edac) {
   const int64_t nb = n - n_int;
   double* vp = (double*)malloc(sizeof(double) * 3 * n);
   double* pb = (double*)malloc(sizeof(double) * (nb > 0 ? nb : 1));
+  double* pold = (double*)malloc(sizeof(double) * n);
   for (int step = 0; step < n_steps; ++step) {
     /* intermediate velocity, Eq. MNS_intermediate */
     for (int64_t i = 0; i < n_int; ++i) {
@@ -312,17 +318,29 @@ int mpfo_acm_run(int64_t n, int64_t n_int, int nl, const int32_t* sten, const do
     /* pressure-velocity coupling */
     for (int it = 0; it < n_p; ++it) {
       double c2 = (*C) * (*C);
+      memcpy(pold, p, sizeof(double) * n);
       for (int64_t i = 0; i < n_int; ++i) { /* Eq. MNS_pressure */
         const int32_t* S = sten + i * nl;
         const double* wx = w + (i * 4 + 0) * nl;
         const double* wy = w + (i * 4 + 1) * nl;
         const double* wz = w + (i * 4 + 2) * nl;
+        const double* wl = w + (i * 4 + 3) * nl;
         double div = 0.0;
         for (int j = 0; j < nl; ++j) {
           const double* u = v + 3 * (int64_t)S[j];
           div += wx[j] * u[0] + wy[j] * u[1] + wz[j] * u[2];
         }
-        p[i] -= dt * c2 * rho * div;
+        if (!edac) {
+          p[i] -= dt * c2 * rho * div;
+          continue;
+        }
+        double gp[3] = {0.0, 0.0, 0.0}, lp = 0.0;
+        for (int j = 0; j < nl; ++j) {
+          double q = pold[S[j]];
+          gp[0] += wx[j] * q; gp[1] += wy[j] * q; gp[2] += wz[j] * q; lp += wl[j] * q;
+        }
+        double adv = v[3 * i] * gp[0] + v[3 * i + 1] * gp[1] + v[3 * i + 2] * gp[2];
+        p[i] = pold[i] + dt * (-c2 * rho * div - adv + nu * lp);
       }
       for (int64_t b = 0; b < nb; ++b) { /* dp/dn = 0 on the grain */
         const int32_t* S = sn + b * nl;
@@ -347,7 +365,7 @@ int mpfo_acm_run(int64_t n, int64_t n_int, int nl, const int32_t* sten, const do
       *C = beta * (vmax > v_ref ? vmax : v_ref); /* Eq. MNS_C */
     }
   }
-  free(vp); free(pb);
+  free(vp); free(pb); free(pold);
   return 0;
 }
 

@@ -105,3 +105,67 @@ def test_time_steps_match_paper_footnotes():
         h, dt, tol = float(h), float(dt), float(tol)
         got = O.acm_dt(h, 1.0) if solver == "acm" else O.lbm_units(h, 1.0, 1.0, (0, 0, 0), 1.0)["dt"]
         assert abs(got - dt) <= tol * dt, (solver, h, got, dt)
+
+
+# --- the entropically damped pressure equation (the remedy Sec. 2.3 names) ---
+
+def test_edac_keeps_poiseuille_a_fixed_point(channel):
+    """Constant pressure has no gradient and no Laplacian, so the damping and
+    advection terms vanish and the Poiseuille profile stays exact."""
+    c, S, Sn = channel
+    a = O.ACM(c.pos, c.n_int, S, c.nrm, sten_n=Sn, h_min=0.05, v_ref=1e-3, edac=True)
+    u = poiseuille(c)
+    a.v[:, 0] = u
+    a.run(50)
+    assert np.abs(a.v[:, 0] - u).max() < 1e-12 * u.max()
+    assert np.ptp(a.p) < 1e-10
+
+
+def stencil_safe(S, safe):
+    """Nodes whose own stencil and every neighbour's stencil avoid the seam."""
+    return safe & safe[S].all(1)
+
+
+def test_edac_pressure_diffusion_exact_on_quadratics(box):
+    """From rest without forcing (div v' = 0, v' = 0) one coupling iteration
+    gives p = q + dt nu lap q with lap q = 2 - 1 = 1, and then v = -(dt/rho)
+    grad q (the added constant has no gradient)."""
+    c, S, safe = box
+    X, Y, Z = (c.pos - 0.5).T
+    dt, nu, rho = 2e-4, 0.7, 1.3
+    a = O.ACM(c.pos, c.n, S, np.zeros((0, 3)), dt=dt, nu=nu, rho=rho, g=(0, 0, 0), n_p=1, edac=True)
+    q = X * X + X * Y - 0.5 * Z * Z
+    a.p[:] = q
+    a.run(1)
+    assert np.abs(a.p[safe] - (q[safe] + dt * nu * 1.0)).max() < 1e-14
+    s2 = stencil_safe(S, safe)
+    assert s2.sum() > 50
+    gq = np.stack([2 * X + Y, X, -Z], 1)
+    assert np.abs(a.v[s2] + dt / rho * gq[s2]).max() < 1e-13
+
+
+def test_edac_pressure_advection_exact_on_quadratics(box):
+    """With beta = 0 the compressibility term is off (C = 0) and a
+    divergence-free quadratic v = (Y^2, Z^2, X^2) is advanced by the closed form
+    of the predictor; the pressure then moves by dt (-v' . grad q + nu lap q)."""
+    c, S, safe = box
+    X, Y, Z = (c.pos - 0.5).T
+    dt, nu = 1e-4, 0.9
+    g = np.array([0.7, -0.2, 0.1])
+    a = O.ACM(c.pos, c.n, S, np.zeros((0, 3)), dt=dt, nu=nu, beta=0.0, v_ref=1.0, g=g, n_p=1, edac=True)
+    v0 = np.stack([Y * Y, Z * Z, X * X], 1)
+    a.v[:] = v0
+    q = X * X + X * Y - 0.5 * Z * Z
+    a.p[:] = q
+    a.run(1)
+    adv = np.stack([Z * Z * 2 * Y, X * X * 2 * Z, Y * Y * 2 * X], 1)
+    vp = v0 + dt * (nu * 2.0 - adv + g)
+    gq = np.stack([2 * X + Y, X, -Z], 1)
+    expect = q + dt * (-(vp * gq).sum(1) + nu * 1.0)
+    assert np.abs(a.p[safe] - expect[safe]).max() < 1e-13
+    # the plain method leaves p alone here (C = 0)
+    b = O.ACM(c.pos, c.n, S, np.zeros((0, 3)), dt=dt, nu=nu, beta=0.0, v_ref=1.0, g=g, n_p=1)
+    b.v[:] = v0
+    b.p[:] = q
+    b.run(1)
+    assert np.array_equal(b.p, q)
