@@ -269,15 +269,20 @@ def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
     """The paper's comparison of the two solvers on identical nodes: the
     71k-node cell, MLBM and ACM (both FP32 weights, FP64 state) started from
     the learned prediction and run until k changes by < 1e-8 relative per
-    check; reports k, drag K and the field differences."""
+    check (ACM at most max_acm_steps); reports k, drag K and the field
+    differences.  ACM runs twice: as written, and with the damped pressure
+    equation the paper names for its pressure oscillations, whose surface
+    pressure is compared with the MLBM's separately."""
     import numpy as np
     from paper_2404_14195_amd import MPF_MIXED
     from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver
     say = lambda m: print(f"[bench] cross-validation: {m}", file=sys.stderr, flush=True)
     disc = Discretization(nc.config_cloud("lbm_mid"), nl=30, M=64)
     out = {}
+    fields = {}
     for name, make, check in (("mlbm", lambda: MLBMSolver(disc, q=19, precision=MPF_MIXED), 500),
-                              ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED), 5000)):
+                              ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED), 5000),
+                              ("acm_edac", lambda: ACMSolver(disc, precision=MPF_MIXED, edac=True), 5000)):
         s = make()
         (ws_model.load_mlbm if name == "mlbm" else ws_model.load_acm)(s)
         t0 = time.perf_counter()
@@ -292,24 +297,28 @@ def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
         F, K = s.drag()
         if name == "mlbm":
             v, p = s.macros()
-            v = v.clone()
-            p = p.clone()
         else:
-            v, p = s.v.double().clone(), s.p.double().clone()
+            v, p = s.v, s.p
+        fields[name] = (v.double().cpu().numpy(), p.double().cpu().numpy())
         out[name] = {"k": ks[-1], "K": float(K), "steps": s.steps, "seconds": time.perf_counter() - t0,
-                     "settled": len(ks) > 2 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1]),
-                     "_v": v.cpu().numpy(), "_p": p.cpu().numpy()}
+                     "settled": len(ks) > 2 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1])}
         say(f"{name}: k = {ks[-1]:.8e}, K = {float(K):.6f} after {s.steps} steps ({out[name]['seconds']:.1f}s)")
         del s
     n_int = disc.n_int
-    vm, va = out["mlbm"].pop("_v")[:, :n_int], out["acm"].pop("_v")[:, :n_int]
-    pm, pa = out["mlbm"].pop("_p"), out["acm"].pop("_p")
-    pm, pa = pm - pm.mean(), pa - pa.mean()
-    out["k_rel_diff"] = abs(out["mlbm"]["k"] / out["acm"]["k"] - 1)
-    out["K_rel_diff"] = abs(out["mlbm"]["K"] / out["acm"]["K"] - 1)
-    out["v_rel_l2_diff"] = float(np.linalg.norm(vm - va) / np.linalg.norm(va))
-    out["v_max_diff_over_max_v"] = float(np.abs(vm - va).max() / np.abs(va).max())
-    out["p_rel_l2_diff"] = float(np.linalg.norm(pm - pa) / np.linalg.norm(pa))
+    vm, pm = fields["mlbm"]
+    vm = vm[:, :n_int]
+    pm = pm - pm.mean()
+    for name in ("acm", "acm_edac"):
+        va, pa = fields[name]
+        va = va[:, :n_int]
+        pa = pa - pa.mean()
+        out[name + "_vs_mlbm"] = {
+            "k_rel_diff": abs(out["mlbm"]["k"] / out[name]["k"] - 1),
+            "K_rel_diff": abs(out["mlbm"]["K"] / out[name]["K"] - 1),
+            "v_rel_l2_diff": float(np.linalg.norm(vm - va) / np.linalg.norm(va)),
+            "v_max_diff_over_max_v": float(np.abs(vm - va).max() / np.abs(va).max()),
+            "p_rel_l2_diff": float(np.linalg.norm(pm - pa) / np.linalg.norm(pa)),
+            "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:]))}
     say(json.dumps(out))
     return out
 
@@ -397,11 +406,13 @@ def weights_batch(torch, nc, api):
     return out
 
 
-def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4):
+def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4, edac=False):
     """Algorithmic bytes of one ACM node-step: predictor (4 operators, v in,
     v' out), then per coupling iteration a pressure pass (3 operators, v and p
-    in, p out) and a velocity pass (3 operators, p and v' in, v out)."""
-    return ((4 * s_w + s_i) * nl + 6 * s_f + n_p * ((3 * s_w + s_i) * nl + 5 * s_f)
+    in, p out; the damped pressure equation adds the Laplacian, a fourth
+    operator) and a velocity pass (3 operators, p and v' in, v out)."""
+    ops_p = 4 if edac else 3
+    return ((4 * s_w + s_i) * nl + 6 * s_f + n_p * ((ops_p * s_w + s_i) * nl + 5 * s_f)
             + n_p * ((3 * s_w + s_i) * nl + 7 * s_f))
 
 
@@ -453,6 +464,25 @@ def acm_and_weights(torch, nc, api):
                   file=sys.stderr, flush=True)
             del s, s2
         rec["k_rel_err_fp32"] = abs(rec["fp32"]["k_after"] / rec["fp64"]["k_after"] - 1.0)
+        if name == "acm_large":  # the damped pressure equation (one more operator per pressure pass)
+            for pname, prec in (("edac_fp64", MPF_F64), ("edac_fp32", MPF_F32)):
+                s = ACMSolver(disc, precision=prec, edac=True)
+                s.run(5)
+                torch.cuda.synchronize()
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                s.run(steps)
+                ev1.record()
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1)
+                sz = 8 if prec == MPF_F64 else 4
+                bpn = acm_bytes_per_node_step(30, sz, sz, edac=True)
+                rec[pname] = {"us_per_step": ms * 1e3 / steps, "node_steps_per_s": cloud.n * steps / (ms * 1e-3),
+                              "bytes_per_node_step": bpn,
+                              "hbm_frac": bpn * cloud.n / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS}
+                print(f"[bench] {name} {pname}: {ms * 1e3 / steps:.1f} us/step", file=sys.stderr, flush=True)
+                del s
         out[name] = rec
         del disc
         torch.cuda.empty_cache()
@@ -504,6 +534,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
     ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
+    ap.add_argument("--xval-acm-steps", type=int, default=1_500_000, help="cap on the ACM steps of --cross-validate")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
     ap.add_argument("--weights-batch", action="store_true",
@@ -539,7 +570,8 @@ def main():
     if args.cross_validate:
         torch.cuda.set_device(0)
         ws_model, info = train_warm_start(torch, nc)
-        print(json.dumps({"cross_validation": cross_validate(torch, nc, ws_model), "warm_start_training": info}))
+        print(json.dumps({"cross_validation": cross_validate(torch, nc, ws_model, args.xval_acm_steps),
+                          "warm_start_training": info}))
         return
     if args.mlp:
         torch.cuda.set_device(0)

@@ -234,20 +234,27 @@ int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const 
  *       boundary)
  * vmax  dev double [1]: max_i |v_i| of the current state, in/out (0 for a
  *       state at rest); C is derived from it
- * ws    workspace of mpf_acm_workspace() bytes
+ * ws    workspace of mpf_acm_workspace() bytes (velocity and v' records
+ *       [n][4] and a second pressure [n])
  * precision: MPF_F64, MPF_F32 (weights and fields FP32, all arithmetic
  * except the max FP32) or MPF_MIXED (weights w, wn FP32; fields v, p and the
  * workspace FP64; FP64 arithmetic).
  * lanes: how many adjacent lanes share one node's stencil sum (1, 2, 4, 8 or
  * 16; 0 picks 8 for n_int <= 200000 and 2 above).  Results agree to rounding
- * (the order of the partial sums differs). */
+ * (the order of the partial sums differs).
+ * edac: 0 for the method as written; 1 for the entropically damped pressure
+ * equation, which Sec. 2.3 names as the remedy for the stagnant-region
+ * pressure oscillations of Sec. 3.6.  Its pressure update is
+ *     p_i += dt (-C^2 rho (div v)_i - v_i . (grad p)_i + nu (lap p)_i)
+ * with the iteration's velocity (v' at the first) and every pressure term
+ * from before the update; the other passes are unchanged. */
 typedef struct {
   double nu, rho, dt, beta, v_ref;
   double g[3];
   int32_t n_p;
   int32_t precision;
   int32_t lanes;
-  int32_t reserved;
+  int32_t edac;
 } mpf_acm_params;
 
 size_t mpf_acm_workspace(int64_t n, int precision);

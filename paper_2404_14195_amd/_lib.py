@@ -72,7 +72,7 @@ class AcmParams(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("rho", ctypes.c_double), ("dt", ctypes.c_double),
                 ("beta", ctypes.c_double), ("v_ref", ctypes.c_double), ("g", ctypes.c_double * 3),
                 ("n_p", ctypes.c_int32), ("precision", ctypes.c_int32), ("lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("edac", ctypes.c_int32)]
 
 
 class LbmParams(ctypes.Structure):

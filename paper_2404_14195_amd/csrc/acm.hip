@@ -10,6 +10,11 @@
 //           neumann  (boundary)  p_b from dp/dn = 0, in place (its stencil
 //                                holds only interior neighbours)
 //           velocity (interior)  v = v' - dt/rho grad p, max |v| }
+// With the entropically damped pressure equation (Sec. 2.3 names it as the
+// remedy for the oscillations of Sec. 3.6) the pressure pass also gathers p:
+//   p <- p + dt (-C^2 rho div v - v . grad p + nu lap p),
+// reading the old pressure and writing a second buffer (Jacobi); the buffers
+// alternate from pass to pass.
 // C is never stored: each pressure pass derives it from the running max |v|
 // (device double, updated with an integer atomicMax on the bit pattern, which
 // orders non-negative doubles), so no host round trip enters a step.
@@ -104,7 +109,8 @@ struct Fields {
   const int32_t* sn;
   const TW* wn;  // [nl][nb]
   T* V;         // [n][4] velocity records (x, y, z, 0), the run's working copy of v
-  T* p;         // [n]
+  T* p;         // [n] the caller's pressure
+  T* P1;        // [n] second pressure buffer (damped pressure equation only)
   T* VP;        // [n][4] v' records
   double* vmax;
   T nu, dt, dt_rho, g0, g1, g2;
@@ -153,8 +159,8 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
 }
 
 template <typename T, typename TW, int LPN, int NLC>
-__device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* __restrict__ vsrc, T coef, int64_t i,
-                                              int sl) {
+__device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* __restrict__ vsrc,
+                                              const T* pin, T* pout, T coef, int64_t i, int sl) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   const int64_t n = F.n, os = (int64_t)nl * n;
   T div = T(0);
@@ -164,30 +170,63 @@ __device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* _
     div += (T)F.w[at] * r.x + (T)F.w[os + at] * r.y + (T)F.w[2 * os + at] * r.z;
   });
   div = group_sum<LPN>(div);
-  if (sl == 0) F.p[i] -= coef * div;
+  if (sl == 0) pout[i] = pin[i] - coef * div;  // in place (pin == pout) for the plain method
+}
+
+// The damped pressure equation: p_new = p - coef div v - dt v_i . grad p + dt nu lap p.
+template <typename T, typename TW, int LPN, int NLC>
+__device__ __forceinline__ void pressure_edac_node(const Fields<T, TW>& F, const T* __restrict__ vsrc,
+                                                   const T* __restrict__ pin, T* __restrict__ pout, T coef,
+                                                   int64_t i, int sl) {
+  const int nl = NLC ? NLC : F.nl;
+  const int64_t n = F.n, os = (int64_t)nl * n;
+  T div = T(0), gx = T(0), gy = T(0), gz = T(0), lp = T(0);
+  columns<LPN, NLC>(nl, 0, sl, [&](int j) {
+    const int64_t at = (int64_t)j * n + i;
+    const int s = F.sten[at];
+    const T wx = (T)F.w[at], wy = (T)F.w[os + at], wz = (T)F.w[2 * os + at], wl = (T)F.w[3 * os + at];
+    const auto r = load4(vsrc, s);
+    const T ps = pin[s];
+    div += wx * r.x + wy * r.y + wz * r.z;
+    gx += wx * ps;
+    gy += wy * ps;
+    gz += wz * ps;
+    lp += wl * ps;
+  });
+  div = group_sum<LPN>(div);
+  gx = group_sum<LPN>(gx);
+  gy = group_sum<LPN>(gy);
+  gz = group_sum<LPN>(gz);
+  lp = group_sum<LPN>(lp);
+  if (sl == 0) {
+    const auto ri = load4(vsrc, i);
+    const T adv = ri.x * gx + ri.y * gy + ri.z * gz;
+    pout[i] = pin[i] - coef * div + F.dt * (F.nu * lp - adv);
+  }
 }
 
 template <typename T, typename TW, int LPN, int NLC>
-__device__ __forceinline__ void neumann_node(const Fields<T, TW>& F, int64_t b, int sl) {
+__device__ __forceinline__ void neumann_node(const Fields<T, TW>& F, T* P, int64_t b, int sl) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   T s = T(0);
   columns<LPN, NLC>(nl, 1, sl, [&](int j) {
     const int64_t at = (int64_t)j * F.nb + b;
-    s += (T)F.wn[at] * F.p[F.sn[at]];
+    s += (T)F.wn[at] * P[F.sn[at]];
   });
   s = group_sum<LPN>(s);
-  if (sl == 0) F.p[F.n_int + b] = -s / (T)F.wn[b];
+  if (sl == 0) P[F.n_int + b] = -s / (T)F.wn[b];
 }
 
 // returns |v_i| (valid in every lane of the node's group)
 template <typename T, typename TW, int LPN, int NLC>
-__device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, int64_t i, int sl) {
+__device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, const T* __restrict__ P, int64_t i,
+                                                int sl) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   const int64_t n = F.n, os = (int64_t)nl * n;
   T gp[3] = {T(0), T(0), T(0)};
   columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
-    const T ps = F.p[F.sten[at]];
+    const T ps = P[F.sten[at]];
     gp[0] += (T)F.w[at] * ps;
     gp[1] += (T)F.w[os + at] * ps;
     gp[2] += (T)F.w[2 * os + at] * ps;
@@ -239,30 +278,45 @@ __global__ __launch_bounds__(kBlock) void k_predictor(Fields<T, TW> F) {
 }
 
 template <typename T, typename TW, int LPN, int NLC>
-__global__ __launch_bounds__(kBlock) void k_pressure(Fields<T, TW> F, const T* __restrict__ vsrc) {
+__global__ __launch_bounds__(kBlock) void k_pressure(Fields<T, TW> F, const T* __restrict__ vsrc, T* P) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_node<T, TW, LPN, NLC>(F, vsrc, coupling_coef(F), i, (int)(g % LPN));
+  pressure_node<T, TW, LPN, NLC>(F, vsrc, P, P, coupling_coef(F), i, (int)(g % LPN));
 }
 
 template <typename T, typename TW, int LPN, int NLC>
-__global__ __launch_bounds__(kBlock) void k_neumann(Fields<T, TW> F) {
+__global__ __launch_bounds__(kBlock) void k_pressure_edac(Fields<T, TW> F, const T* __restrict__ vsrc,
+                                                          const T* __restrict__ pin, T* __restrict__ pout) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = g / LPN;
+  if (i >= F.n_int) return;
+  pressure_edac_node<T, TW, LPN, NLC>(F, vsrc, pin, pout, coupling_coef(F), i, (int)(g % LPN));
+}
+
+template <typename T, typename TW, int LPN, int NLC>
+__global__ __launch_bounds__(kBlock) void k_neumann(Fields<T, TW> F, T* P) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g == 0) *F.vmax = 0.0;  // the pressure pass has consumed it; the velocity pass rebuilds it
   const int64_t b = g / LPN;
   if (b >= F.nb) return;
-  neumann_node<T, TW, LPN, NLC>(F, b, (int)(g % LPN));
+  neumann_node<T, TW, LPN, NLC>(F, P, b, (int)(g % LPN));
 }
 
 template <typename T, typename TW, int LPN, int NLC>
-__global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F) {
+__global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F, const T* __restrict__ P) {
   __shared__ double red[kBlock / kWave];
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   double mag = 0.0;
-  if (i < F.n_int) mag = velocity_node<T, TW, LPN, NLC>(F, i, (int)(g % LPN));
+  if (i < F.n_int) mag = velocity_node<T, TW, LPN, NLC>(F, P, i, (int)(g % LPN));
   block_max_into(mag, red, F.vmax);
+}
+
+template <typename T>
+__global__ void copy_field(int64_t n, const T* __restrict__ src, T* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 template <typename T>
@@ -276,16 +330,27 @@ __global__ void fill_zero(T* __restrict__ x, int64_t n) {
 constexpr int64_t kFewNodes = 200000;
 
 template <typename T, typename TW, int LPN, int NLC>
-int run_launches(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
+int run_launches(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
+  T* cur = F.p;  // the pressure of the current iteration (alternates with F.P1 when damped)
   for (int s = 0; s < n_steps; ++s) {
     hipLaunchKernelGGL((k_predictor<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
     for (int it = 0; it < n_p; ++it) {
-      hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)(it == 0 ? F.VP : F.V));
-      hipLaunchKernelGGL((k_neumann<T, TW, LPN, NLC>), dim3(gb), dim3(kBlock), 0, st, F);
-      hipLaunchKernelGGL((k_velocity<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
+      const T* vsrc = it == 0 ? F.VP : F.V;
+      if (edac) {
+        T* nxt = cur == F.p ? F.P1 : F.p;
+        hipLaunchKernelGGL((k_pressure_edac<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, vsrc,
+                           (const T*)cur, nxt);
+        cur = nxt;
+      } else {
+        hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, vsrc, cur);
+      }
+      hipLaunchKernelGGL((k_neumann<T, TW, LPN, NLC>), dim3(gb), dim3(kBlock), 0, st, F, cur);
+      hipLaunchKernelGGL((k_velocity<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)cur);
     }
   }
+  if (cur != F.p)
+    hipLaunchKernelGGL(copy_field<T>, dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, st, F.n, (const T*)cur, F.p);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
@@ -293,8 +358,9 @@ int run_launches(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
 // stencils of 30 nodes (the measured size) get fully unrolled column loops,
 // which lets every lane issue all its index, weight and gather loads early
 template <typename T, typename TW, int LPN>
-int launch_nl(Fields<T, TW>& F, int n_steps, int n_p, hipStream_t st) {
-  return F.nl == 30 ? run_launches<T, TW, LPN, 30>(F, n_steps, n_p, st) : run_launches<T, TW, LPN, 0>(F, n_steps, n_p, st);
+int launch_nl(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
+  return F.nl == 30 ? run_launches<T, TW, LPN, 30>(F, n_steps, n_p, edac, st)
+                    : run_launches<T, TW, LPN, 0>(F, n_steps, n_p, edac, st);
 }
 
 template <typename T, typename TW>
@@ -305,6 +371,7 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.p = p;
   F.V = reinterpret_cast<T*>(ws);
   F.VP = F.V + 4 * n;
+  F.P1 = F.VP + 4 * n;
   F.vmax = vmax;
   F.nu = (T)prm->nu; F.dt = (T)prm->dt; F.dt_rho = (T)(prm->dt / prm->rho);
   F.g0 = (T)prm->g[0]; F.g1 = (T)prm->g[1]; F.g2 = (T)prm->g[2];
@@ -314,15 +381,16 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   const unsigned gn = grid_for(n, kBlock);
   hipLaunchKernelGGL(to_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)v, F.V);
   hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(4 * n, kBlock)), dim3(kBlock), 0, st, F.VP, 4 * n);
+  const bool edac = prm->edac != 0;
   int lanes = prm->lanes;
   if (lanes == 0) lanes = n_int <= kFewNodes ? 8 : 2;
   int rc;
   switch (lanes) {
-    case 1: rc = launch_nl<T, TW, 1>(F, n_steps, prm->n_p, st); break;
-    case 2: rc = launch_nl<T, TW, 2>(F, n_steps, prm->n_p, st); break;
-    case 4: rc = launch_nl<T, TW, 4>(F, n_steps, prm->n_p, st); break;
-    case 8: rc = launch_nl<T, TW, 8>(F, n_steps, prm->n_p, st); break;
-    default: rc = launch_nl<T, TW, 16>(F, n_steps, prm->n_p, st); break;
+    case 1: rc = launch_nl<T, TW, 1>(F, n_steps, prm->n_p, edac, st); break;
+    case 2: rc = launch_nl<T, TW, 2>(F, n_steps, prm->n_p, edac, st); break;
+    case 4: rc = launch_nl<T, TW, 4>(F, n_steps, prm->n_p, edac, st); break;
+    case 8: rc = launch_nl<T, TW, 8>(F, n_steps, prm->n_p, edac, st); break;
+    default: rc = launch_nl<T, TW, 16>(F, n_steps, prm->n_p, edac, st); break;
   }
   if (rc) return rc;
   hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.V, v);
@@ -335,7 +403,7 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
 
 extern "C" size_t mpf_acm_workspace(int64_t n, int precision) {
   const size_t es = precision == MPF_F32 ? sizeof(float) : sizeof(double);
-  return n > 0 ? 8 * (size_t)n * es + 256 : 256;  // V and V' records [n][4]
+  return n > 0 ? 9 * (size_t)n * es + 256 : 256;  // V and V' records [n][4], a second pressure [n]
 }
 
 extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
@@ -347,6 +415,7 @@ extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, 
     return MPF_ERR_ARG;
   if (n > n_int && (!sn || !wn)) return MPF_ERR_ARG;
   if (prm->precision != MPF_F64 && prm->precision != MPF_F32 && prm->precision != MPF_MIXED) return MPF_ERR_ARG;
+  if (prm->edac != 0 && prm->edac != 1) return MPF_ERR_ARG;
   if (prm->lanes != 0 && prm->lanes != 1 && prm->lanes != 2 && prm->lanes != 4 && prm->lanes != 8 &&
       prm->lanes != 16)
     return MPF_ERR_ARG;

@@ -61,11 +61,11 @@ class ACMSolver:
     """Artificial-compressibility Navier-Stokes (Sec. 2.3) on a Discretization."""
 
     def __init__(self, disc: Discretization, precision: int = MPF_F64, nu=1.0, rho=1.0, dt=None, beta=10.0,
-                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0):
+                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False):
         self.d, self.precision = disc, precision
         dt = 0.1 * disc.cloud.h_min ** 2 / (2.0 * nu) if dt is None else dt
         self.prm = AcmParams(nu=nu, rho=rho, dt=dt, beta=beta, v_ref=v_ref, g=(ctypesarr(g)), n_p=n_p,
-                             precision=precision, lanes=lanes)
+                             precision=precision, lanes=lanes, edac=int(bool(edac)))
         self.g = tuple(g)
         w64, w32, info = api.rbffd_weights(disc.pos, disc.sten, [("dx",), ("dy",), ("dz",), ("lap",)],
                                            want64=True, want32=precision != MPF_F64)

@@ -105,12 +105,12 @@ def test_weights_argument_errors(api, small_cloud):
 
 # ----------------------------------------------------------------- ACM
 
-def acm_pair(api, disc, precision, steps, v_ref=1e-3, lanes=0):
+def acm_pair(api, disc, precision, steps, v_ref=1e-3, lanes=0, edac=False, n_p=3):
     from paper_2404_14195_amd.solvers import ACMSolver
     c = disc.cloud
-    g = ACMSolver(disc, precision=precision, v_ref=v_ref, lanes=lanes)
+    g = ACMSolver(disc, precision=precision, v_ref=v_ref, lanes=lanes, edac=edac, n_p=n_p)
     o = O.ACM(c.pos, c.n_int, disc.sten_host, c.nrm, sten_n=nc.neumann_stencils(c, 30), h_min=c.h_min,
-              v_ref=v_ref)
+              v_ref=v_ref, edac=edac, n_p=n_p)
     g.run(steps)
     o.run(steps)
     return g, o
@@ -155,6 +155,39 @@ def test_acm_mixed_error_vs_fp64(api, disc_small):
     k = g.permeability()
     print(f"[acm mixed] k={k:.12e} k64={q_o:.12e} rel={abs(k / q_o - 1):.3e}", flush=True)
     assert k == pytest.approx(q_o, rel=1e-6)
+
+
+@pytest.mark.parametrize("lanes, n_p", [(0, 3), (1, 3), (16, 3), (0, 2)])
+def test_acm_edac_parity_fp64_500_steps(api, disc_small, lanes, n_p):
+    """The damped pressure equation, FP64, 500 steps, each side its own
+    weights: fields and permeability within 1e-10.  n_p = 3 ends each step on
+    the second pressure buffer every other step (and the run copies back);
+    n_p = 2 never leaves the caller's buffer at a step's end."""
+    g, o = acm_pair(api, disc_small, 0, 500, lanes=lanes, edac=True, n_p=n_p)
+    v = g.v.cpu().numpy().T
+    p = g.p.cpu().numpy()
+    assert np.abs(v - o.v).max() <= 1e-10 * np.abs(o.v).max()
+    assert np.abs(p - o.p).max() <= 1e-10 * np.abs(o.p).max()
+    pp = disc_small.plan
+    q_o = O.flux(pp.idx, O.plane_weights(disc_small.cloud.pos, pp.idx, pp.shift), o.v[:, 0], disc_small.n_all)
+    assert g.permeability() == pytest.approx(q_o, rel=1e-10)
+    # and it is not the plain method
+    _, o_plain = acm_pair(api, disc_small, 0, 10, n_p=n_p)
+    o_edac = O.ACM(disc_small.cloud.pos, disc_small.cloud.n_int, disc_small.sten_host, disc_small.cloud.nrm,
+                   sten_n=nc.neumann_stencils(disc_small.cloud, 30), h_min=disc_small.cloud.h_min, v_ref=1e-3,
+                   edac=True, n_p=n_p)
+    o_edac.run(10)
+    assert np.abs(o_edac.p - o_plain.p).max() > 1e-6 * np.abs(o_plain.p).max()
+
+
+@pytest.mark.parametrize("precision, tol", [(1, 1e-4), (2, 1e-6)])
+def test_acm_edac_reduced_precision(api, disc_small, precision, tol):
+    g, o = acm_pair(api, disc_small, precision, 500, edac=True)
+    pp = disc_small.plan
+    q_o = O.flux(pp.idx, O.plane_weights(disc_small.cloud.pos, pp.idx, pp.shift), o.v[:, 0], disc_small.n_all)
+    k = g.permeability()
+    print(f"[acm edac p{precision}] k={k:.12e} k64={q_o:.12e} rel={abs(k / q_o - 1):.3e}", flush=True)
+    assert k == pytest.approx(q_o, rel=tol)
 
 
 def test_acm_zero_steps_and_rest(api, disc_small):

@@ -92,6 +92,11 @@ def test_host_argument_checks(lib):
     assert lib.mpf_lbm_unknown(19, 10, 11, fake, fake, 0, 0.0, 0.0, fake, None) == -1  # n_int > n
     assert lib.mpf_flux_planes(5, 30, fake, fake, fake, 0, 0, fake, fake, 1 << 20, None) == -1
     assert lib.mpf_drag(10, fake, fake, 0, 2, 30, fake, fake, fake, 1.0, 1.0, 0.1, fake, fake, 8, None) == -4
+    prm.n_p, prm.edac = 3, 2
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, fake, 1, fake, 1 << 20,
+                           None) == -1  # edac is 0 or 1
+    prm.edac = 0
+    assert lib.mpf_acm_workspace(1000, 0) >= 9 * 1000 * 8  # v, v' records and a second pressure
     assert lib.mpf_acm_workspace(1000, 0) >= 3 * 1000 * 8
     assert lib.mpf_acm_workspace(1000, 1) >= 3 * 1000 * 4
 
