@@ -282,7 +282,10 @@ def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
     fields = {}
     for name, make, check in (("mlbm", lambda: MLBMSolver(disc, q=19, precision=MPF_MIXED), 500),
                               ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED), 5000),
-                              ("acm_edac", lambda: ACMSolver(disc, precision=MPF_MIXED, edac=True), 5000)):
+                              # the damped equation settles on the incompressible state only when the
+                              # sound speed is far above nu / l (here C = beta v_ref = 1000)
+                              ("acm_edac", lambda: ACMSolver(disc, precision=MPF_MIXED, edac=True, v_ref=100.0),
+                               5000)):
         s = make()
         (ws_model.load_mlbm if name == "mlbm" else ws_model.load_acm)(s)
         t0 = time.perf_counter()
@@ -320,6 +323,51 @@ def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
             "p_rel_l2_diff": float(np.linalg.norm(pm - pa) / np.linalg.norm(pa)),
             "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:]))}
     say(json.dumps(out))
+    return out
+
+
+def edac_sound_speed(torch, nc, ws_model, v_refs, cap=400_000):
+    """The damped pressure equation against the sound-speed floor: on the
+    71k-node cell, from the learned prediction, EDAC (mixed precision) with
+    C = beta max(max |v|, v_ref) for each v_ref, run until k settles (at most
+    cap steps); k, drag and field differences against the settled MLBM."""
+    import numpy as np
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver
+    disc = Discretization(nc.config_cloud("lbm_mid"), nl=30, M=64)
+
+    def settle(s, check):
+        ks = []
+        while s.steps < cap:
+            s.run(check)
+            ks.append(s.permeability())
+            if not np.isfinite(ks[-1]) or (len(ks) > 2 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1])):
+                break
+        return ks[-1]
+
+    m = MLBMSolver(disc, q=19, precision=MPF_MIXED)
+    ws_model.load_mlbm(m)
+    k_m = settle(m, 500)
+    vm, pm = m.macros()
+    vm, pm = vm.cpu().numpy()[:, :disc.n_int], pm.cpu().numpy()
+    pm = pm - pm.mean()
+    n_int = disc.n_int
+    out = {"mlbm": {"k": k_m, "K": float(m.drag()[1]), "steps": m.steps}, "edac": []}
+    for v_ref in v_refs:
+        t0 = time.perf_counter()
+        s = ACMSolver(disc, precision=MPF_MIXED, edac=True, v_ref=v_ref)
+        ws_model.load_acm(s)
+        k = settle(s, 5000)
+        va, pa = s.v.double().cpu().numpy()[:, :n_int], s.p.double().cpu().numpy()
+        pa = pa - pa.mean()
+        rec = {"v_ref": v_ref, "C_floor": s.prm.beta * v_ref, "k": k, "K": float(s.drag()[1]), "steps": s.steps,
+               "seconds": time.perf_counter() - t0, "k_rel_diff": abs(k / k_m - 1),
+               "v_rel_l2_diff": float(np.linalg.norm(vm - va) / np.linalg.norm(va)),
+               "p_rel_l2_diff": float(np.linalg.norm(pm - pa) / np.linalg.norm(pa)),
+               "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:]))}
+        print(f"[bench] edac v_ref={v_ref}: {json.dumps(rec)}", file=sys.stderr, flush=True)
+        out["edac"].append(rec)
+        del s
     return out
 
 
@@ -535,6 +583,8 @@ def main():
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
     ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
     ap.add_argument("--xval-acm-steps", type=int, default=1_500_000, help="cap on the ACM steps of --cross-validate")
+    ap.add_argument("--edac-vref-sweep", type=float, nargs="+", default=None,
+                    help="only the damped pressure equation for these sound-speed floors v_ref")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
     ap.add_argument("--weights-batch", action="store_true",
@@ -566,6 +616,11 @@ def main():
         print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
         torch.cuda.set_device(0)
         print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
+        return
+    if args.edac_vref_sweep:
+        torch.cuda.set_device(0)
+        ws_model, info = train_warm_start(torch, nc)
+        print(json.dumps({"edac_sound_speed": edac_sound_speed(torch, nc, ws_model, args.edac_vref_sweep)}))
         return
     if args.cross_validate:
         torch.cuda.set_device(0)
