@@ -7,7 +7,9 @@
 // rotation, one point per 1.15*hb^2 of surface (the density that reproduces
 // the paper's count of about 175 surface nodes for r = 0.04 at h_min = 0.01,
 // Sec. 3.4); a point is kept only if it lies inside the
-// cell, which drops the parts of the sphere that are covered by its images.
+// cell, which drops the parts of the sphere that are covered by its images,
+// and only if no surface point placed before it lies within half the surface
+// spacing (near the circles where the grain meets its images).
 // Each boundary node carries the unit normal pointing from the solid into the
 // fluid.
 //
@@ -16,8 +18,12 @@
 // uses, Sec. 2.1).  A dequeued node x_d spawns n_cand candidates on a sphere of
 // radius h(x_d); a candidate is kept if it is in the fluid and no existing node
 // lies closer than min(h(candidate), h(x_d)) under the minimum-image
-// convention.  The target
-// spacing is h(d) = min(h0 + slope*d, hmax), d the distance to the grain.
+// convention.  The target spacing h(d), d the distance to the grain, is either
+// linear, h(d) = min(h0 + slope*d, hmax), or the paper's Gaussian refinement
+// (Sec. 2.4, Eq. refinement_function), h = hmax - exp(-t^2 / (2 eps^2))
+// (hmax - hmin) with t = d / (sqrt(3)/2 - r): the distance normalised by the
+// largest distance from a grain that the cell holds (the printed product form
+// is read as this quotient, which the paper's node counts fit).
 //
 // Build: g++ -O2 -shared -fPIC _fill.cpp -o _libfill.so
 #include <cmath>
@@ -58,6 +64,20 @@ inline double wrap(double x) {
   return x >= 1.0 ? 0.0 : x;
 }
 inline double mi(double d) { return d - std::nearbyint(d); }
+
+struct Spacing {  // target internodal distance as a function of the distance d to the grain
+  int gaussian;
+  double a, b, c;  // linear: h0, slope, hmax; Gaussian: hmin, hmax, eps
+  double norm;     // Gaussian: sqrt(3)/2 - r
+  double operator()(double d) const {
+    d = std::fmax(d, 0.0);
+    if (!gaussian) return std::fmin(a + b * d, c);
+    const double t = d / norm;
+    return b - std::exp(-t * t / (2.0 * c * c)) * (b - a);
+  }
+  double lo() const { return a; }
+  double hi() const { return gaussian ? b : c; }
+};
 
 struct Cell {
   double r;
@@ -131,26 +151,13 @@ struct Grid {
   }
 };
 
-}  // namespace
-
-extern "C" {
-
-// Returns 0 on success, 1 if cap was too small (n_out then holds the count
-// reached), 2 on bad arguments.  pos and nrm are [cap][3]; boundary nodes come
-// first (nb_out of them, with normals), interior nodes after them.
-int nc_fill(double r, double h0, double slope, double hmax, double hb, uint64_t seed, int n_cand,
-            int64_t cap, double* pos, double* nrm, int64_t* n_out, int64_t* nb_out) {
-  if (!(r >= 0.0 && r < 0.70710678) || !(h0 > 0.0) || !(hmax >= h0) || !(hb > 0.0) || slope < 0.0 ||
-      n_cand < 1 || cap < 1)
-    return 2;
+int fill(double r, const Spacing& h, double hb, uint64_t seed, int n_cand, int64_t cap, double* pos, double* nrm,
+         int64_t* n_out, int64_t* nb_out) {
   Cell cell{r};
   Rng rng(seed);
-  Grid grid(std::fmin(h0, hb), hmax, cap);
+  Grid grid(std::fmin(h.lo(), hb), h.hi(), cap);
   int64_t n = 0;
-  auto h_at = [&](const double* x) {
-    double d = cell.sdf(x);
-    return std::fmin(h0 + slope * std::fmax(d, 0.0), hmax);
-  };
+  auto h_at = [&](const double* x) { return h(cell.sdf(x)); };
 
   // random rotation: orthonormal frame from two random directions
   double R[3][3];
@@ -178,6 +185,10 @@ int nc_fill(double r, double h0, double slope, double hmax, double hb, uint64_t 
       for (int a = 0; a < 3; ++a) u[a] = R[a][0] * u0[0] + R[a][1] * u0[1] + R[a][2] * u0[2];
       double x[3] = {0.5 + r * u[0], 0.5 + r * u[1], 0.5 + r * u[2]};
       if (x[0] < 0.0 || x[0] >= 1.0 || x[1] < 0.0 || x[1] >= 1.0 || x[2] < 0.0 || x[2] >= 1.0) continue;
+      // where the grain meets an image of itself (r > 1/2) the two surfaces
+      // are sampled independently up to their intersection; keep one of any
+      // two points closer than half the surface spacing
+      if (grid.occupied(x, 0.5 * hb, pos)) continue;
       if (n >= cap) { *n_out = n; return 1; }
       for (int a = 0; a < 3; ++a) { pos[3 * n + a] = x[a]; nrm[3 * n + a] = u[a]; }
       grid.insert((int32_t)n, x);
@@ -201,7 +212,7 @@ int nc_fill(double r, double h0, double slope, double hmax, double hb, uint64_t 
       double x[3] = {wrap(xd[0] + hd * u[0]), wrap(xd[1] + hd * u[1]), wrap(xd[2] + hd * u[2])};
       double d = cell.sdf(x);
       if (!(d > 0.0)) continue;
-      double hc = std::fmin(h0 + slope * d, hmax);
+      double hc = h(d);
       // exclusion radius: the smaller of the two target spacings, so that a
       // candidate spawned outward (where h grows) is not rejected by its parent
       if (grid.occupied(x, 0.999 * std::fmin(hc, hd), pos)) continue;
@@ -214,5 +225,30 @@ int nc_fill(double r, double h0, double slope, double hmax, double hb, uint64_t 
   }
   *n_out = n;
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Returns 0 on success, 1 if cap was too small (n_out then holds the count
+// reached), 2 on bad arguments.  pos and nrm are [cap][3]; boundary nodes come
+// first (nb_out of them, with normals), interior nodes after them.
+int nc_fill(double r, double h0, double slope, double hmax, double hb, uint64_t seed, int n_cand,
+            int64_t cap, double* pos, double* nrm, int64_t* n_out, int64_t* nb_out) {
+  if (!(r >= 0.0 && r < 0.70710678) || !(h0 > 0.0) || !(hmax >= h0) || !(hb > 0.0) || slope < 0.0 ||
+      n_cand < 1 || cap < 1)
+    return 2;
+  return fill(r, Spacing{0, h0, slope, hmax, 1.0}, hb, seed, n_cand, cap, pos, nrm, n_out, nb_out);
+}
+
+// The same fill with the Gaussian refinement of Sec. 2.4.
+int nc_fill_gauss(double r, double hmin, double hmax, double eps, double hb, uint64_t seed, int n_cand,
+                  int64_t cap, double* pos, double* nrm, int64_t* n_out, int64_t* nb_out) {
+  if (!(r >= 0.0 && r < 0.70710678) || !(hmin > 0.0) || !(hmax >= hmin) || !(eps > 0.0) || !(hb > 0.0) ||
+      n_cand < 1 || cap < 1)
+    return 2;
+  return fill(r, Spacing{1, hmin, hmax, eps, std::sqrt(3.0) / 2.0 - r}, hb, seed, n_cand, cap, pos, nrm, n_out,
+              nb_out);
 }
 }
