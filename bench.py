@@ -371,6 +371,92 @@ def edac_sound_speed(torch, nc, ws_model, v_refs, cap=400_000):
     return out
 
 
+def _settle(s, check, cap, tol):
+    """Run until k changes by at most tol relative per check (or cap steps);
+    returns the last k, its Aitken extrapolation from the last three checks,
+    and whether it settled."""
+    import numpy as np
+    ks = []
+    t_say = time.perf_counter()
+    while s.steps < cap:
+        s.run(check)
+        ks.append(s.permeability())
+        if not np.isfinite(ks[-1]):
+            break
+        if len(ks) > 3 and abs(ks[-1] - ks[-2]) <= tol * abs(ks[-1]):
+            break
+        if time.perf_counter() - t_say > 30.0:
+            t_say = time.perf_counter()
+            print(f"[bench] ... {s.steps} steps, k = {ks[-1]:.8e}", file=sys.stderr, flush=True)
+    k_inf = ks[-1]
+    if len(ks) >= 3:
+        d1, d2 = ks[-1] - ks[-2], ks[-2] - ks[-3]
+        if d2 != d1 and abs(d1) < abs(d2):
+            k_inf = ks[-1] - d1 * d1 / (d1 - d2)
+    return ks[-1], k_inf, len(ks) > 3 and abs(ks[-1] - ks[-2]) <= tol * abs(ks[-1])
+
+
+def gci_table(hs, X, fs=1.3):
+    """Grid convergence index of Appendix B: relative errors against the finest
+    grid, the apparent order p from a least-squares line through
+    (log h, log e) of the coarser grids, and for each pair of successive grids
+    GCI = F_s |eps| / (ratio^p - 1) on the finer one."""
+    import numpy as np
+    hs, X = np.asarray(hs, dtype=float), np.asarray(X, dtype=float)
+    order = np.argsort(-hs)
+    hs, X = hs[order], X[order]
+    e = np.abs(X[:-1] - X[-1]) / X[-1]
+    p = float(np.polyfit(np.log(hs[:-1]), np.log(np.maximum(e, 1e-300)), 1)[0])
+    rows = []
+    for i in range(1, len(hs)):
+        eps = abs(X[i - 1] - X[i]) / X[i]
+        ratio = hs[i - 1] / hs[i]
+        rows.append({"h": float(hs[i]), "eps": float(eps), "gci": float(fs * eps / (ratio ** p - 1.0))})
+    return {"p": p, "e_vs_finest": [float(x) for x in e], "pairs": rows}
+
+
+def convergence_study(torch, nc, r, hs, seed=1, nl=25, solvers=("mlbm", "acm"), acm_v_ref=1e-3, acm_edac=False):
+    """The paper's grid-convergence study (Sec. 3.2, Appendix B) on its own
+    discretisation: Gaussian refinement (h_max = 2 h_min, eps = 0.295, node
+    counts matched to the printed ones), N_L = 25, MLBM in the paper's D3Q15 TRT
+    form (tau+ = 1, Lambda = 1) and ACM, both mixed precision, each run to
+    steady state on every grid; k/d^2, drag K and the GCI of both."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver
+    say = lambda m: print(f"[bench] convergence r={r}: {m}", file=sys.stderr, flush=True)
+    grids = []
+    for h in hs:
+        t0 = time.perf_counter()
+        cloud = nc.gauss_cloud(r, h, seed=seed)
+        disc = Discretization(cloud, nl=nl, M=64)
+        rec = {"h_min": h, "n": cloud.n, "n_boundary": cloud.n_bnd}
+        for name, make, check, cap, tol in (
+                ("mlbm", lambda: MLBMSolver(disc, q=15, precision=MPF_MIXED, magic=1.0), 500, 600_000, 1e-8),
+                ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED, v_ref=acm_v_ref, edac=acm_edac), 5000,
+                 1_500_000, 1e-7)):
+            if name not in solvers:
+                continue
+            t1 = time.perf_counter()
+            s = make()
+            k, k_inf, settled = _settle(s, check, cap, tol)
+            F, K = s.drag()
+            rec[name] = {"k": k, "k_aitken": k_inf, "K": float(K), "steps": s.steps, "settled": bool(settled),
+                         "physical_time": s.steps * (s.units["dt"] if name == "mlbm" else s.prm.dt),
+                         "seconds": time.perf_counter() - t1}
+            say(f"h={h} n={cloud.n} {name}: k={k:.7e} (Aitken {k_inf:.7e}) K={float(K):.5f} "
+                f"{s.steps} steps, settled={settled}, {rec[name]['seconds']:.1f}s")
+            del s
+        grids.append(rec)
+        del disc
+        torch.cuda.empty_cache()
+        say(f"h={h} done in {time.perf_counter() - t0:.1f}s")
+    out = {"r": r, "nl": nl, "grids": grids, "acm_v_ref": acm_v_ref, "acm_edac": acm_edac}
+    for name in solvers:
+        out["gci_" + name] = {"k": gci_table(hs, [g[name]["k_aitken"] for g in grids]),
+                              "K": gci_table(hs, [g[name]["K"] for g in grids])}
+    return out
+
+
 def _batch_cell(args):
     import nodecloud as nc
     r, h0, seed = args
@@ -583,6 +669,12 @@ def main():
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
     ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
     ap.add_argument("--xval-acm-steps", type=int, default=1_500_000, help="cap on the ACM steps of --cross-validate")
+    ap.add_argument("--convergence", type=float, default=None, metavar="R",
+                    help="only the paper's grid-convergence study (GCI) at grain radius R")
+    ap.add_argument("--conv-h", type=float, nargs="+", default=[0.014, 0.01, 0.007, 0.005])
+    ap.add_argument("--conv-solvers", nargs="+", default=["mlbm", "acm"])
+    ap.add_argument("--conv-acm-vref", type=float, default=1e-3)
+    ap.add_argument("--conv-acm-edac", action="store_true")
     ap.add_argument("--edac-vref-sweep", type=float, nargs="+", default=None,
                     help="only the damped pressure equation for these sound-speed floors v_ref")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
@@ -616,6 +708,13 @@ def main():
         print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
         torch.cuda.set_device(0)
         print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
+        return
+    if args.convergence is not None:
+        torch.cuda.set_device(0)
+        print(json.dumps({"convergence": convergence_study(torch, nc, args.convergence, args.conv_h,
+                                                           solvers=tuple(args.conv_solvers),
+                                                           acm_v_ref=args.conv_acm_vref,
+                                                           acm_edac=args.conv_acm_edac)}))
         return
     if args.edac_vref_sweep:
         torch.cuda.set_device(0)

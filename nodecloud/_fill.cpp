@@ -16,7 +16,8 @@
 // Interior nodes: an advancing front seeded with the boundary nodes (in the
 // spirit of the dimension-independent variable-density generator the paper
 // uses, Sec. 2.1).  A dequeued node x_d spawns n_cand candidates on a sphere of
-// radius h(x_d); a candidate is kept if it is in the fluid and no existing node
+// radius h(x_d); a candidate is kept if it is in the fluid, at least half its
+// spacing away from the wall, and no existing node
 // lies closer than min(h(candidate), h(x_d)) under the minimum-image
 // convention.  The target spacing h(d), d the distance to the grain, is either
 // linear, h(d) = min(h0 + slope*d, hmax), or the paper's Gaussian refinement
@@ -213,6 +214,10 @@ int fill(double r, const Spacing& h, double hb, uint64_t seed, int n_cand, int64
       double d = cell.sdf(x);
       if (!(d > 0.0)) continue;
       double hc = h(d);
+      // no fluid node closer to the wall than half its spacing: where clipped
+      // surface lattices meet at the cell faces (r > 1/2) the surface sampling
+      // can leave room for one
+      if (d < 0.5 * hc) continue;
       // exclusion radius: the smaller of the two target spacings, so that a
       // candidate spawned outward (where h grows) is not rejected by its parent
       if (grid.occupied(x, 0.999 * std::fmin(hc, hd), pos)) continue;
