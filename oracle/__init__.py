@@ -63,6 +63,8 @@ def _load():
         lib.mpfo_flux.argtypes = [i64, i32, vp, vp, vp, i64]
         lib.mpfo_drag.restype = None
         lib.mpfo_drag.argtypes = [i64, i32, vp, vp, vp, i64, vp, vp, dbl, dbl, dbl, vp]
+        lib.mpfo_traction.restype = None
+        lib.mpfo_traction.argtypes = [i64, i32, vp, vp, vp, i64, vp, vp, dbl, dbl, vp, vp]
         _lib = lib
     return _lib
 
@@ -325,6 +327,21 @@ def drag(sb, wg, nrm, v, p, rho, nu, dA):
     _load().mpfo_drag(sb.shape[0], sb.shape[1], sb.ctypes.data, wg.ctypes.data, nrm.ctypes.data, len(p),
                       v.ctypes.data, p.ctypes.data, rho, nu, dA, F.ctypes.data)
     return F
+
+
+def traction(sb, wg, nrm, v, p, rho, nu):
+    """Traction sigma n [nb][3] at every boundary node and the centred pressure
+    [nb] there (the surface maps of Sec. 3.1)."""
+    sb = _c(sb, np.int32)
+    wg = _c(wg, np.float64)
+    nrm = _c(nrm, np.float64)
+    v = _c(v, np.float64)
+    p = _c(p, np.float64)
+    t = np.zeros((sb.shape[0], 3))
+    pc = np.zeros(sb.shape[0])
+    _load().mpfo_traction(sb.shape[0], sb.shape[1], sb.ctypes.data, wg.ctypes.data, nrm.ctypes.data, len(p),
+                          v.ctypes.data, p.ctypes.data, rho, nu, t.ctypes.data, pc.ctypes.data)
+    return t, pc
 
 
 def drag_coefficient(Fx: float, r: float, phi: float, q: float, mu: float) -> float:

@@ -562,12 +562,15 @@ double mpfo_flux(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, co
  * derivative weights wg[(b*3 + a)*nl + j] (a = x, y, z) over stencil
  * sb[b*nl + j]; pressure relative to the node mean of p over all n nodes;
  * sigma = -p' I + rho nu (grad v + grad v^T); F = dA * sum_b sigma n_b. */
-void mpfo_drag(int64_t nb, int nl, const int32_t* sb, const double* wg, const double* nrm, int64_t n,
-               const double* v, const double* p, double rho, double nu, double dA, double* F) {
+/* Traction t = sigma n at every boundary node (Eq. stress_tensor_force), the
+ * surface map of Sec. 3.1: t_b = -(p_b - <p>) n_b + rho nu (grad v + grad v^T) n_b,
+ * written t [nb][3]; the centred pressure p_b - <p> goes to pc [nb] (if not
+ * NULL).  <p> is the mean of p over all n nodes. */
+void mpfo_traction(int64_t nb, int nl, const int32_t* sb, const double* wg, const double* nrm, int64_t n,
+                   const double* v, const double* p, double rho, double nu, double* t, double* pc) {
   double pm = 0.0;
   for (int64_t i = 0; i < n; ++i) pm += p[i];
   pm /= (double)n;
-  double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t b = 0; b < nb; ++b) {
     const int32_t* S = sb + b * nl;
     double G[3][3]; /* G[i][j] = d v_i / d x_j */
@@ -575,16 +578,28 @@ void mpfo_drag(int64_t nb, int nl, const int32_t* sb, const double* wg, const do
       for (int j = 0; j < 3; ++j) {
         const double* wj = wg + (b * 3 + j) * nl;
         double s = 0.0;
-        for (int t = 0; t < nl; ++t) s += wj[t] * v[3 * (int64_t)S[t] + i];
+        for (int q = 0; q < nl; ++q) s += wj[q] * v[3 * (int64_t)S[q] + i];
         G[i][j] = s;
       }
     double pp = p[S[0]] - pm;
     const double* nv = nrm + 3 * b;
     for (int i = 0; i < 3; ++i) {
-      double t = -pp * nv[i];
-      for (int j = 0; j < 3; ++j) t += rho * nu * (G[i][j] + G[j][i]) * nv[j];
-      acc[i] += t;
+      double ti = -pp * nv[i];
+      for (int j = 0; j < 3; ++j) ti += rho * nu * (G[i][j] + G[j][i]) * nv[j];
+      t[3 * b + i] = ti;
     }
+    if (pc) pc[b] = pp;
   }
+}
+
+/* Hydrodynamic force, Eq. integration_force: F = dA sum_b t_b. */
+void mpfo_drag(int64_t nb, int nl, const int32_t* sb, const double* wg, const double* nrm, int64_t n,
+               const double* v, const double* p, double rho, double nu, double dA, double* F) {
+  double* t = (double*)malloc(sizeof(double) * 3 * (nb > 0 ? nb : 1));
+  mpfo_traction(nb, nl, sb, wg, nrm, n, v, p, rho, nu, t, NULL);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t b = 0; b < nb; ++b)
+    for (int i = 0; i < 3; ++i) acc[i] += t[3 * b + i];
   for (int i = 0; i < 3; ++i) F[i] = dA * acc[i];
+  free(t);
 }

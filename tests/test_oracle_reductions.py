@@ -109,3 +109,28 @@ def test_drag_ignores_pressure_gauge(small_cloud, small_stencils, grad_bnd):
     F1 = O.drag(S[c.n_int:], grad_bnd, c.nrm, np.zeros((c.n, 3)), p, 1.0, 1.0, dA)
     F2 = O.drag(S[c.n_int:], grad_bnd, c.nrm, np.zeros((c.n, 3)), p + 123.0, 1.0, 1.0, dA)
     assert np.abs(F1 - F2).max() < 1e-9
+
+
+def test_traction_pointwise_closed_forms(small_cloud, small_stencils, grad_bnd):
+    """The surface map node by node: a linear pressure gives t = -(p - <p>) n
+    exactly (no velocity), and the shear field v = (z^2, 0, 0) gives
+    t = rho nu (grad v + grad v^T) n with the exact gradient (2z in the xz and
+    zx entries), the weights being exact on quadratics."""
+    c, S = small_cloud, small_stencils
+    X = nc.min_image(c.pos - 0.5)
+    p = -2.5 * X[:, 0]
+    t, pc = O.traction(S[c.n_int:], grad_bnd, c.nrm, np.zeros((c.n, 3)), p, 1.0, 1.0)
+    pb = p[c.n_int:] - p.mean()
+    assert np.abs(pc - pb).max() < 1e-14
+    assert np.abs(t + pb[:, None] * c.nrm).max() < 1e-14
+    v = np.zeros((c.n, 3))
+    v[:, 0] = X[:, 2] ** 2
+    rho, nu = 1.2, 0.7
+    t, _ = O.traction(S[c.n_int:], grad_bnd, c.nrm, v, np.zeros(c.n), rho, nu)
+    z, n = X[c.n_int:, 2], c.nrm
+    expect = rho * nu * np.stack([2 * z * n[:, 2], np.zeros_like(z), 2 * z * n[:, 0]], 1)
+    assert np.abs(t - expect).max() < 1e-9 * np.abs(expect).max()
+    # the drag is the area-weighted sum of the map
+    dA = O.area(c.r) / c.n_bnd
+    F = O.drag(S[c.n_int:], grad_bnd, c.nrm, v, np.zeros(c.n), rho, nu, dA)
+    assert np.abs(F - dA * t.sum(0)).max() <= 1e-14 * np.abs(F).max()
