@@ -298,21 +298,27 @@ def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
             if len(ks) % 40 == 0:
                 say(f"{name} {s.steps} steps, k = {ks[-1]:.8e}")
         F, K = s.drag()
+        t_map, _ = s.surface_map()
         if name == "mlbm":
             v, p = s.macros()
         else:
             v, p = s.v, s.p
-        fields[name] = (v.double().cpu().numpy(), p.double().cpu().numpy())
+        fields[name] = (v.double().cpu().numpy(), p.double().cpu().numpy(), t_map.cpu().numpy())
         out[name] = {"k": ks[-1], "K": float(K), "steps": s.steps, "seconds": time.perf_counter() - t0,
                      "settled": len(ks) > 2 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1])}
         say(f"{name}: k = {ks[-1]:.8e}, K = {float(K):.6f} after {s.steps} steps ({out[name]['seconds']:.1f}s)")
         del s
     n_int = disc.n_int
-    vm, pm = fields["mlbm"]
+    vm, pm, tm = fields["mlbm"]
     vm = vm[:, :n_int]
     pm = pm - pm.mean()
+    nrm = disc.nrm.cpu().numpy()
+
+    def tangential(t):  # |t - (t . n) n| per grain node
+        return np.linalg.norm(t - (t * nrm).sum(0) * nrm, axis=0)
+
     for name in ("acm", "acm_edac"):
-        va, pa = fields[name]
+        va, pa, ta = fields[name]
         va = va[:, :n_int]
         pa = pa - pa.mean()
         out[name + "_vs_mlbm"] = {
@@ -321,7 +327,9 @@ def cross_validate(torch, nc, ws_model, max_acm_steps=1_500_000):
             "v_rel_l2_diff": float(np.linalg.norm(vm - va) / np.linalg.norm(va)),
             "v_max_diff_over_max_v": float(np.abs(vm - va).max() / np.abs(va).max()),
             "p_rel_l2_diff": float(np.linalg.norm(pm - pa) / np.linalg.norm(pa)),
-            "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:]))}
+            "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:])),
+            "tangential_traction_rel_l2_diff": float(np.linalg.norm(tangential(tm) - tangential(ta))
+                                                     / np.linalg.norm(tangential(ta)))}
     say(json.dumps(out))
     return out
 
@@ -364,7 +372,9 @@ def edac_sound_speed(torch, nc, ws_model, v_refs, cap=400_000):
                "seconds": time.perf_counter() - t0, "k_rel_diff": abs(k / k_m - 1),
                "v_rel_l2_diff": float(np.linalg.norm(vm - va) / np.linalg.norm(va)),
                "p_rel_l2_diff": float(np.linalg.norm(pm - pa) / np.linalg.norm(pa)),
-               "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:]))}
+               "p_surface_rel_l2_diff": float(np.linalg.norm(pm[n_int:] - pa[n_int:]) / np.linalg.norm(pa[n_int:])),
+            "tangential_traction_rel_l2_diff": float(np.linalg.norm(tangential(tm) - tangential(ta))
+                                                     / np.linalg.norm(tangential(ta)))}
         print(f"[bench] edac v_ref={v_ref}: {json.dumps(rec)}", file=sys.stderr, flush=True)
         out["edac"].append(rec)
         del s

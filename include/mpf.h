@@ -343,6 +343,13 @@ int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w,
 int mpf_drag(int64_t n, const void* v, const void* p, int precision, int64_t nb, int nl, const int32_t* sb,
              const double* wg, const double* nrm, double rho, double nu, double dA, double* F_out, void* ws,
              size_t ws_bytes, void* stream);
+/* The surface maps of Sec. 3.1: the traction t_b = sigma n_b of the force
+ * above at every boundary node, t_out dev [3][nb] double, and the centred
+ * pressure p_b - <p>, pc_out dev [nb] double (the tangential force is
+ * t - (t . n) n).  Same arguments and workspace as mpf_drag. */
+int mpf_traction(int64_t n, const void* v, const void* p, int precision, int64_t nb, int nl, const int32_t* sb,
+                 const double* wg, const double* nrm, double rho, double nu, double* t_out, double* pc_out, void* ws,
+                 size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------- learned warm start
  * An addition to the paper's method: a multilayer perceptron maps per-node

@@ -107,6 +107,7 @@ def _load():
         "mpf_reduce_workspace": (sz, [i64]),
         "mpf_flux_planes": (i32, [i64, i32, vp, vp, vp, i32, i64, vp, vp, sz, vp]),
         "mpf_drag": (i32, [i64, vp, vp, i32, i64, i32, vp, vp, vp, dbl, dbl, dbl, vp, vp, sz, vp]),
+        "mpf_traction": (i32, [i64, vp, vp, i32, i64, i32, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]),
         "mpf_mlp_param_count": (i64, [vp]),
         "mpf_mlp_packed_count": (i64, [vp]),
         "mpf_mlp_workspace": (sz, [vp, i64, i32]),
@@ -146,7 +147,7 @@ EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",
             "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_unknown", "mpf_lbm_moments",
             "mpf_knn_workspace", "mpf_knn", "mpf_solver_stencils", "mpf_reduce_workspace",
-            "mpf_flux_planes", "mpf_drag", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
+            "mpf_flux_planes", "mpf_drag", "mpf_traction", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
             "mpf_mlp_pack", "mpf_mlp_forward", "mpf_mlp_backward", "mpf_mlp_mse", "mpf_adam_step",
             "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16", "mpf_mlp_train_workspace", "mpf_mlp_train",
             "mpf_shuffle_rows", "mpf_scale"]

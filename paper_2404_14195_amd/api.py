@@ -269,6 +269,23 @@ def drag(v, p, sb, wg, nrm, rho: float, nu: float, dA: float, F_out=None, ws=Non
     return F_out
 
 
+def traction(v, p, sb, wg, nrm, rho: float, nu: float, ws=None):
+    """Surface maps: traction sigma n [3][nb] and centred pressure [nb] at the
+    boundary nodes (double)."""
+    n = p.shape[0]
+    nl, nb = sb.shape
+    _need(wg, torch.float64, (3, nl, nb), "wg")
+    _need(nrm, torch.float64, (3, nb), "nrm")
+    if v.dtype != p.dtype:
+        raise TypeError("v and p must share a dtype")
+    t = torch.empty((3, nb), dtype=torch.float64, device=v.device)
+    pc = torch.empty(nb, dtype=torch.float64, device=v.device)
+    ws = reduce_workspace(max(n, nb), v.device) if ws is None else ws
+    check(lib().mpf_traction(n, _p(v), _p(p), precision_of(p.dtype), nb, nl, _p(sb), _p(wg), _p(nrm), float(rho),
+                             float(nu), _p(t), _p(pc), _p(ws), ws.numel(), _stream()), "mpf_traction")
+    return t, pc
+
+
 # ---------------------------------------------------------------- learned warm start
 
 MLP_DESC = _lib.MlpDesc(5, 128, 4, 4)

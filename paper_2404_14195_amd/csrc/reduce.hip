@@ -48,14 +48,17 @@ __global__ __launch_bounds__(kRBlock) void sum_partial(int64_t n, const T* __res
   if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
-// Traction sigma n at boundary node b, summed per block into part[3][nblk].
+// Traction sigma n at boundary node b, summed per block into part[3][nblk]
+// (part may be NULL); when t_out is given, also written per node as
+// t_out[3][nb], with the centred pressure in pc_out[nb].
 template <typename T>
 __global__ __launch_bounds__(kRBlock) void drag_partial(int64_t n, const T* __restrict__ v, const T* __restrict__ p,
                                                         int64_t nb, int nl, const int32_t* __restrict__ sb,
                                                         const double* __restrict__ wg,
                                                         const double* __restrict__ nrm,
                                                         const double* __restrict__ pmean, double rho_nu,
-                                                        double* __restrict__ part, int64_t nblk) {
+                                                        double* __restrict__ part, int64_t nblk,
+                                                        double* __restrict__ t_out, double* __restrict__ pc_out) {
   __shared__ double lds[kRBlock];
   const int64_t b = (int64_t)blockIdx.x * kRBlock + threadIdx.x;
   double t[3] = {0.0, 0.0, 0.0};
@@ -86,7 +89,13 @@ __global__ __launch_bounds__(kRBlock) void drag_partial(int64_t n, const T* __re
       for (int a = 0; a < 3; ++a) s += rho_nu * (G[c][a] + G[a][c]) * nv[a];
       t[c] = s;
     }
+    if (t_out) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t_out[c * nb + b] = t[c];
+      pc_out[b] = pp;
+    }
   }
+  if (!part) return;  // block-uniform: the map alone needs no sums
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double bsum = block_sum<kRBlock>(t[c], lds);
@@ -172,13 +181,44 @@ extern "C" int mpf_drag(int64_t n, const void* v, const void* p, int precision, 
   const unsigned gb = grid_for(nb, kRBlock);
   if (precision != MPF_F32)
     hipLaunchKernelGGL(drag_partial<double>, dim3(gb), dim3(kRBlock), 0, st, n, (const double*)v, (const double*)p,
-                       nb, nl, sb, wg, nrm, (const double*)pmean, rho * nu, part, (int64_t)gb);
+                       nb, nl, sb, wg, nrm, (const double*)pmean, rho * nu, part, (int64_t)gb, nullptr, nullptr);
   else
     hipLaunchKernelGGL(drag_partial<float>, dim3(gb), dim3(kRBlock), 0, st, n, (const float*)v, (const float*)p, nb,
-                       nl, sb, wg, nrm, (const double*)pmean, rho * nu, part, (int64_t)gb);
+                       nl, sb, wg, nrm, (const double*)pmean, rho * nu, part, (int64_t)gb, nullptr, nullptr);
   for (int c = 0; c < 3; ++c)
     hipLaunchKernelGGL(finish_sum, dim3(1), dim3(256), 0, st, (const double*)(part + c * gb), (int64_t)gb, 1, dA,
                        F_out + c);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+extern "C" int mpf_traction(int64_t n, const void* v, const void* p, int precision, int64_t nb, int nl,
+                            const int32_t* sb, const double* wg, const double* nrm, double rho, double nu,
+                            double* t_out, double* pc_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!v || !p || n < 1 || nb < 0 || nl < 1 || (nb > 0 && (!sb || !wg || !nrm || !t_out || !pc_out)))
+    return MPF_ERR_ARG;
+  if (precision != MPF_F64 && precision != MPF_F32 && precision != MPF_MIXED) return MPF_ERR_ARG;
+  if (!ws || ws_bytes < mpf_reduce_workspace(n > nb ? n : nb)) return MPF_ERR_WORKSPACE;
+  if (nb == 0) return MPF_OK;
+  hipStream_t st = as_stream(stream);
+  double* part = reinterpret_cast<double*>(ws);
+  const int64_t nmax = n > nb ? n : nb;
+  const int64_t cap = (nmax + kRBlock - 1) / kRBlock;
+  double* pmean = part + 3 * cap;
+  const unsigned gn = grid_for(n, kRBlock);
+  if (precision != MPF_F32)
+    hipLaunchKernelGGL(sum_partial<double>, dim3(gn), dim3(kRBlock), 0, st, n, (const double*)p, part);
+  else
+    hipLaunchKernelGGL(sum_partial<float>, dim3(gn), dim3(kRBlock), 0, st, n, (const float*)p, part);
+  hipLaunchKernelGGL(finish_sum, dim3(1), dim3(256), 0, st, (const double*)part, (int64_t)gn, 1, 1.0 / (double)n,
+                     pmean);
+  const unsigned gb = grid_for(nb, kRBlock);
+  if (precision != MPF_F32)
+    hipLaunchKernelGGL(drag_partial<double>, dim3(gb), dim3(kRBlock), 0, st, n, (const double*)v, (const double*)p,
+                       nb, nl, sb, wg, nrm, (const double*)pmean, rho * nu, nullptr, (int64_t)gb, t_out, pc_out);
+  else
+    hipLaunchKernelGGL(drag_partial<float>, dim3(gb), dim3(kRBlock), 0, st, n, (const float*)v, (const float*)p, nb,
+                       nl, sb, wg, nrm, (const double*)pmean, rho * nu, nullptr, (int64_t)gb, t_out, pc_out);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }

@@ -105,6 +105,12 @@ class ACMSolver:
         K = F[0] / (6.0 * math.pi * d.cloud.r * d.phi * q * self.prm.rho * self.prm.nu)
         return F, K
 
+    def surface_map(self):
+        """Traction sigma n [3][nb] and centred pressure [nb] on the grain
+        (device, double): the surface maps of Sec. 3.1."""
+        d = self.d
+        return api.traction(self.v, self.p, d.sb, self.wg, d.nrm, self.prm.rho, self.prm.nu, ws=d.red_ws)
+
 
 def ctypesarr(g):
     import ctypes
@@ -217,3 +223,13 @@ class MLBMSolver:
         q = float(api.flux_planes(d.s_idx, d.s_w, v[0], d.n_all, ws=d.red_ws).item())
         K = F[0] / (6.0 * math.pi * d.cloud.r * d.phi * q * self.nu)
         return F, K
+
+    def surface_map(self):
+        """Traction sigma n [3][nb] and centred pressure [nb] on the grain
+        (device, double), with the no-slip velocity on the grain."""
+        d = self.d
+        v, p = self.macros()
+        v[:, d.n_int:] = 0.0
+        if self._wg is None:
+            self._wg = api.rbffd_weights(d.pos, d.sb, [("dx",), ("dy",), ("dz",)])[0]
+        return api.traction(v, p, d.sb, self._wg, d.nrm, 1.0, self.nu, ws=d.red_ws)

@@ -455,6 +455,44 @@ def test_flux_and_drag_parity(api, disc_small):
     assert q_g2 == q_g
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_surface_traction_map_parity(api, disc_small, precision):
+    """The per-node traction and centred pressure on the grain (the surface
+    maps of Sec. 3.1) against the oracle node by node; FP32 state is rounded
+    first and the map computed in FP64 from it on both sides."""
+    c = disc_small.cloud
+    rng = np.random.default_rng(13)
+    dt = torch.float64 if precision == 0 else torch.float32
+    v = dev(rng.normal(size=(3, c.n)), dt)
+    p = dev(rng.normal(size=c.n), dt)
+    S = disc_small.sten_host
+    wg, _ = O.weights(c.pos, S[c.n_int:], [("dx",), ("dy",), ("dz",)])
+    wg_d = dev(wg.transpose(1, 2, 0), torch.float64)
+    t_g, pc_g = api.traction(v, p, disc_small.sb, wg_d, disc_small.nrm, 1.1, 0.9)
+    t_o, pc_o = O.traction(S[c.n_int:], wg, c.nrm, v.double().cpu().numpy().T, p.double().cpu().numpy(), 1.1, 0.9)
+    t_g = t_g.cpu().numpy().T
+    assert np.abs(pc_g.cpu().numpy() - pc_o).max() <= 1e-12 * np.abs(pc_o).max()
+    assert np.abs(t_g - t_o).max() <= 1e-11 * np.abs(t_o).max()
+    # the drag is the area-weighted sum of the map
+    dA = O.area(c.r) / c.n_bnd
+    F_g = api.drag(v, p, disc_small.sb, wg_d, disc_small.nrm, 1.1, 0.9, dA).cpu().numpy()
+    assert np.abs(F_g - dA * t_o.sum(0)).max() <= 1e-11 * np.abs(F_g).max()
+
+
+def test_solver_surface_maps(api, disc_small):
+    """Both solvers expose the map of their current state; the pressure part
+    has zero mean over all nodes by construction, so over the grain it is the
+    grain's mean offset; the traction sums to the solver's own drag."""
+    from paper_2404_14195_amd.solvers import ACMSolver, MLBMSolver
+    for s in (ACMSolver(disc_small), MLBMSolver(disc_small, q=19)):
+        s.run(200)
+        t, pc = s.surface_map()
+        F, _ = s.drag()
+        dA = disc_small.area / disc_small.nb
+        assert t.shape == (3, disc_small.nb) and pc.shape == (disc_small.nb,)
+        assert np.abs(dA * t.sum(1).cpu().numpy() - F).max() <= 1e-10 * np.abs(F).max()
+
+
 def test_geometry_from_library(api):
     for r in (0.04, 0.3, 0.55, 0.69):
         phi, A = api.sc_cell(r)

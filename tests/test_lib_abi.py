@@ -147,3 +147,12 @@ def test_knn_host_checks(lib):
     assert lib.mpf_solver_stencils(fake, 1000, 20, 30, fake, fake, ws, None) == -1  # surface rows need 29 interior
     assert lib.mpf_solver_stencils(fake, 1000, 900, 65, fake, fake, ws, None) == -1
     assert lib.mpf_solver_stencils(fake, 1000, 900, 30, fake, fake, 100, None) == -1
+
+
+def test_traction_host_checks(lib):
+    fake = ctypes.c_void_p(0x1000)
+    ws = lib.mpf_reduce_workspace(100)
+    assert lib.mpf_traction(100, fake, fake, 0, 10, 30, fake, fake, fake, 1.0, 1.0, None, fake, fake, ws, None) == -1
+    assert lib.mpf_traction(100, fake, fake, 5, 10, 30, fake, fake, fake, 1.0, 1.0, fake, fake, fake, ws, None) == -1
+    assert lib.mpf_traction(100, fake, fake, 0, 10, 30, fake, fake, fake, 1.0, 1.0, fake, fake, fake, 8, None) == -4
+    assert lib.mpf_traction(100, fake, fake, 0, 0, 30, None, None, None, 1.0, 1.0, None, None, fake, ws, None) == 0
