@@ -290,14 +290,15 @@ def test_lbm_fp32_shifted_error(api, disc_small):
     assert k_g == pytest.approx(k_o, rel=1e-4)
 
 
-def test_lbm_mixed_error(api, disc_small):
+@pytest.mark.parametrize("q, magic", [(19, 0.25), (15, 1.0)])
+def test_lbm_mixed_error(api, disc_small, q, magic):
     """FP32 interpolation weights, FP64 populations: 200 steps within 1e-6
-    of the FP64 oracle's permeability."""
+    of the FP64 oracle's permeability (D3Q19 BGK, and the paper's D3Q15 TRT)."""
     from paper_2404_14195_amd.solvers import MLBMSolver
     c = disc_small.cloud
-    g = MLBMSolver(disc_small, q=19, precision=2)
+    g = MLBMSolver(disc_small, q=q, precision=2, magic=magic)
     assert g.f.dtype == torch.float64 and g.W.dtype == torch.float32
-    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=19, h_min=c.h_min)
+    o = O.MLBM(c.pos, c.n_int, disc_small.sten_host, c.nrm, q=q, h_min=c.h_min, magic=magic)
     g.run(200)
     o.run(200)
     v_o, _ = o.macros()
