@@ -180,6 +180,46 @@ def test_acm_edac_parity_fp64_500_steps(api, disc_small, lanes, n_p):
     assert np.abs(o_edac.p - o_plain.p).max() > 1e-6 * np.abs(o_plain.p).max()
 
 
+@pytest.fixture(scope="module", params=[25, 45])
+def disc_other_nl(api, small_cloud, request):
+    """The 8k-node cell with stencils of another size: the ACM passes take
+    their generic column loop (the unrolled one is for N_L = 30)."""
+    from paper_2404_14195_amd.solvers import Discretization
+    return Discretization(small_cloud, nl=request.param, M=32)
+
+
+@pytest.mark.parametrize("edac", [False, True])
+def test_acm_parity_fp64_other_stencil_sizes(api, disc_other_nl, edac):
+    from paper_2404_14195_amd.solvers import ACMSolver
+    d = disc_other_nl
+    c = d.cloud
+    g = ACMSolver(d, precision=0, edac=edac)
+    o = O.ACM(c.pos, c.n_int, d.sten_host, c.nrm, sten_n=nc.neumann_stencils(c, d.nl), h_min=c.h_min, v_ref=1e-3,
+              edac=edac)
+    g.run(200)
+    o.run(200)
+    v = g.v.cpu().numpy().T
+    p = g.p.cpu().numpy()
+    assert np.abs(v - o.v).max() <= 1e-10 * np.abs(o.v).max()
+    assert np.abs(p - o.p).max() <= 1e-10 * np.abs(o.p).max()
+
+
+def test_lbm_parity_paper_stencil_size(api, disc_other_nl):
+    """MLBM (the paper's D3Q15 TRT) with N_L = 25 or 45, each side its own
+    weights, 100 steps: permeability within 1e-8."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    d = disc_other_nl
+    c = d.cloud
+    g = MLBMSolver(d, q=15, precision=0, magic=1.0)
+    o = O.MLBM(c.pos, c.n_int, d.sten_host, c.nrm, q=15, h_min=c.h_min, magic=1.0)
+    g.run(100)
+    o.run(100)
+    v_o, _ = o.macros()
+    pp = d.plan
+    k_o = O.flux(pp.idx, O.plane_weights(c.pos, pp.idx, pp.shift), v_o[:, 0], d.n_all)
+    assert g.permeability() == pytest.approx(k_o, rel=1e-8)
+
+
 @pytest.mark.parametrize("precision, tol", [(1, 1e-4), (2, 1e-6)])
 def test_acm_edac_reduced_precision(api, disc_small, precision, tol):
     g, o = acm_pair(api, disc_small, precision, 500, edac=True)
