@@ -97,6 +97,39 @@ def steady_fields(solver, check=500, tol=1e-6, max_steps=1_000_000, log=None, lo
     raise RuntimeError(f"k not steady after {solver.steps} steps (last {ks[-3:]})")
 
 
+def steady_fields_many(solvers, check=500, tol=1e-6, max_steps=1_000_000, log=None, log_every=20.0):
+    """steady_fields for several solvers at once, each on a stream of its own
+    (default priority): small cells leave most of the chip idle, and their
+    launches overlap this way.  Every solver takes exactly the steps and
+    checks it would take alone, so the results are the same bit for bit.
+    Returns [(k, steps)] in the solvers' order."""
+    streams = [torch.cuda.Stream() for _ in solvers]
+    torch.cuda.synchronize()  # set-up ran on the default stream
+    ks = [[] for _ in solvers]
+    out = [None] * len(solvers)
+    t_log = time.perf_counter()
+    while any(o is None for o in out):
+        live = [i for i, o in enumerate(out) if o is None]
+        for i in live:
+            if solvers[i].steps >= max_steps:
+                raise RuntimeError(f"k not steady after {solvers[i].steps} steps (last {ks[i][-3:]})")
+            with torch.cuda.stream(streams[i]):
+                solvers[i].run(check)
+        for i in live:
+            with torch.cuda.stream(streams[i]):
+                ks[i].append(solvers[i].permeability())
+            k = ks[i]
+            if not math.isfinite(k[-1]):
+                raise FloatingPointError(f"k is {k[-1]} after {solvers[i].steps} steps")
+            if len(k) > 2 and all(abs(k[-j] - k[-j - 1]) <= tol * abs(k[-1]) for j in (1, 2)):
+                out[i] = (k[-1], solvers[i].steps)
+        if log and time.perf_counter() - t_log > log_every:
+            log(f"steady: {sum(o is not None for o in out)} of {len(out)} cells settled")
+            t_log = time.perf_counter()
+    torch.cuda.synchronize()
+    return out
+
+
 class WarmStart:
     """The network, its optimiser state and the training set on the device."""
 

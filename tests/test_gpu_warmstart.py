@@ -55,12 +55,13 @@ def steps_to_band(ns, ks, k_ref, rel=1e-3):
 def trained():
     from paper_2404_14195_amd import MPF_MIXED
     from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
-    from paper_2404_14195_amd.warmstart import WarmStart, steady_fields, training_radii
+    from paper_2404_14195_amd.warmstart import WarmStart, steady_fields_many, training_radii
     ws = WarmStart(seed=0)
-    for i, r in enumerate(training_radii(10, lo=0.2, hi=0.45, held_out=(HELD_OUT_R,))):
-        d = Discretization(nc.sphere_cloud(r, H0, SLOPE, HMAX, seed=200 + i), nl=30, M=64)
-        s = MLBMSolver(d, q=19, precision=MPF_MIXED)
-        k, steps = steady_fields(s, tol=1e-6)
+    radii = training_radii(10, lo=0.2, hi=0.45, held_out=(HELD_OUT_R,))
+    discs = [Discretization(nc.sphere_cloud(r, H0, SLOPE, HMAX, seed=200 + i), nl=30, M=64)
+             for i, r in enumerate(radii)]
+    solvers = [MLBMSolver(d, q=19, precision=MPF_MIXED) for d in discs]
+    for r, d, s, (k, steps) in zip(radii, discs, solvers, steady_fields_many(solvers, tol=1e-6)):
         v, p = s.macros()
         ws.add_cell(d, v, p, k)
         print(f"[warm-start data] r={r:.3f} n={d.n} k={k:.6e} steps={steps}", flush=True)
@@ -118,3 +119,16 @@ def test_warm_start_acm(trained, held_out):
     print(f"[warm-start acm] k(200k cold)={k_ref:.8e}; at 20k steps: cold {k_c20:.8e} (rel {abs(k_c20 / k_ref - 1):.2e})"
           f", warm {k_w20:.8e} (rel {abs(k_w20 / k_ref - 1):.2e}); warm initial {k_w0:.8e}", flush=True)
     assert abs(k_w20 - k_ref) * 5 <= abs(k_c20 - k_ref)
+
+
+def test_steady_fields_many_equals_one_at_a_time():
+    """Several cells on streams of their own take the same steps and reach
+    the same k, bit for bit, as one after the other."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
+    from paper_2404_14195_amd.warmstart import steady_fields, steady_fields_many
+    discs = [Discretization(nc.sphere_cloud(r, 0.03, 0.16, 0.06, seed=50 + i), nl=30, M=32)
+             for i, r in enumerate((0.25, 0.35, 0.42))]
+    one = [steady_fields(MLBMSolver(d, q=19, precision=MPF_MIXED), tol=1e-6) for d in discs]
+    many = steady_fields_many([MLBMSolver(d, q=19, precision=MPF_MIXED) for d in discs], tol=1e-6)
+    assert many == one
