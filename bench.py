@@ -473,6 +473,26 @@ def convergence_study(torch, nc, r, hs, seed=1, nl=25, solvers=("mlbm", "acm"), 
     return out
 
 
+def weights_cell(torch, nc, api, name="lbm_mid", reps=5):
+    """The FP64 weight solve of one workload cell, as the solvers request it
+    (their stencils, d/dx, d/dy, d/dz and the Laplacian), launched reps times
+    with the block shape (4 waves, 2 rows per wave): the unit a counter run
+    profiles."""
+    from paper_2404_14195_amd.solvers import Discretization
+    disc = Discretization(nc.config_cloud(name), nl=30, M=16, plan=False)
+    ops = [("dx",), ("dy",), ("dz",), ("lap",)]
+    ms = []
+    for _ in range(reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        api.rbffd_weights_batched([(disc.pos, disc.sten, None)], ops, solve=0, tune=(4, 2))
+        ev1.record()
+        torch.cuda.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    return {"cell": name, "rows": disc.n, "ms": ms}
+
+
 def _batch_cell(args):
     import nodecloud as nc
     r, h0, seed = args
@@ -685,6 +705,8 @@ def main():
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
     ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
     ap.add_argument("--xval-acm-steps", type=int, default=1_500_000, help="cap on the ACM steps of --cross-validate")
+    ap.add_argument("--weights-cell", default=None, metavar="CELL",
+                    help="only the FP64 weight solve of one workload cell, five launches (for counter runs)")
     ap.add_argument("--convergence", type=float, default=None, metavar="R",
                     help="only the paper's grid-convergence study (GCI) at grain radius R")
     ap.add_argument("--conv-h", type=float, nargs="+", default=[0.014, 0.01, 0.007, 0.005])
@@ -724,6 +746,10 @@ def main():
         print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
         torch.cuda.set_device(0)
         print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
+        return
+    if args.weights_cell:
+        torch.cuda.set_device(0)
+        print(json.dumps({"weights_cell": weights_cell(torch, nc, api, args.weights_cell)}))
         return
     if args.convergence is not None:
         torch.cuda.set_device(0)
