@@ -495,11 +495,32 @@ def weights_cell(torch, nc, api, name="lbm_mid", reps=5):
     return {"cell": name, "rows": disc.n, "ms": ms}
 
 
-def _batch_cell(args):
-    import nodecloud as nc
-    r, h0, seed = args
-    c = nc.sphere_cloud(r, h0, 0.3, 4 * h0, seed=seed)
-    return c.pos, c.n
+def batch_cells(workers=8, context="fork"):
+    """The eight cells of the batched weight solve: r uniform in [0.15, 0.6]
+    (seed 4), sized to about 0.5, 1, ..., 4 M nodes (a seeded permutation),
+    h(d) = min(h0 + 0.3 d, 4 h0), filled in parallel on the host: in forked
+    processes, or (context "threads", for a process that already holds a GPU
+    context) in threads, the fill itself running in C without the GIL.
+    Returns (radii, [(pos [n][3], n)])."""
+    import multiprocessing as mp
+    import numpy as np
+    rng = np.random.default_rng(4)
+    radii = rng.uniform(0.15, 0.6, 8)
+    targets = rng.permutation([0.5e6, 1e6, 1.5e6, 2e6, 2.5e6, 3e6, 3.5e6, 4e6])
+    # node count ~ c / h0^3, c calibrated on the 1.83M-node cell (h0 = 0.002)
+    # and scaled by porosity
+    h0s = [0.002 * (1.83e6 / t * (1 - 4.19 * min(r, 0.5) ** 3) / (1 - 4.19 * 0.027)) ** (1 / 3)
+           for r, t in zip(radii, targets)]
+    import nodecloud
+    jobs = [(float(r), float(h), 40 + i) for i, (r, h) in enumerate(zip(radii, h0s))]
+    if context == "threads":
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            cells = list(ex.map(nodecloud.batch_fill, jobs))
+    else:
+        with mp.get_context(context).Pool(workers) as pool:
+            cells = pool.map(nodecloud.batch_fill, jobs)
+    return radii, cells
 
 
 def weights_batch(torch, nc, api):
@@ -507,18 +528,8 @@ def weights_batch(torch, nc, api):
     0.5, 1, ..., 4 M nodes (a seeded permutation), N_L = 30, four operators
     (d/dx, d/dy, d/dz, Laplacian): every 40 x 40 saddle system in one launch,
     FP64 direct and FP32 factors with FP64 refinement, autotuned block shape."""
-    import multiprocessing as mp
-    import numpy as np
-    rng = np.random.default_rng(4)
-    radii = rng.uniform(0.15, 0.6, 8)
-    targets = rng.permutation([0.5e6, 1e6, 1.5e6, 2e6, 2.5e6, 3e6, 3.5e6, 4e6])
-    # h(d) = min(h0 + 0.3 d, 4 h0): node count ~ c / h0^3, c calibrated on the
-    # 1.83M-node cell (h0 = 0.002) and scaled by porosity
-    h0s = [0.002 * (1.83e6 / t * (1 - 4.19 * min(r, 0.5) ** 3) / (1 - 4.19 * 0.027)) ** (1 / 3)
-           for r, t in zip(radii, targets)]
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(8) as pool:
-        cells = pool.map(_batch_cell, [(float(r), float(h), 40 + i) for i, (r, h) in enumerate(zip(radii, h0s))])
+    radii, cells = batch_cells()
     torch.cuda.set_device(0)
     print(f"[bench] 8 cells, {sum(c[1] for c in cells)} nodes, fill {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)

@@ -192,6 +192,14 @@ def sphere_cloud(r: float, h0: float, slope: float, hmax: float, seed: int, hb: 
                  meta=dict(kind="sphere", r=r, h0=h0, slope=slope, hmax=hmax, hb=hb, seed=seed, n_cand=n_cand))
 
 
+def batch_fill(args):
+    """(r, h0, seed) -> (pos [n][3], n) of the cell h(d) = min(h0 + 0.3 d,
+    4 h0): one worker's share of a parallel fill of several cells."""
+    r, h0, seed = args
+    c = sphere_cloud(r, h0, 0.3, 4 * h0, seed=seed)
+    return c.pos, c.n
+
+
 def lattice_cloud(n_side: int) -> Cloud:
     """All nodes of a regular periodic n^3 lattice with spacing 1/n, no grain."""
     a = (np.arange(n_side) + 0.5) / n_side

@@ -1,0 +1,64 @@
+"""The batched weight solve at its full benchmark size: the eight cells of
+bench.py --weights-batch (21.6M rows, N_L = 30, four operators) in one launch,
+FP64 direct and FP32 factors with FP64 refinement.  Every 1000th row of every
+cell is checked against the oracle, whose stencils come from the host fixture
+(so the GPU stencils of those rows are checked too)."""
+import importlib.util
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import nodecloud as nc
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def say(m):
+    print(f"[batch-full] {m}", flush=True)
+    sys.stdout.flush()
+
+
+def test_batched_weights_full_size_sampled():
+    from paper_2404_14195_amd import api
+    assert torch.cuda.is_available()
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t0 = time.perf_counter()
+    # threads, not processes: this process already holds a GPU context
+    _, cells = bench.batch_cells(workers=8, context="threads")
+    say(f"{sum(n for _, n in cells)} nodes in 8 cells, fill {time.perf_counter() - t0:.0f}s")
+    ops = [("dx",), ("dy",), ("dz",), ("lap",)]
+    clouds, samples = [], []
+    for pos, n in cells:
+        p = torch.as_tensor(np.ascontiguousarray(pos.T), device="cuda")
+        clouds.append((p, api.knn(p, 30), None))
+        rows = np.arange(0, n, 1000)
+        samples.append((rows, nc.stencils(pos, 30, queries=pos[rows])))
+        say(f"cell of {n} nodes: {len(rows)} sampled rows, host stencils ({time.perf_counter() - t0:.0f}s)")
+    for c, (rows, s_host) in enumerate(samples):
+        assert np.array_equal(clouds[c][1][:, rows].T.cpu().numpy(), s_host), c
+    refs = [O.weights(pos, s_host, ops)[0] for (pos, _), (rows, s_host) in zip(cells, samples)]
+    say(f"oracle weights of {sum(len(r) for r, _ in samples)} rows ({time.perf_counter() - t0:.0f}s)")
+    for solve, tol in ((0, 1e-10), (1, 1e-9)):
+        api.weights_autotune(clouds[0][0], clouds[0][1], ops, solve=solve, sample_rows=65536)
+        res = api.rbffd_weights_batched(clouds, ops, solve=solve)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for c, (rows, _) in enumerate(samples):
+            w64, _, info = res[c]
+            assert not (info[rows].cpu().numpy() > 0).any()
+            w = w64[:, :, rows].cpu().numpy().transpose(2, 0, 1)  # [rows][op][nl]
+            scale = np.abs(refs[c]).max(2)
+            worst = max(worst, float((np.abs(w - refs[c]).max(2) / scale).max()))
+        say(f"solve {solve}: worst row error {worst:.2e} ({time.perf_counter() - t0:.0f}s)")
+        assert worst < tol
+        del res
+        torch.cuda.empty_cache()
