@@ -62,3 +62,33 @@ def test_batched_weights_full_size_sampled():
         assert worst < tol
         del res
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision, tol", [(0, 1e-11), (2, 1e-6)])
+def test_acm_poiseuille_fixed_point_at_full_size(precision, tol):
+    """A property that holds at any size, checked where the oracle cannot
+    follow: plane Poiseuille flow between walls at z = 0 and H with constant
+    pressure is an exact fixed point of the whole ACM step, every weight being
+    exact on quadratics.  On a channel of about a million nodes the GPU step
+    keeps it over 20 steps: to rounding in FP64, and to the rounding of the
+    FP32 weights in mixed precision.  The step is half the nominal one: on
+    this jittered lattice the nominal step lets a mode of the Laplacian grow
+    (test_oracle_acm shows it on the oracle)."""
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization
+    c = nc.channel_cloud(0.008, 0.5, seed=3)
+    assert c.n > 900_000
+    d = Discretization(c, nl=30, M=16, plan=False)
+    s = ACMSolver(d, precision=precision, v_ref=1e-3, dt=0.025 * c.h_min ** 2)
+    z = c.pos[:, 2]
+    u = z * (0.5 - z) / 2.0  # g = 1, nu = 1
+    u[c.n_int:] = 0.0
+    s.v[0].copy_(torch.as_tensor(u, dtype=s.v.dtype))
+    s.vmax.fill_(float(u.max()))
+    s.run(20)
+    v = s.v.double().cpu().numpy()
+    say(f"Poiseuille on {c.n} nodes, precision {precision}: max |dv_x| / max u = "
+        f"{np.abs(v[0] - u).max() / u.max():.2e}")
+    assert np.abs(v[0] - u).max() <= tol * u.max()
+    assert np.abs(v[1:]).max() <= tol * u.max()
+    p = s.p.double().cpu().numpy()
+    assert np.ptp(p) <= tol * u.max()

@@ -169,3 +169,26 @@ def test_edac_pressure_advection_exact_on_quadratics(box):
     b.p[:] = q
     b.run(1)
     assert np.array_equal(b.p, q)
+
+
+def test_nominal_step_on_a_jittered_channel_is_not_stable():
+    """The time step 0.1 h_min^2 / (2 nu) of Sec. 2.3 is not stable on every
+    node set.  On a plane channel filled with a jittered lattice (jitter
+    h / 4) the predictor's RBF-FD Laplacian has a mode that grows by about
+    1.6 per step at that step, with or without the pressure coupling, so the
+    Poiseuille fixed point is lost within tens of steps; at half the step it
+    holds to rounding.  (The sphere-cell clouds of the workloads run stably
+    for millions of steps at the nominal step.)"""
+    c = nc.channel_cloud(0.02, 0.5, seed=3)
+    S, Sn = nc.solver_stencils(c, 30), nc.neumann_stencils(c, 30)
+    z = c.pos[:, 2]
+    u = z * (0.5 - z) / 2.0
+    u[c.n_int:] = 0.0
+    dev = {}
+    for name, dt in (("nominal", O.acm_dt(c.h_min, 1.0)), ("half", 0.5 * O.acm_dt(c.h_min, 1.0))):
+        a = O.ACM(c.pos, c.n_int, S, c.nrm, sten_n=Sn, dt=dt, v_ref=1e-3, beta=0.0)
+        a.v[:, 0] = u
+        a.run(40)
+        dev[name] = np.abs(a.v[:, 0] - u).max() / u.max()
+    assert dev["nominal"] > 1e-9  # grown by six orders of magnitude from rounding
+    assert dev["half"] < 1e-13
