@@ -859,7 +859,7 @@ def main():
     achieved = bpn * disc.n / (f32["step_kernel_ms"] * 1e-3) / 1e9
     copy_gbs = copy_bandwidth(torch)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic, "kernel": "lbm_step<float,float,19,true>", "bytes_per_node_step": bpn,
+            "traffic": traffic, "kernel": "lbm_step<float,float,19,true,false>", "bytes_per_node_step": bpn,
             "launch_ms": f32["step_kernel_ms"], "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
 
     cpu = None

@@ -135,10 +135,13 @@ inline unsigned tiles_grid(int64_t n) {
 // q - 1 moving populations against the coalesced weights.  The partial sums
 // meet in LDS and are added in a fixed order by the first wave, which then
 // applies bounce-back and the collision and writes the tile.  The column loop
-// is deliberately not unrolled and the weights use plain (cached) loads:
-// measured on the 71k-node cell, both unrolling and non-temporal weight loads
-// cost 30-60 % of the step time.
-template <typename TW, typename T, int Q, bool COLLIDE>
+// is deliberately not unrolled (unrolling cost 30-60 % of the step time).
+// STREAM_W selects non-temporal weight loads.  Weights that fit the 256 MB
+// Infinity Cache are read from it on every step after the first, and
+// streaming them then costs 6-50 %; weights far larger than it are read from
+// HBM anyway, and streaming them keeps the gathered population records in the
+// caches (6 % faster at 1.26-2.5 GB of weights, all precisions).
+template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W>
 __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int, int nl,
                                                        const int32_t* __restrict__ sten,
                                                        const TW* __restrict__ W,
@@ -178,7 +181,13 @@ __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int,
       }
     }
 #pragma unroll
-    for (int k = 1; k < Q; ++k) acc[k] += (T)W[(k - 1) * ks + at] * r[k];
+    for (int k = 1; k < Q; ++k) {
+      const TW* wk = W + (k - 1) * ks + at;
+      TW w;
+      if constexpr (STREAM_W) w = __builtin_nontemporal_load(wk);
+      else w = *wk;
+      acc[k] += (T)w * r[k];
+    }
   }
 #pragma unroll
   for (int k = 1; k < Q; ++k) part[wv][k - 1][lane] = acc[k];
@@ -334,6 +343,25 @@ __global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int
   unknown[b] = mask;
 }
 
+// Weight arrays above this size are streamed (non-temporal loads): twice the
+// Infinity Cache, between the measured points where caching wins (0.31 GB)
+// and where streaming wins (1.26 GB).
+constexpr double kStreamWeightsBytes = 512.0 * 1024 * 1024;
+
+template <typename TW, typename T, int Q, bool STREAM_W>
+void launch_steps(int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W, const uint32_t* unknown,
+                  T* f, T* ft, T* cur, int n_steps, const Prm<T>& pr, hipStream_t st) {
+  const unsigned gt = tiles_grid(n);
+  for (int s = 0; s < n_steps - 1; ++s) {
+    T* nxt = cur == f ? ft : f;
+    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten,
+                       W, unknown, (const T*)cur, nxt, pr);
+    cur = nxt;
+  }
+  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten,
+                     W, unknown, (const T*)cur, f, pr);
+}
+
 template <typename TW, typename T, int Q>
 int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W,
         const uint32_t* unknown, T* f, T* ft, int n_steps, hipStream_t st) {
@@ -350,15 +378,10 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
     hipLaunchKernelGGL((lbm_collide<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, f, pr);
     cur = f;
   }
-  const unsigned gt = tiles_grid(n);
-  for (int s = 0; s < n_steps - 1; ++s) {
-    T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<TW, T, Q, true>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, unknown,
-                       (const T*)cur, nxt, pr);
-    cur = nxt;
-  }
-  hipLaunchKernelGGL((lbm_step<TW, T, Q, false>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten, W, unknown,
-                     (const T*)cur, f, pr);
+  if ((double)(Q - 1) * nl * n * sizeof(TW) > kStreamWeightsBytes)
+    launch_steps<TW, T, Q, true>(n, n_int, nl, sten, W, unknown, f, ft, cur, n_steps, pr, st);
+  else
+    launch_steps<TW, T, Q, false>(n, n_int, nl, sten, W, unknown, f, ft, cur, n_steps, pr, st);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }

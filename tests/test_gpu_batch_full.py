@@ -92,3 +92,66 @@ def test_acm_poiseuille_fixed_point_at_full_size(precision, tol):
     assert np.abs(v[1:]).max() <= tol * u.max()
     p = s.p.double().cpu().numpy()
     assert np.ptp(p) <= tol * u.max()
+
+
+def test_lbm_streamed_weights_parity():
+    """The MLBM step on a cell whose weights exceed 512 MiB in every precision
+    (about 280k nodes: 1.2 GB FP64, 0.6 GB FP32), where the step streams its
+    weights past the caches.  The GPU runs with the oracle's weights from a
+    state with O(1e-2) deviations from rest:
+    * FP64: the oracle's own weights, within 1e-10 of the deviations plus the
+      oracle's rounding floor, as on the small cells;
+    * mixed (FP32 weights, FP64 state and arithmetic) and FP32: the oracle's
+      weights rounded to FP32, with the oracle run on those same rounded
+      values.  The GPU interpolates the shifted populations g = f - w_k and
+      adds w_k back, which equals the oracle's sum of w_j f_j only where a
+      row's weights sum to one: rounded weights miss that by a few 1e-8, so
+      each step may differ by delta = max_k w_k |1 - sum_j w_j| (computed from
+      the rounded weights; bound 10 delta per step, for the collision's
+      mixing).  Beyond that, mixed differs only in FP64 summation order; FP32
+      also stores g in FP32 and sums 30 FP32 products, which bounds its error
+      by 5e-6 max|g| per step."""
+    from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
+    q, nl = 19, 30
+    c = nc.sphere_cloud(0.3, 0.0042, 0.16, 0.02, seed=4)
+    assert (q - 1) * nl * c.n * 4 > 512 * 2 ** 20
+    disc = Discretization(c, nl=nl, M=64)
+    say(f"MLBM streamed weights: {c.n} nodes")
+    o = O.MLBM(c.pos, c.n_int, disc.sten_host, c.nrm, q=q, h_min=c.h_min)
+    e, wk, _ = O.lattice(q)
+    rng = np.random.default_rng(11)
+    rho0 = 1.0 + 0.01 * rng.normal(size=c.n)
+    u0 = 0.02 * rng.normal(size=(c.n, 3))
+    f0 = np.concatenate([O.equilibrium(q, 1, rho0[i], u0[i]) for i in range(c.n)])
+    say("oracle weights and initial state done")
+
+    def check(precision, tol_rel, floor, per_step=0.0):
+        Wd = torch.as_tensor(np.ascontiguousarray(o.W[:, 1:, :].transpose(1, 2, 0)), device="cuda",
+                             dtype=torch.float64 if precision == 0 else torch.float32)
+        g = MLBMSolver(disc, q=q, precision=precision, W=Wd)
+        g.set_populations(f0)
+        o.f[:] = f0
+        done = 0
+        for steps in (1, 2):
+            g.run(steps)
+            o.run(steps)
+            done += steps
+            fg = g.populations()
+            dev_max = np.abs(o.f - wk).max()
+            err = np.abs(fg - o.f).max()
+            tol = tol_rel * done * dev_max + floor(o.f, done) + per_step * done
+            say(f"precision {precision}, {done} steps: max |df| = {err:.3e} (bound {tol:.3e}, max|g| {dev_max:.3e})")
+            assert err <= tol, (precision, done, err, tol)
+        del g, Wd
+        torch.cuda.empty_cache()
+
+    def floor64(f, steps):
+        return 2 * np.finfo(np.float64).eps * np.abs(f).max() * steps
+
+    check(0, 1e-10, floor64)
+    o.W[:] = o.W.astype(np.float32).astype(np.float64)  # the FP32 weights, exactly, in FP64
+    delta = float((wk[1:] * np.abs(1.0 - o.W[:, 1:, :].sum(axis=2))).max())
+    say(f"FP32 weights: max_k w_k |1 - row sum| = {delta:.3e}")
+    assert delta < 1e-8
+    check(2, 1e-10, floor64, 10 * delta)
+    check(1, 5e-6, lambda f, s: 0.0)
