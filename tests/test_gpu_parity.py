@@ -238,6 +238,77 @@ def test_acm_zero_steps_and_rest(api, disc_small):
     assert not g.v.any().item() and not g.p.any().item()
 
 
+@pytest.fixture(scope="module")
+def disc_no_grain(api):
+    """A periodic fill without a grain: every node is interior (n_int = n),
+    there are no surface rows, no Neumann rows and no unknown populations."""
+    from paper_2404_14195_amd.solvers import Discretization
+    c = nc.sphere_cloud(0.0, 0.05, 0.0, 0.05, seed=5)
+    assert c.n_int == c.n and c.n_bnd == 0
+    return Discretization(c, nl=30, M=32)
+
+
+def test_no_grain_acm_uniform_acceleration(api, disc_no_grain):
+    """Without a grain the flow from rest under a body force is uniform: every
+    stencil derivative of a constant field vanishes, so p stays 0 and each
+    step adds dt g to v at every node.  After N steps v = N dt g (to the
+    rounding of the vanishing derivative sums), on the GPU and in the oracle."""
+    from paper_2404_14195_amd.solvers import ACMSolver
+    d = disc_no_grain
+    c = d.cloud
+    g = (0.7, -0.2, 0.1)
+    s = ACMSolver(d, precision=0, g=g)
+    o = O.ACM(c.pos, c.n_int, d.sten_host, c.nrm, h_min=c.h_min, v_ref=1e-3, g=g)
+    s.run(40)
+    o.run(40)
+    exact = 40 * s.prm.dt * np.array(g)
+    vg = s.v.cpu().numpy().T
+    assert np.abs(vg - exact).max() <= 1e-12 * np.abs(exact).max()
+    assert np.abs(o.v - exact).max() <= 1e-12 * np.abs(exact).max()
+    assert np.abs(vg - o.v).max() <= 1e-10 * np.abs(o.v).max()
+    assert np.abs(s.p.cpu().numpy()).max() <= 1e-12 * np.abs(exact).max()
+    # the flux of a uniform flow through the sample planes is that flow
+    assert s.flux().item() == pytest.approx(exact[0], rel=1e-12)
+
+
+def test_no_grain_lbm_parity_and_uniform_acceleration(api, disc_no_grain):
+    """MLBM without boundary nodes (the step takes no mask).  With the
+    oracle's weights, from a perturbed state: the usual 1e-10 bar.  With its
+    own weights, from rest under a force: the state stays uniform and its
+    velocity grows by the same amount every step."""
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    d = disc_no_grain
+    c = d.cloud
+    q = 19
+    o = O.MLBM(c.pos, c.n_int, d.sten_host, c.nrm, q=q, h_min=c.h_min)
+    W = dev(o.W[:, 1:, :].transpose(1, 2, 0), torch.float64)
+    g = MLBMSolver(d, q=q, precision=0, W=W)
+    assert g.unknown.numel() == 0
+    e, wk, _ = O.lattice(q)
+    rng = np.random.default_rng(21)
+    o.f[:] = np.concatenate([O.equilibrium(q, 1, 1.0 + 0.01 * rng.normal(), 0.02 * rng.normal(size=3))
+                             for _ in range(c.n)])
+    g.set_populations(o.f)
+    done = 0
+    for steps in (1, 6):
+        g.run(steps)
+        o.run(steps)
+        done += steps
+        tol = 1e-10 * np.abs(o.f - wk).max() + oracle_floor(o.f, done)
+        assert np.abs(g.populations() - o.f).max() <= tol
+    s = MLBMSolver(d, q=q, precision=0)
+    u = []
+    for _ in range(3):
+        v, _ = s.macros()
+        u.append(v.cpu().numpy())
+        s.run(10)
+    for x in u[1:]:
+        assert np.abs(x - x.mean(1, keepdims=True)).max() <= 1e-11 * np.abs(x[0]).max()
+    du1 = u[1][0].mean() - u[0][0].mean()
+    du2 = u[2][0].mean() - u[1][0].mean()
+    assert du1 > 0 and du2 == pytest.approx(du1, rel=1e-10)
+
+
 # ----------------------------------------------------------------- MLBM
 
 def oracle_floor(f_o, steps):
