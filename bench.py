@@ -730,6 +730,9 @@ def main():
                     help="only the damped pressure equation for these sound-speed floors v_ref")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
+    ap.add_argument("--lbm-large", action="store_true",
+                    help="only the MLBM step on the 581k-node cell (weights streamed past the caches)")
+    ap.add_argument("--lbm-large-steps", type=int, default=300)
     ap.add_argument("--weights-batch", action="store_true",
                     help="only measure the batched weight solve of 8 cells (about 18M rows) and exit")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -798,6 +801,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.lbm_large:
+        print(json.dumps({"lbm_large": lbm_large(torch, nc, steps=args.lbm_large_steps)}))
+        return
     t_setup = time.perf_counter()
     cloud = nc.config_cloud("lbm_mid")
     disc = Discretization(cloud, nl=30, M=64)
