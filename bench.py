@@ -431,6 +431,59 @@ def gci_table(hs, X, fs=1.3):
     return {"p": p, "e_vs_finest": [float(x) for x in e], "pairs": rows}
 
 
+# Physical times to the stopping criterion printed in Sec. 3.4 (h_min = 0.007).
+PAPER_STOP_TIME = {0.062: {"mlbm": 3.57, "acm": 3.58}, 0.6526: {"mlbm": 0.04, "acm": 0.39}}
+
+
+def paper_stop_times(torch, nc, radii, hs, seed=1, nl=25, g=0.1, acm_v_ref=None, max_steps=3_000_000,
+                     solvers=("mlbm", "acm")):
+    """Physical time from rest to the paper's stopping criterion (Eq. stopCrit,
+    |Delta| < 1e-2) for both solvers on the paper's discretisation, set up as
+    in the convergence study (Gaussian refinement, N_L = 25, D3Q15 TRT with
+    Lambda = 1, mixed precision) with the paper's |g| = 0.1.  The criterion
+    is evaluated over the paper's physical interval Dt (1e4 steps at
+    h_min = 0.007: 0.0204 for MLBM, 0.00245 for ACM), so that coarser grids
+    check at the same physical times.  acm_v_ref: the floor of max|v| in
+    C = beta max(max|v|, v_ref); None takes 1e-3 g (C then follows max|v|
+    as in the paper) except on cells with phi < 0.2, where v_ref = g makes
+    the pressure waves fast enough to settle at all."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver, run_to_paper_criterion
+    say = lambda m: print(f"[bench] paper stop: {m}", file=sys.stderr, flush=True)
+    dt_mlbm_paper = (1.0 - 0.5) / 3.0 * (0.007 / 2) ** 2  # nu_lb dx^2 / nu at h_min = 0.007, tau+ = 1
+    dt_acm_paper = 0.1 * 0.007 ** 2 / 2.0
+    out = []
+    for r in radii:
+        for h in hs:
+            cloud = nc.gauss_cloud(r, h, seed=seed)
+            disc = Discretization(cloud, nl=nl, M=64)
+            phi = disc.phi
+            v_ref = acm_v_ref if acm_v_ref is not None else (g if phi < 0.2 else 1e-3 * g)
+            rec = {"r": r, "h_min": h, "n": cloud.n, "phi": phi, "acm_v_ref": v_ref,
+                   "paper_time_h0.007": PAPER_STOP_TIME.get(r)}
+            for name, make, dt_paper in (
+                    ("mlbm", lambda: MLBMSolver(disc, q=15, precision=MPF_MIXED, magic=1.0, g=(g, 0.0, 0.0)),
+                     dt_mlbm_paper),
+                    ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED, v_ref=v_ref, g=(g, 0.0, 0.0)),
+                     dt_acm_paper)):
+                if name not in solvers:
+                    continue
+                t0 = time.perf_counter()
+                s = make()
+                every = max(1, round(1e4 * dt_paper / s.time_step))
+                res = run_to_paper_criterion(s, every=every, tol=1e-2, max_steps=max_steps,
+                                             log=lambda m: say(f"r={r} h={h} {name}: {m}"))
+                res.update(every=every, seconds=time.perf_counter() - t0)
+                rec[name] = res
+                say(f"r={r} h={h} n={cloud.n} {name}: t={res['time']:.4f} ({res['steps']} steps, check every "
+                    f"{every}), k={res['k']:.6e}, converged={res['converged']}, {res['seconds']:.1f}s")
+                del s
+            out.append(rec)
+            del disc
+            torch.cuda.empty_cache()
+    return out
+
+
 def convergence_study(torch, nc, r, hs, seed=1, nl=25, solvers=("mlbm", "acm"), acm_v_ref=1e-3, acm_edac=False):
     """The paper's grid-convergence study (Sec. 3.2, Appendix B) on its own
     discretisation: Gaussian refinement (h_max = 2 h_min, eps = 0.295, node
@@ -730,6 +783,11 @@ def main():
                     help="only the damped pressure equation for these sound-speed floors v_ref")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
+    ap.add_argument("--paper-stop", type=float, nargs="+", default=None, metavar="R",
+                    help="physical time to the paper's stopping criterion on these radii (both solvers)")
+    ap.add_argument("--paper-stop-h", type=float, nargs="+", default=[0.014])
+    ap.add_argument("--paper-stop-solvers", nargs="+", default=["mlbm", "acm"])
+    ap.add_argument("--paper-stop-acm-vref", type=float, default=None)
     ap.add_argument("--lbm-large", action="store_true",
                     help="only the MLBM step on the 581k-node cell (weights streamed past the caches)")
     ap.add_argument("--lbm-large-steps", type=int, default=300)
@@ -773,6 +831,12 @@ def main():
                                                            solvers=tuple(args.conv_solvers),
                                                            acm_v_ref=args.conv_acm_vref,
                                                            acm_edac=args.conv_acm_edac)}))
+        return
+    if args.paper_stop:
+        torch.cuda.set_device(0)
+        print(json.dumps({"paper_stop": paper_stop_times(torch, nc, args.paper_stop, args.paper_stop_h,
+                                                         acm_v_ref=args.paper_stop_acm_vref,
+                                                         solvers=tuple(args.paper_stop_solvers))}))
         return
     if args.edac_vref_sweep:
         torch.cuda.set_device(0)

@@ -88,6 +88,11 @@ class ACMSolver:
                     n_steps, self.ws)
         self.steps += n_steps
 
+    @property
+    def time_step(self) -> float:
+        """Physical time per step (Sec. 2.3: 0.1 h_min^2 / (2 nu) by default)."""
+        return self.prm.dt
+
     def flux(self):
         return api.flux_planes(self.d.s_idx, self.d.s_w, self.v[0], self.d.n_all, ws=self.d.red_ws)
 
@@ -195,6 +200,11 @@ class MLBMSolver:
         api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.unknown, self.f, self.f_tmp, n_steps)
         self.steps += n_steps
 
+    @property
+    def time_step(self) -> float:
+        """Physical time per step: delta t = nu_lb delta x^2 / nu (Sec. 2.2)."""
+        return self.units["dt"]
+
     def populations(self):
         """Host copy of the state as f [n][q] (unshifted)."""
         return self.f[:, :self.q].double().cpu().numpy() + lattice_weights(self.q)
@@ -233,3 +243,39 @@ class MLBMSolver:
         if self._wg is None:
             self._wg = api.rbffd_weights(d.pos, d.sb, [("dx",), ("dy",), ("dz",)])[0]
         return api.traction(v, p, d.sb, self._wg, d.nrm, 1.0, self.nu, ws=d.red_ws)
+
+
+def run_to_paper_criterion(solver, every: int = 10_000, tol: float = 1e-2, max_steps: int = 10_000_000,
+                           log=None, log_every: float = 30.0):
+    """Run until the paper's stopping criterion (Eq. stopCrit) holds: every
+    `every` steps the relative rate of change of the permeability,
+    |k(t) - k(t - Dt)| / (k(t) Dt) with Dt = every delta t in physical time,
+    is evaluated, and the run stops at the first check where it is below
+    `tol` (the paper: every 1e4 steps, tol 1e-2).  The first check compares
+    with the state the call started from.  Returns a dict with the steps and
+    physical time at the stop (counted from the solver's step 0), k there,
+    the last rate and the number of checks; "converged" is False if
+    max_steps ran out first.  log: optional callable(str), called about every
+    log_every seconds of wall-clock with the progress."""
+    import time
+    if every < 1 or not tol > 0:
+        raise ValueError("every must be >= 1 and tol > 0")
+    dt = solver.time_step * every
+    k_prev = solver.permeability()
+    rate, checks = math.inf, 0
+    t_log = time.perf_counter()
+    while solver.steps < max_steps:
+        solver.run(every)
+        k = solver.permeability()
+        checks += 1
+        rate = abs(k - k_prev) / (abs(k) * dt) if k != 0 else math.inf
+        if not math.isfinite(k):
+            raise FloatingPointError(f"permeability is {k} after {solver.steps} steps")
+        if rate < tol:
+            break
+        k_prev = k
+        if log and time.perf_counter() - t_log > log_every:
+            log(f"{solver.steps} steps, t = {solver.steps * solver.time_step:.4g}, k = {k:.6e}, rate {rate:.3e}")
+            t_log = time.perf_counter()
+    return {"steps": solver.steps, "time": solver.steps * solver.time_step, "k": k, "rate": rate,
+            "checks": checks, "converged": rate < tol}

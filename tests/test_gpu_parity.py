@@ -681,3 +681,39 @@ def test_autotune_and_tuned_launch(api, three_clouds):
         assert not info.cpu().numpy().any()
         w = w64.cpu().numpy().transpose(2, 0, 1)
         assert row_rel_err(w[:, 1], w_ref[:, 1]) < 1e-10
+
+
+def test_paper_stopping_criterion_on_the_gpu(api, disc_small):
+    """Eq. stopCrit on a real run: the MLBM run stops at the first check whose
+    relative rate of change of k is below 1e-2 per unit time, with every
+    earlier check above it.  Near steady state the gap to the settled k is
+    about rate x tau, with the relaxation time tau shorter than the time
+    already run, so the stop is within 1e-2 x t_stop of the settled k."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import MLBMSolver, run_to_paper_criterion
+    from paper_2404_14195_amd.warmstart import steady_fields
+    s = MLBMSolver(disc_small, q=19, precision=MPF_MIXED)
+    rates = []
+
+    class Probe:  # records the rate of every check of the same run
+        def __init__(self, inner):
+            self.inner, self.prev = inner, None
+
+        def __getattr__(self, name):
+            return getattr(self.inner, name)
+
+        def permeability(self):
+            k = self.inner.permeability()
+            if self.prev is not None:
+                rates.append(abs(k - self.prev) / (abs(k) * self.inner.time_step * 500))
+            self.prev = k
+            return k
+
+    out = run_to_paper_criterion(Probe(s), every=500, tol=1e-2)
+    assert out["converged"] and out["steps"] == s.steps and out["checks"] == len(rates)
+    assert rates[-1] < 1e-2 and all(r >= 1e-2 for r in rates[:-1])
+    assert out["time"] == pytest.approx(s.steps * s.units["dt"], rel=1e-15)
+    k_inf, _ = steady_fields(s, tol=1e-7)
+    print(f"[paper stop] {out['steps']} steps, t = {out['time']:.4f}, k = {out['k']:.6e}, settled {k_inf:.6e}",
+          flush=True)
+    assert abs(out["k"] / k_inf - 1) <= 1e-2 * out["time"]

@@ -1,0 +1,58 @@
+"""Host-side stop control of the solvers (no GPU): the paper's stopping
+criterion, Eq. stopCrit, on stand-in solvers whose permeability history is
+known exactly."""
+import math
+
+import pytest
+
+from paper_2404_14195_amd.solvers import run_to_paper_criterion
+
+
+class History:
+    """A stand-in solver: k is a given function of the physical time."""
+
+    def __init__(self, k_of_t, time_step):
+        self.k_of_t, self.time_step, self.steps = k_of_t, time_step, 0
+
+    def run(self, n):
+        self.steps += n
+
+    def permeability(self):
+        return self.k_of_t(self.steps * self.time_step)
+
+
+def test_linear_growth_stops_where_one_over_t_drops_below_tol():
+    """k = t gives a rate of exactly 1/t over any interval ending at t, so with
+    checks every Dt = 2 the run stops at the first check past t = 100 (at
+    t = 100 the rate equals the tolerance and does not pass)."""
+    s = History(lambda t: t, 0.5)
+    out = run_to_paper_criterion(s, every=4, tol=1e-2)
+    assert out["converged"] and out["steps"] == 204 and out["time"] == 102.0
+    assert out["rate"] == pytest.approx(1 / 102)
+    assert out["checks"] == 51
+
+
+def test_settled_history_stops_at_the_next_check():
+    s = History(lambda t: min(t, 10.0) + 1.0, 1.0)
+    out = run_to_paper_criterion(s, every=2, tol=1e-2)
+    assert out["rate"] == 0.0 and out["steps"] == 12 and out["k"] == 11.0
+
+
+def test_first_check_compares_with_the_starting_state():
+    """A run resumed from a settled state stops at its first check."""
+    s = History(lambda t: 3.0, 1.0)
+    s.steps = 1000
+    out = run_to_paper_criterion(s, every=10, tol=1e-2)
+    assert out["checks"] == 1 and out["steps"] == 1010 and out["time"] == 1010.0
+
+
+def test_running_out_of_steps_and_bad_input():
+    s = History(lambda t: math.exp(t), 1.0)  # rate stays near 1
+    out = run_to_paper_criterion(s, every=5, tol=1e-2, max_steps=50)
+    assert not out["converged"] and out["steps"] == 50 and out["checks"] == 10
+    with pytest.raises(FloatingPointError):
+        run_to_paper_criterion(History(lambda t: math.nan if t > 3 else t, 1.0), every=2)
+    with pytest.raises(ValueError):
+        run_to_paper_criterion(History(lambda t: t, 1.0), every=0)
+    with pytest.raises(ValueError):
+        run_to_paper_criterion(History(lambda t: t, 1.0), tol=0.0)
