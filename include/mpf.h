@@ -240,8 +240,10 @@ int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const 
  * except the max FP32) or MPF_MIXED (weights w, wn FP32; fields v, p and the
  * workspace FP64; FP64 arithmetic).
  * lanes: how many adjacent lanes share one node's stencil sum (1, 2, 4, 8 or
- * 16; 0 picks 8 for n_int <= 200000 and 2 above).  Results agree to rounding
- * (the order of the partial sums differs).
+ * 16; 0 lets the library pick from n_int and the state's precision: 8 up to
+ * 12000 interior nodes, 2 up to 50000, then 1, and 2 again above 500000 for
+ * an FP64 state).  Results agree to rounding (the order of the partial sums
+ * differs).
  * edac: 0 for the method as written; 1 for the entropically damped pressure
  * equation, which Sec. 2.3 names as the remedy for the stagnant-region
  * pressure oscillations of Sec. 3.6.  Its pressure update is

@@ -325,9 +325,22 @@ __global__ void fill_zero(T* __restrict__ x, int64_t n) {
   if (i < n) x[i] = T(0);
 }
 
-// below this many interior nodes a pass cannot fill the chip and is bound by
-// the chain of dependent gathers of one node: split each stencil 8 ways
-constexpr int64_t kFewNodes = 200000;
+// Lanes per node when the caller leaves the choice to the library, from a
+// sweep over cells of 2k to 1.8M nodes (N_L = 30, every precision).  Only a
+// pass too small to fill the chip gains from splitting each stencil 8 ways
+// (the dependent gather chain of one node is then the bound); from a few
+// tens of thousands of nodes on, the split's idle lanes and butterflies cost
+// more than they hide, and one lane per node wins (FP32 on 1.8M nodes: 1.43
+// vs 1.54 ms at 2 lanes; all precisions at 71k and 219k nodes, 2.4x over 8
+// lanes at 219k).  FP64 state records (32 bytes per gathered node) prefer 2
+// lanes again on the largest cells (1.8M nodes: 2.52 vs 2.69 ms FP64).
+template <typename T>
+int default_lanes(int64_t n_int) {
+  if (n_int <= 12000) return 8;
+  if (n_int <= 50000) return 2;
+  if (sizeof(T) == sizeof(double) && n_int > 500000) return 2;
+  return 1;
+}
 
 template <typename T, typename TW, int LPN, int NLC>
 int run_launches(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
@@ -385,7 +398,7 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(4 * n, kBlock)), dim3(kBlock), 0, st, F.VP, 4 * n);
   const bool edac = prm->edac != 0;
   int lanes = prm->lanes;
-  if (lanes == 0) lanes = n_int <= kFewNodes ? 8 : 2;
+  if (lanes == 0) lanes = default_lanes<T>(n_int);
   int rc;
   switch (lanes) {
     case 1: rc = launch_nl<T, TW, 1>(F, n_steps, prm->n_p, edac, st); break;
