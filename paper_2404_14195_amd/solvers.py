@@ -6,6 +6,7 @@ at checks, reads back one or three doubles."""
 from __future__ import annotations
 
 import math
+import time
 
 import numpy as np
 import torch
@@ -257,7 +258,6 @@ def run_to_paper_criterion(solver, every: int = 10_000, tol: float = 1e-2, max_s
     the last rate and the number of checks; "converged" is False if
     max_steps ran out first.  log: optional callable(str), called about every
     log_every seconds of wall-clock with the progress."""
-    import time
     if every < 1 or not tol > 0:
         raise ValueError("every must be >= 1 and tol > 0")
     dt = solver.time_step * every
