@@ -180,11 +180,12 @@ def test_acm_edac_parity_fp64_500_steps(api, disc_small, lanes, n_p):
     assert np.abs(o_edac.p - o_plain.p).max() > 1e-6 * np.abs(o_plain.p).max()
 
 
-@pytest.fixture(scope="module", params=[25, 45])
+@pytest.fixture(scope="module", params=[25, 45, 50])
 def disc_other_nl(api, small_cloud, request):
     """The 8k-node cell with stencils of other sizes: N_L = 25 takes the
-    second unrolled column loop of the ACM passes, N_L = 45 the generic one
-    (the first unrolled loop, N_L = 30, is the default fixture's)."""
+    second unrolled column loop of the ACM passes, N_L = 45 and the largest
+    supported size, 50, the generic one (the first unrolled loop, N_L = 30,
+    is the default fixture's)."""
     from paper_2404_14195_amd.solvers import Discretization
     return Discretization(small_cloud, nl=request.param, M=32)
 
