@@ -14,6 +14,7 @@ CPU oracle timed on the host.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -431,6 +432,55 @@ def gci_table(hs, X, fs=1.3):
     return {"p": p, "e_vs_finest": [float(x) for x in e], "pairs": rows}
 
 
+def hasimoto_K(r):
+    """Hasimoto's drag coefficient of a simple cubic array of spheres of
+    radius r in a unit cell, to the order of its solid-fraction series that
+    he gives: K = 1 / (1 - 1.7601 c^(1/3) + c - 1.5593 c^2), c = 4 pi r^3 / 3.
+    Close to the exact value only for dilute arrays (r <= 0.2)."""
+    c = 4.0 / 3.0 * math.pi * r ** 3
+    return 1.0 / (1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c * c)
+
+
+def hasimoto_check(torch, nc, radii=(0.1, 0.15), h0=0.012, slope=0.16, hmax=0.04, seed=1, paper_cloud=False,
+                   solvers=("mlbm", "acm")):
+    """Both solvers (mixed precision, N_L = 30) run to steady state on dilute
+    cells and compared with Hasimoto's drag: K from the surface tractions
+    (Eqs. stress_tensor_force, K_definition) and k/d^2 against 1 / (6 pi r K),
+    which is what the body-force balance F = rho |g| phi d^3 turns K into.
+    paper_cloud: the paper's Gaussian refinement with h_min = h0 (h <= 2 h0
+    everywhere) instead of h(d) = min(h0 + slope d, hmax)."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver
+    say = lambda m: print(f"[bench] hasimoto: {m}", file=sys.stderr, flush=True)
+    out = []
+    for r in radii:
+        cloud = nc.gauss_cloud(r, h0, seed=seed) if paper_cloud else nc.sphere_cloud(r, h0, slope, hmax, seed=seed)
+        disc = Discretization(cloud, nl=30, M=64)
+        K_h = hasimoto_K(r)
+        rec = {"r": r, "n": cloud.n, "h": f"paper h_min={h0}" if paper_cloud else f"min({h0}+{slope}d,{hmax})",
+               "K_hasimoto": K_h,
+               "k_hasimoto": 1.0 / (6.0 * math.pi * r * K_h)}
+        for name, make, check, tol in (("mlbm", lambda: MLBMSolver(disc, q=19, precision=MPF_MIXED), 500, 1e-8),
+                                       ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED), 5000, 1e-7)):
+            if name not in solvers:
+                continue
+            t0 = time.perf_counter()
+            s = make()
+            k, k_inf, settled = _settle(s, check, 3_000_000, tol)
+            _, K = s.drag()
+            rec[name] = {"k": k, "K": float(K), "steps": s.steps, "settled": bool(settled),
+                         "k_rel_err": k / rec["k_hasimoto"] - 1.0, "K_rel_err": float(K) / K_h - 1.0,
+                         "balance": float(K) * k * 6.0 * math.pi * r, "seconds": time.perf_counter() - t0}
+            say(f"r={r} n={cloud.n} {name}: k={k:.6e} (Hasimoto {rec['k_hasimoto']:.6e}, "
+                f"{rec[name]['k_rel_err']:+.2%}), K={float(K):.5f} (Hasimoto {K_h:.5f}, "
+                f"{rec[name]['K_rel_err']:+.2%}), {s.steps} steps, settled={settled}, {rec[name]['seconds']:.1f}s")
+            del s
+        out.append(rec)
+        del disc
+        torch.cuda.empty_cache()
+    return out
+
+
 # Physical times to the stopping criterion printed in Sec. 3.4 (h_min = 0.007).
 PAPER_STOP_TIME = {0.062: {"mlbm": 3.57, "acm": 3.58}, 0.6526: {"mlbm": 0.04, "acm": 0.39}}
 
@@ -788,6 +838,11 @@ def main():
     ap.add_argument("--paper-stop-h", type=float, nargs="+", default=[0.014])
     ap.add_argument("--paper-stop-solvers", nargs="+", default=["mlbm", "acm"])
     ap.add_argument("--paper-stop-acm-vref", type=float, default=None)
+    ap.add_argument("--hasimoto", action="store_true",
+                    help="both solvers to steady state on dilute cells against Hasimoto's drag")
+    ap.add_argument("--hasimoto-h0", type=float, nargs="+", default=[0.012])
+    ap.add_argument("--hasimoto-paper-cloud", action="store_true")
+    ap.add_argument("--hasimoto-solvers", nargs="+", default=["mlbm", "acm"])
     ap.add_argument("--lbm-large", action="store_true",
                     help="only the MLBM step on the 581k-node cell (weights streamed past the caches)")
     ap.add_argument("--lbm-large-steps", type=int, default=300)
@@ -831,6 +886,12 @@ def main():
                                                            solvers=tuple(args.conv_solvers),
                                                            acm_v_ref=args.conv_acm_vref,
                                                            acm_edac=args.conv_acm_edac)}))
+        return
+    if args.hasimoto:
+        torch.cuda.set_device(0)
+        print(json.dumps({"hasimoto": [hasimoto_check(torch, nc, h0=h0, paper_cloud=args.hasimoto_paper_cloud,
+                                                      solvers=tuple(args.hasimoto_solvers))
+                                       for h0 in args.hasimoto_h0]}))
         return
     if args.paper_stop:
         torch.cuda.set_device(0)
