@@ -282,7 +282,9 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  *         may be NULL when nb = 0)
  * f     dev [n][qp] state, updated in place; f_tmp dev [n][qp] scratch:
  *       double for MPF_F64 and MPF_MIXED, float for MPF_F32
- * q is 15 or 19. */
+ * q is 15 or 19.  A W larger than 512 MiB (twice the Infinity Cache) is read
+ * with non-temporal loads so that it does not evict the gathered population
+ * records; the results are the same bit for bit either way. */
 typedef struct {
   int32_t q;
   int32_t precision;
