@@ -75,3 +75,23 @@ def test_gci_of_a_hand_computed_series(bench):
         eps = abs(xc - xf) / xf
         assert row["h"] == hf and row["eps"] == pytest.approx(eps, rel=1e-12)
         assert row["gci"] == pytest.approx(1.3 * eps / ((hc / hf) ** p - 1.0), rel=1e-12)
+
+
+def test_hasimoto_drag_limits(bench):
+    """Hasimoto's series: an isolated sphere's Stokes drag (K -> 1) as the
+    array dilutes, with the leading correction 1.7601 c^(1/3) of the periodic
+    images; and the permeability the paper derives from K, d / (6 pi r K),
+    falls with the radius."""
+    for r in (1e-3, 1e-2):
+        c = 4.0 / 3.0 * math.pi * r ** 3
+        x = c ** (1.0 / 3.0)
+        K = bench.hasimoto_K(r)
+        assert abs(K - (1.0 + 1.7601 * x)) <= 5.0 * x * x  # next term is (1.7601 x)^2
+    ks = [1.0 / (6.0 * math.pi * r * bench.hasimoto_K(r)) for r in (0.05, 0.1, 0.15, 0.2)]
+    assert all(a > b for a, b in zip(ks, ks[1:]))
+
+
+def test_paper_stop_times_are_the_printed_ones(bench):
+    """The physical times to the stopping criterion that Sec. 3.4 prints
+    (h_min = 0.007), as the bench reports them beside its own."""
+    assert bench.PAPER_STOP_TIME == {0.062: {"mlbm": 3.57, "acm": 3.58}, 0.6526: {"mlbm": 0.04, "acm": 0.39}}
