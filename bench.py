@@ -119,9 +119,12 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
     return out
 
 
-def copy_bandwidth(torch, mib=1024, reps=5):
-    """Achievable HBM bandwidth: best of reps device-to-device copies of mib
-    MiB (read + write bytes over time)."""
+def copy_bandwidth(torch, mib=1024, reps=5, inner=1):
+    """Achievable bandwidth of a plain device-to-device copy of mib MiB (read
+    + write bytes over time), best of reps timings of inner back-to-back
+    copies.  At 1 GiB the copy streams from HBM; a copy whose read + write
+    bytes fit the 256 MB Infinity Cache is served partly from it when
+    repeated, as a stencil step on a cell of that size is."""
     src = torch.ones(mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -130,13 +133,14 @@ def copy_bandwidth(torch, mib=1024, reps=5):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record()
-        dst.copy_(src)
+        for _ in range(inner):
+            dst.copy_(src)
         ev1.record()
         torch.cuda.synchronize()
         best = min(best, ev0.elapsed_time(ev1))
     del src, dst
     torch.cuda.empty_cache()
-    return 2 * mib * 2 ** 20 / (best * 1e-3) / 1e9
+    return 2 * mib * 2 ** 20 * inner / (best * 1e-3) / 1e9
 
 
 def train_warm_start(torch, nc, n_cells=16, h0=0.016, epochs=200, batch=8192):
@@ -989,9 +993,15 @@ def main():
     bpn = bytes_per_node_step(19, 30, 4, 4)
     achieved = bpn * disc.n / (f32["step_kernel_ms"] * 1e-3) / 1e9
     copy_gbs = copy_bandwidth(torch)
+    # a copy moving the step's algorithmic bytes per launch (read + write), the
+    # ceiling at this working-set size: it fits the Infinity Cache
+    same_mib = max(1, round(bpn * disc.n / 2 / 2 ** 20))
+    copy_same = copy_bandwidth(torch, mib=same_mib, reps=5, inner=20)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "kernel": "lbm_step<float,float,19,true,false>", "bytes_per_node_step": bpn,
-            "launch_ms": f32["step_kernel_ms"], "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
+            "launch_ms": f32["step_kernel_ms"], "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+            "copy_same_bytes_MiB": 2 * same_mib, "copy_same_bytes_GBs": copy_same,
+            "frac_of_same_bytes_copy": achieved / copy_same}
 
     cpu = None
     if not args.no_cpu_baseline:
