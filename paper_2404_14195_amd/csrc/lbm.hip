@@ -118,8 +118,11 @@ __global__ __launch_bounds__(kBlock) void lbm_collide(int64_t n, const T* src, T
 // sees one contiguous (Morton-ordered, hence compact) range of nodes.
 constexpr int kTile = 64;
 constexpr int kXcd = 8;
-constexpr int kStepWaves = 8;  // waves per 64-node tile in the step kernel
-constexpr int kStepBlock = kStepWaves * kWave;
+// Waves per 64-node tile in the step kernel: 8, and 6 for FP32 weights with
+// an FP64 state (6 % faster on a 581k-node cell, equal on a 71k-node one;
+// FP32 and FP64 are fastest at 8 on both).
+template <typename TW, typename T>
+constexpr int step_waves() { return sizeof(TW) == 4 && sizeof(T) == 8 ? 6 : 8; }
 
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) { return (b % kXcd) * (G / kXcd) + b / kXcd; }
 
@@ -129,8 +132,8 @@ inline unsigned tiles_grid(int64_t n) {
   return (unsigned)t;
 }
 
-// One step for a tile of 64 nodes (lane = node).  The eight waves of the
-// block take every eighth stencil column; for each column a lane loads its
+// One step for a tile of 64 nodes (lane = node).  The waves of the
+// block (step_waves) take the stencil columns in turn; for each column a lane loads its
 // neighbour's whole population record with 16-byte loads and accumulates all
 // q - 1 moving populations against the coalesced weights.  The partial sums
 // meet in LDS and are added in a fixed order by the first wave, which then
@@ -142,7 +145,7 @@ inline unsigned tiles_grid(int64_t n) {
 // HBM anyway, and streaming them keeps the gathered population records in the
 // caches (6 % faster at 1.26-2.5 GB of weights, all precisions).
 template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W>
-__global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int, int nl,
+__global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(int64_t n, int64_t n_int, int nl,
                                                        const int32_t* __restrict__ sten,
                                                        const TW* __restrict__ W,
                                                        const uint32_t* __restrict__ unknown,
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(kStepBlock) void lbm_step(int64_t n, int64_t n_int,
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
   constexpr int NV = QP / VN;
-  constexpr int NW = kStepWaves;
+  constexpr int NW = step_waves<TW, T>();
   __shared__ T part[NW][Q - 1][kTile];
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile * kTile >= n) return;  // whole block
@@ -354,11 +357,11 @@ void launch_steps(int64_t n, int64_t n_int, int nl, const int32_t* sten, const T
   const unsigned gt = tiles_grid(n);
   for (int s = 0; s < n_steps - 1; ++s) {
     T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten,
+    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W>), dim3(gt), dim3(step_waves<TW, T>() * kWave), 0, st, n, n_int, nl, sten,
                        W, unknown, (const T*)cur, nxt, pr);
     cur = nxt;
   }
-  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W>), dim3(gt), dim3(kStepBlock), 0, st, n, n_int, nl, sten,
+  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W>), dim3(gt), dim3(step_waves<TW, T>() * kWave), 0, st, n, n_int, nl, sten,
                      W, unknown, (const T*)cur, f, pr);
 }
 
