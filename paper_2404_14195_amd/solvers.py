@@ -261,7 +261,7 @@ def run_to_paper_criterion(solver, every: int = 10_000, tol: float = 1e-2, max_s
     if every < 1 or not tol > 0:
         raise ValueError("every must be >= 1 and tol > 0")
     dt = solver.time_step * every
-    k_prev = solver.permeability()
+    k = k_prev = solver.permeability()
     rate, checks = math.inf, 0
     t_log = time.perf_counter()
     while solver.steps < max_steps:

@@ -50,6 +50,10 @@ def test_running_out_of_steps_and_bad_input():
     s = History(lambda t: math.exp(t), 1.0)  # rate stays near 1
     out = run_to_paper_criterion(s, every=5, tol=1e-2, max_steps=50)
     assert not out["converged"] and out["steps"] == 50 and out["checks"] == 10
+    s = History(lambda t: 2.0, 1.0)
+    s.steps = 60  # already past max_steps: no check, nothing run
+    out = run_to_paper_criterion(s, every=5, max_steps=50)
+    assert out == {"steps": 60, "time": 60.0, "k": 2.0, "rate": math.inf, "checks": 0, "converged": False}
     with pytest.raises(FloatingPointError):
         run_to_paper_criterion(History(lambda t: math.nan if t > 3 else t, 1.0), every=2)
     with pytest.raises(ValueError):
