@@ -145,3 +145,42 @@ def test_singular_system_flagged():
     pts[S[0, 5]] = pts[S[0, 6]]  # two coincident stencil nodes: identical rows
     w, info = O.weights(pts, S, [("dx",)])
     assert info[0] > 0
+
+
+def null_space_weights(X, op):
+    """Weights of one row by a second algorithm: the null-space method for the
+    saddle system [A P; P^T 0][w; lam] = [b; c] (Sec. 2.1, PHS r^3 plus the ten
+    monomials), in the row's own minimum-image coordinates X [nl][3] (the
+    weights do not depend on a scaling).  P = Q R; w = Q1 R^-T c + Q2 z with
+    (Q2^T A Q2) z = Q2^T (b - A Q1 R^-T c); no factorisation of the full saddle
+    matrix is involved.  b_j is L applied to |x - x_j|^3 at x = 0, written from
+    calculus: d/dx gives -3 |x_j| x_j,x; the Laplacian gives 12 |x_j|."""
+    r = np.sqrt((X * X).sum(1))
+    A = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(2)) ** 3
+    P = np.stack([f(X[:, 0], X[:, 1], X[:, 2]) for f in MONO], 1)  # [nl][10]
+    b = -3.0 * r * X[:, 0] if op == "dx" else 12.0 * r
+    c = target(op, None)
+    Q, R = np.linalg.qr(P, mode="complete")
+    m = P.shape[1]
+    Q1, Q2, R1 = Q[:, :m], Q[:, m:], R[:m, :]
+    w0 = Q1 @ np.linalg.solve(R1.T, c)
+    z = np.linalg.solve(Q2.T @ A @ Q2, Q2.T @ (b - A @ w0))
+    return w0 + Q2 @ z
+
+
+def test_null_space_method_agrees(small_cloud, small_stencils):
+    """The oracle's weights (LU with partial pivoting of the full saddle
+    matrix) against the null-space method on every 40th row, for the x
+    derivative and the Laplacian: they agree to the systems' conditioning."""
+    pos, S = small_cloud.pos, small_stencils
+    rows = np.arange(0, S.shape[0], 40)
+    ops = [("dx",), ("lap",)]
+    w, info = O.weights(pos, S[rows], ops)
+    assert not info.any()
+    worst = 0.0
+    for k, i in enumerate(rows):
+        X = nc.min_image(pos[S[i]] - pos[S[i, 0]])
+        for o, (op,) in enumerate(ops):
+            ref = null_space_weights(X, op)
+            worst = max(worst, np.abs(w[k, o] - ref).max() / np.abs(ref).max())
+    assert worst < 1e-11, worst  # measured 1e-13
