@@ -192,3 +192,60 @@ def test_nominal_step_on_a_jittered_channel_is_not_stable():
         dev[name] = np.abs(a.v[:, 0] - u).max() / u.max()
     assert dev["nominal"] > 1e-9  # grown by six orders of magnitude from rounding
     assert dev["half"] < 1e-13
+
+
+# --- pins of the pressure update (Eq. MNS_pressure) and the Neumann pass ---
+
+def test_pressure_update_coefficient_on_a_linear_field(box):
+    """Eq. MNS_pressure with C != 0 and div v' != 0.  From v = (aX, bY, cZ)
+    without forcing the predictor is exact: the Laplacian vanishes and
+    (v . grad) v = (a^2 X, b^2 Y, c^2 Z), so v' = (a(1 - dt a) X, ...) and
+    div v' = a(1 - dt a) + b(1 - dt b) + c(1 - dt c).  The first pressure
+    update then gives p = -dt C^2 rho div v' with C = beta |v_ref| (the sound
+    speed before the first correction).  Mistakes this catches: C for C^2, a
+    dropped rho, div v instead of div v', one divergence term taken from the
+    wrong weight row (a transposed operand) and a sign error."""
+    c, S, safe = box
+    X, Y, Z = (c.pos - 0.5).T
+    dt, rho, beta, v_ref = 1e-3, 1.3, 2.0, 0.7
+    a_, b_, c_ = 0.9, -0.4, 0.25
+    o = O.ACM(c.pos, c.n, S, np.zeros((0, 3)), dt=dt, rho=rho, beta=beta, v_ref=v_ref, g=(0, 0, 0), n_p=1)
+    o.v[:] = np.stack([a_ * X, b_ * Y, c_ * Z], 1)
+    o.run(1)
+    div = a_ * (1 - dt * a_) + b_ * (1 - dt * b_) + c_ * (1 - dt * c_)
+    C = beta * v_ref
+    expect = -dt * C * C * rho * div
+    s2 = stencil_safe(S, safe)  # v' is exact at every stencil node of these
+    assert s2.sum() > 50
+    assert np.abs(o.p[s2] - expect).max() < 1e-13 * abs(expect)
+    # the alternatives named above all miss by far more than the bound
+    for wrong in (-dt * C * rho * div, -dt * C * C * div, -dt * C * C * rho * (a_ + b_ + c_),
+                  -dt * C * C * rho * (a_ * (1 - dt * a_) + 2 * b_ * (1 - dt * b_)), dt * C * C * rho * div):
+        assert abs(wrong - expect) > 1e-6 * abs(expect)
+
+
+def test_neumann_pass_reproduces_a_field_with_zero_normal_derivative():
+    """The boundary update of the coupling iteration solves the discrete
+    dp/dn = 0 row for the node's own pressure.  On the plane channel the
+    normals are +-z, so any quadratic in x and y alone has zero normal
+    derivative; the normal-derivative weights are exact on quadratics, and the
+    solved value must be the field's own value at the wall node, whatever the
+    wall held before.  From rest without forcing the interior pressure is
+    untouched (div v' = 0), so one iteration isolates the pass.  A sign error
+    in the solve gives -q at the wall, a wrong self weight a scaled q."""
+    c = nc.channel_cloud(0.05, 0.5, seed=4)
+    S, Sn = nc.solver_stencils(c, 30), nc.neumann_stencils(c, 30)
+    X, Y = c.pos[:, 0] - 0.5, c.pos[:, 1] - 0.5
+    q = 1.0 + X * X - 0.5 * X * Y + 0.3 * Y + 0.2 * X - 0.7 * Y * Y
+    o = O.ACM(c.pos, c.n_int, S, c.nrm, sten_n=Sn, dt=1e-5, g=(0, 0, 0), n_p=1)
+    o.p[:] = q
+    o.p[c.n_int:] = 123.0  # the old wall values must not matter
+    o.run(1)
+    # wall nodes whose Neumann stencil does not wrap in x or y
+    d_raw = c.pos[Sn] - c.pos[Sn[:, :1]]
+    safe = np.all(np.abs(d_raw - nc.min_image(d_raw)) < 1e-12, axis=(1, 2))
+    assert safe.sum() > 200
+    pb = o.p[c.n_int:]
+    qb = q[c.n_int:]
+    assert np.abs(pb[safe] - qb[safe]).max() < 1e-12
+    assert np.array_equal(o.p[:c.n_int], q[:c.n_int])  # interior untouched

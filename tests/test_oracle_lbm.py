@@ -268,3 +268,42 @@ def test_bounce_back_reads_streamed_values():
     assert f[b, k] == pytest.approx(f0[up, kb], abs=1e-15)
     assert f[b, kb] == pytest.approx(f0[down, k], abs=1e-15)
     assert abs(f0[up, kb] - f0[down, k]) > 1e-4  # the two readings differ here
+
+
+# --- the two relaxation rates of Eq. LBM_collision, each on its own mode ---
+
+@pytest.mark.parametrize("q", [15, 19])
+@pytest.mark.parametrize("tau_plus,magic", [(1.0, 1.0), (0.8, 0.25), (0.62, 0.03)])
+def test_trt_relaxes_odd_and_even_modes_at_their_own_rates(q, tau_plus, magic):
+    """TRT relaxes the symmetric part of f - f^eq at 1/tau+ and the
+    antisymmetric part at 1/tau- (Eq. LBM_collision with Lambda =
+    (tau+ - 1/2)(tau- - 1/2)).  Add to a uniform moving equilibrium the odd
+    mode eps w_k (e_kx (e_ky^2 - e_kz^2) + e_kx e_ky e_kz) (the first term
+    lives on the D3Q19 edge vectors, the second on the D3Q15 diagonals), which
+    has no mass and no momentum on either lattice (fourth-order isotropy and
+    parity), so rho, u and f^eq are unchanged:
+    after one step (without forcing, a uniform state streams onto itself) the
+    mode must be scaled by exactly 1 - 1/tau-.  The even mode
+    eps w_k (e_kx^2 - e_ky^2) likewise has no mass or momentum and must be
+    scaled by 1 - 1/tau+.  Taking 1/tau+ for both parts, swapping the two, or
+    a sign error in either relaxation term fails one of the two checks."""
+    n = 6
+    c = nc.lattice_cloud(n)
+    S = nc.stencils(c.pos, 27)
+    m = O.MLBM(c.pos, c.n, S, np.zeros((0, 3)), q=q, dx=1.0 / n, tau_plus=tau_plus, magic=magic, g=(0, 0, 0))
+    tau_minus = 0.5 + magic / (tau_plus - 0.5)
+    assert m.tau_minus == pytest.approx(tau_minus, rel=1e-15)
+    e, w, _ = O.lattice(q)
+    feq = O.equilibrium(q, 1, 1.02, np.array([0.03, -0.02, 0.01]))[0]
+    odd = w * (e[:, 0] * (e[:, 1] ** 2 - e[:, 2] ** 2) + e[:, 0] * e[:, 1] * e[:, 2])
+    even = w * (e[:, 0] ** 2 - e[:, 1] ** 2)
+    for mode in (odd, even):  # neither mode carries mass or momentum
+        assert abs(mode.sum()) < 1e-17 and np.abs(mode @ e).max() < 1e-17
+    eps = 1e-3
+    for mode, tau in ((odd, tau_minus), (even, tau_plus)):
+        m.f[:] = feq + eps * mode
+        m.run(1)
+        expect = feq + (1.0 - 1.0 / tau) * eps * mode
+        assert np.abs(m.f - expect).max() < 1e-15
+    # the two rates are distinguishable in every case above
+    assert abs(1.0 / tau_minus - 1.0 / tau_plus) * eps * np.abs(odd).max() > 1e-7
