@@ -28,11 +28,12 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 CHECK_EVERY = 100
 
 
-def bytes_per_node_step(q, nl, s_w, s_f, s_i=4):
+def bytes_per_node_step(q, nl, s_w, s_f, s_i=4, s_comp=0):
     """Algorithmic HBM bytes of one MLBM node-step: the q-1 interpolation
     weight rows and the stencil indices streamed once, the q populations read
-    once (gathers of neighbours hit the caches) and written once."""
-    return (q - 1) * s_w * nl + s_i * nl + 2 * q * s_f
+    once (gathers of neighbours hit the caches) and written once; a
+    compensated state also reads and writes its q compensation terms."""
+    return (q - 1) * s_w * nl + s_i * nl + 2 * q * s_f + 2 * q * s_comp
 
 
 def measured_traffic():
@@ -59,8 +60,10 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
     1e-8 relative per check, then Aitken-extrapolated from its last three
     checks.  Every other run is timed into the band and then continued until
     it settles too, so that its own steady k (where rounding stalls the
-    iteration) is reported against k_inf.  warm: optional callable(solver)
-    that loads a predicted state; its time counts."""
+    iteration) is reported against k_inf.  warm: optional {suffix: (callable
+    (solver) that loads a start state, [precision names])}; each listed
+    precision also runs from that start, named <precision>_<suffix>, and the
+    loading (prediction, burn-in, flux matches) counts in its time."""
     def trajectory(prec, stop, init=None):
         s = MLBMSolver(disc, q=19, precision=prec)
         torch.cuda.synchronize()
@@ -93,8 +96,9 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
     for name, prec in precisions.items():
         if name != "fp64":
             runs[name] = trajectory(prec, settled)
-        if warm is not None:
-            runs[name + "_warm"] = trajectory(prec, settled, warm)
+        for suffix, (load, names) in (warm or {}).items():
+            if name in names:
+                runs[f"{name}_{suffix}"] = trajectory(prec, settled, load)
 
     def inside(k):
         return abs(k - k_inf) <= rel * abs(k_inf)
@@ -110,13 +114,62 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
                      "first_entry_steps": None if entry is None else ns[entry],
                      "max_rel_err_after_entry": None if entry is None else max(abs(k / k_inf - 1) for k in ks[entry:]),
                      "settled_after_steps": ns[-1], "settled_k": ks[-1],
-                     "settled_rel_err": abs(ks[-1] - k_inf) / abs(k_inf), "initial_k": ks[0] if name.endswith("_warm") else 0.0}
+                     "settled_rel_err": abs(ks[-1] - k_inf) / abs(k_inf),
+                     "initial_k": ks[0] if name not in precisions else 0.0}
     base = out["fp64"]["seconds"]
     for name in runs:
         if name != "fp64" and out[name]["seconds"]:
             out[name]["speedup_vs_fp64"] = base / out[name]["seconds"]
     print("[bench] time to steady: " + json.dumps(out), file=sys.stderr, flush=True)
     return out
+
+
+def host_cpu():
+    """(nproc, CPU model, usable cores) of the host this runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return os.cpu_count(), model, usable
+
+
+def cpu_baseline(cloud, disc, seconds):
+    """The FP64 oracle's MLBM step timed on the host (weights precomputed and
+    not timed): single-threaded as the paper ran it, and on all usable host
+    cores (OpenMP over nodes; OMP_NUM_THREADS caps it where set).  Each leg
+    runs about `seconds` of steps; the reported value is the all-cores leg."""
+    import oracle as O
+    nproc, model, usable = host_cpu()
+    env_cap = os.environ.get("OMP_NUM_THREADS")
+    threads = min(usable, int(env_cap)) if env_cap and env_cap.isdigit() else usable
+    o = O.MLBM(cloud.pos, cloud.n_int, disc.sten_host, cloud.nrm, q=19, h_min=cloud.h_min)
+    legs = {}
+    try:
+        for th in (1, threads):
+            used = O.set_threads(th)
+            t0 = time.perf_counter()
+            o.run(2)
+            per = (time.perf_counter() - t0) / 2
+            n_cpu = max(2, int(seconds / per))
+            t0 = time.perf_counter()
+            o.run(n_cpu)
+            dt_cpu = time.perf_counter() - t0
+            legs[used] = {"value": cloud.n * n_cpu / dt_cpu, "steps": n_cpu, "seconds": dt_cpu}
+            print(f"[bench] cpu oracle, {used} thread(s): {legs[used]['value']:.3e} node-steps/s", file=sys.stderr,
+                  flush=True)
+    finally:
+        O.set_threads(1)
+    all_cores = legs[max(legs)]
+    return {"value": all_cores["value"], "unit": "node-steps/s", "cores": max(legs), "kind": "oracle",
+            "sample": f"{all_cores['steps']} FP64 steps of the full {cloud.n}-node cell (weights precomputed, not "
+                      f"timed), scalar C, OpenMP over nodes on {max(legs)} threads",
+            "single_thread": legs[1]["value"], "single_thread_steps": legs[1]["steps"],
+            "nproc": nproc, "usable_cores": usable, "cpu_model": model}
 
 
 def copy_bandwidth(torch, mib=1024, reps=5, inner=1):
@@ -818,7 +871,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="per leg (one thread, all cores)")
     ap.add_argument("--no-extra", action="store_true", help="skip the ACM and weight-solve side measurements")
     ap.add_argument("--no-steady", action="store_true", help="skip the time-to-steady measurement")
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
@@ -864,7 +917,7 @@ def main():
     import torch
 
     import nodecloud as nc
-    from paper_2404_14195_amd import MPF_F32, MPF_F64, MPF_MIXED, api
+    from paper_2404_14195_amd import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, api
     from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
 
     if args.acm_sweep:
@@ -940,11 +993,13 @@ def main():
           file=sys.stderr, flush=True)
 
     res = {}
-    for name, prec in (("f32", MPF_F32), ("mixed", MPF_MIXED), ("f64", MPF_F64)):
+    for name, prec in (("f32", MPF_F32), ("f32_kahan", MPF_F32_KAHAN), ("mixed", MPF_MIXED), ("f64", MPF_F64)):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record()
-        s = MLBMSolver(disc, q=19, precision=prec)
+        # the throughput loop reads k every CHECK_EVERY steps and does not
+        # wait for the flags word after every call
+        s = MLBMSolver(disc, q=19, precision=prec, check=False)
         ev1.record()
         torch.cuda.synchronize()
         t_weights = ev0.elapsed_time(ev1)
@@ -1005,24 +1060,19 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-        o = O.MLBM(cloud.pos, cloud.n_int, disc.sten_host, cloud.nrm, q=19, h_min=cloud.h_min)
-        t0 = time.perf_counter()
-        o.run(2)
-        per = (time.perf_counter() - t0) / 2
-        n_cpu = max(2, int(args.cpu_seconds / per))
-        t0 = time.perf_counter()
-        o.run(n_cpu)
-        dt_cpu = time.perf_counter() - t0
-        cpu = {"value": cloud.n * n_cpu / dt_cpu, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n_cpu} FP64 steps of the full {cloud.n}-node cell (weights precomputed, not timed), "
-                         f"single-threaded scalar C"}
+        cpu = cpu_baseline(cloud, disc, args.cpu_seconds)
 
     tts = ws_info = None
     if not args.no_steady:
         ws_model, ws_info = (None, None) if args.no_warm else train_warm_start(torch, nc)
-        tts = time_to_steady(torch, disc, MLBMSolver, {"fp64": MPF_F64, "fp32": MPF_F32, "mixed": MPF_MIXED},
-                             warm=None if ws_model is None else ws_model.load_mlbm)
+        starts = None
+        if ws_model is not None:
+            starts = {"warm": (ws_model.load_mlbm, ["fp64", "fp32", "mixed", "fp32_kahan"]),
+                      # the same magnitude, burn-in and flux matches without the network
+                      "nonet": (lambda s: ws_model.load_mlbm(s, network=False), ["mixed", "fp32_kahan"])}
+        tts = time_to_steady(torch, disc, MLBMSolver,
+                             {"fp64": MPF_F64, "fp32": MPF_F32, "mixed": MPF_MIXED, "fp32_kahan": MPF_F32_KAHAN},
+                             warm=starts)
     extra = None if args.no_extra else acm_and_weights(torch, nc, api)
 
     out = {
@@ -1036,13 +1086,20 @@ def main():
                  "step_kernel_ms": res["f64"]["step_kernel_ms"],
                  "roofline_frac": bytes_per_node_step(19, 30, 8, 8) * disc.n / (res["f64"]["step_kernel_ms"] * 1e-3)
                  / 1e9 / HBM_PEAK_GBS},
+        "fp32_kahan": {"value": res["f32_kahan"]["value"], "ms_per_step": res["f32_kahan"]["ms_per_step"],
+                       "step_kernel_ms": res["f32_kahan"]["step_kernel_ms"],
+                       "step_vs_fp32": res["f32_kahan"]["step_kernel_ms"] / f32["step_kernel_ms"],
+                       "roofline_frac": bytes_per_node_step(19, 30, 4, 4, s_comp=4) * disc.n
+                       / (res["f32_kahan"]["step_kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "precision": "fp32 weights and populations plus an fp32 compensation record per node"},
         "mixed": {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_step"],
                   "step_kernel_ms": res["mixed"]["step_kernel_ms"],
                   "roofline_frac": bytes_per_node_step(19, 30, 4, 8) * disc.n
                   / (res["mixed"]["step_kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                   "precision": "fp32 weights, fp64 populations and arithmetic"},
-        "k": {"fp32": f32["k"], "mixed": res["mixed"]["k"], "fp64": res["f64"]["k"],
+        "k": {"fp32": f32["k"], "mixed": res["mixed"]["k"], "fp64": res["f64"]["k"], "fp32_kahan": res["f32_kahan"]["k"],
               "rel_err_fp32": abs(f32["k"] / res["f64"]["k"] - 1.0),
+              "rel_err_fp32_kahan": abs(res["f32_kahan"]["k"] / res["f64"]["k"] - 1.0),
               "rel_err_mixed": abs(res["mixed"]["k"] / res["f64"]["k"] - 1.0), "steps": f32["steps_total"]},
         "weights_ms": {"fp32": f32["weights_ms"], "fp64": res["f64"]["weights_ms"]},
         "roofline": roof,

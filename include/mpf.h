@@ -50,20 +50,50 @@ extern "C" {
 #define MPF_ERR_ARG (-1)         /* invalid argument (host check, nothing launched) */
 #define MPF_ERR_HIP (-2)         /* a HIP runtime call failed */
 #define MPF_ERR_UNSUPPORTED (-3) /* valid but not built: e.g. a stencil size without a kernel */
-#define MPF_ERR_WORKSPACE (-4)   /* workspace missing or too small */
+#define MPF_ERR_DIVERGED (-4)    /* a *_run given a flags word found it set at the end of the call */
+#define MPF_ERR_WORKSPACE (-5)   /* workspace missing or too small */
 
 /* Precision of stencil weights and state.
- *   MPF_F64    weights and state FP64
- *   MPF_F32    weights and state FP32 (reductions stay FP64)
- *   MPF_MIXED  weights FP32, state and all step arithmetic FP64.  An explicit
- *              iteration whose slowest mode decays over tau steps settles
- *              within about tau ulp of its fixed point, so FP32 state stalls
- *              at ~1e-3 relative on the cells here (tau ~ 2e4 steps); the
- *              weights, which dominate the bytes per step, carry the FP32
- *              saving without that stall. */
+ *   MPF_F64        weights and state FP64
+ *   MPF_F32        weights and state FP32 (reductions stay FP64)
+ *   MPF_MIXED      weights FP32, state and all step arithmetic FP64.  An
+ *                  explicit iteration whose slowest mode decays over tau steps
+ *                  and whose state is rounded every step stops within about
+ *                  tau ulp of its fixed point (the updates fall below half an
+ *                  ulp), so an FP32 state stalls at ~1e-3 relative on the
+ *                  cells here (tau ~ 2e4 steps).
+ *   MPF_F32_KAHAN  weights and state FP32 plus an FP32 compensation term per
+ *                  state value (caller-owned, argument comp): the state is
+ *                  hi + lo with hi the FP32 rounding of the value, neighbours
+ *                  gather hi only, and each node's update is formed in FP64
+ *                  from its own hi + lo and split back, so updates below half
+ *                  an ulp of hi accumulate in lo instead of being lost.  The
+ *                  gathered bytes stay those of MPF_F32. */
 #define MPF_F64 0
 #define MPF_F32 1
 #define MPF_MIXED 2
+#define MPF_F32_KAHAN 3
+
+/* Flags word (device uint32) that the *_run calls OR bits into when given
+ * one; the caller clears it.  At the end of such a call the library waits for
+ * the stream, reads the word and returns MPF_ERR_DIVERGED if any bit is set
+ * (pass NULL to keep a call fully asynchronous, e.g. under graph capture).
+ *   bit 0  a non-finite state value (NaN or inf) was produced
+ *   bit 1  a stability limit was exceeded: for the ACM the Courant number
+ *          of the pressure waves, C dt / h_min > 1 (only when the params give
+ *          h_min > 0); for the MLBM a lattice speed |u| >= c_s = 1/sqrt(3),
+ *          where the second-order equilibrium of Eq. feq loses its meaning */
+#define MPF_FLAG_NONFINITE 1u
+#define MPF_FLAG_LIMIT 2u
+
+/* Library context: the HIP device it was created for and the weight solve's
+ * autotune cache (tile shape per stencil size, operator count and solve).
+ * Field memory is never owned by it.  One context per host thread, or calls
+ * on it externally synchronised.  mpf_create makes `hip_device` current on
+ * the calling thread. */
+typedef struct mpf_ctx mpf_ctx;
+int mpf_create(mpf_ctx** out, int hip_device);
+int mpf_destroy(mpf_ctx* ctx);
 
 /* Static description of an error code; never NULL. */
 const char* mpf_strerror(int code);
@@ -174,8 +204,10 @@ int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32_t* sten, i
  *        |dx| <= 1e-15 |x|, or once |dx| <= 1e-9 |x| no longer shrinks 4x per
  *        sweep, the FP64-residual floor; otherwise the row is re-solved in
  *        FP64, info -1).
+ * ctx:   the context whose autotune cache supplies the tile shape when
+ *        tune is NULL; may be NULL (then the default shape).
  * tune:  host pointer to the tile shape, or NULL for the shape that
- *        mpf_weights_autotune last chose for (device, nl, n_ops, solve), or a
+ *        mpf_weights_autotune last stored in ctx for (nl, n_ops, solve), or a
  *        default (4 waves per block, 1 row per wave).
  * The geometry table is copied into ws on the stream, and the call waits for
  * that copy (one stream synchronisation) before it launches the solve. */
@@ -198,16 +230,17 @@ typedef struct {
   int32_t rows_per_wave;   /* 1..64 */
 } mpf_wtune;
 
-int mpf_rbffd_weights_batched(int n_geoms, const mpf_wgeom* geoms_host, int nl, int n_ops, const mpf_op* ops,
-                              int solve, const mpf_wtune* tune, void* ws, size_t ws_bytes, void* stream);
+int mpf_rbffd_weights_batched(mpf_ctx* ctx, int n_geoms, const mpf_wgeom* geoms_host, int nl, int n_ops,
+                              const mpf_op* ops, int solve, const mpf_wtune* tune, void* ws, size_t ws_bytes,
+                              void* stream);
 
 /* Autotuner: times every candidate tile shape (waves per block 1, 2, 4, 8 x
  * rows per wave 1, 2, 4, 8) on the first sample_rows rows of *sample (whose
- * outputs it overwrites), on a
- * private stream, synchronously; stores the fastest in *out and in the
- * library's per-process cache used when mpf_rbffd_weights_batched gets
- * tune = NULL. */
-int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
+ * outputs it overwrites), on a private stream of the context's device,
+ * synchronously; stores the fastest in *out and in ctx's cache, which
+ * mpf_rbffd_weights_batched reads when it gets tune = NULL.  ctx must not be
+ * NULL. */
+int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
                          int64_t sample_rows, mpf_wtune* out, void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------- ACM step
@@ -232,13 +265,24 @@ int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const 
  * sn    dev [nl][nb]; wn dev [nl][nb] normal-derivative weights on sn
  * v     dev [3][n], p dev [n]: state, updated in place (v stays 0 on the
  *       boundary)
+ * comp  dev float [4][n] for MPF_F32_KAHAN (NULL otherwise): the
+ *       compensation terms of v (rows 0-2) and p (row 3), in/out; zero for a
+ *       state given exactly in FP32 (e.g. rest).  The true state is v + comp,
+ *       p + comp[3]; boundary entries stay zero.
  * vmax  dev double [1]: max_i |v_i| of the current state, in/out (0 for a
- *       state at rest); C is derived from it
+ *       state at rest); C is derived from it.  A non-finite |v_i| counts as
+ *       +inf.
+ * flags dev uint32 [1] or NULL: bit 0 when a velocity is not finite, bit 1
+ *       when h_min > 0 and C dt / h_min > 1 at a pressure pass (see the
+ *       flags word above; MPF_ERR_DIVERGED when set at the end of the call)
  * ws    workspace of mpf_acm_workspace() bytes (velocity and v' records
- *       [n][4] and a second pressure [n])
+ *       [n][4], a second pressure [n], and for MPF_F32_KAHAN the
+ *       compensation of v' [n][4])
  * precision: MPF_F64, MPF_F32 (weights and fields FP32, all arithmetic
- * except the max FP32) or MPF_MIXED (weights w, wn FP32; fields v, p and the
- * workspace FP64; FP64 arithmetic).
+ * except the max FP32), MPF_MIXED (weights w, wn FP32; fields v, p and the
+ * workspace FP64; FP64 arithmetic) or MPF_F32_KAHAN (as MPF_F32, and each
+ * interior node's v and p updates are added to hi + lo with an error-free
+ * two-sum, so increments below half an ulp of the FP32 value are kept).
  * lanes: how many adjacent lanes share one node's stencil sum (1, 2, 4, 8 or
  * 16; 0 lets the library pick from n_int and the state's precision: 8 up to
  * 12000 interior nodes, 2 up to 50000, then 1, and 2 again above 500000 for
@@ -257,12 +301,15 @@ typedef struct {
   int32_t precision;
   int32_t lanes;
   int32_t edac;
+  double h_min; /* smallest node spacing, for the Courant check of flags bit 1; 0 = no check */
 } mpf_acm_params;
 
+/* The ACM time step of Sec. 2.3, dt = 0.1 h_min^2 / (2 nu).  Host-only. */
+int mpf_acm_dt(double h_min, double nu, double* dt_host);
 size_t mpf_acm_workspace(int64_t n, int precision);
 int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* w,
-                const int32_t* sn, const void* wn, void* v, void* p, double* vmax, int n_steps, void* ws,
-                size_t ws_bytes, void* stream);
+                const int32_t* sn, const void* wn, void* v, void* p, void* comp, double* vmax, uint32_t* flags,
+                int n_steps, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------- MLBM step
  * Meshless lattice Boltzmann steps with TRT collision (Sec. 2.2, Eqs.
@@ -277,11 +324,21 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  *   bounce-back at boundary node b (Eq. interpolated_bounceback_mlbm): where
  *     bit k of unknown[b] is set, f_k = f_{opp(k)}.
  * W       dev [q-1][nl][n] (population k uses slice k - 1): double for
- *         MPF_F64, float for MPF_F32 and MPF_MIXED
+ *         MPF_F64, float for MPF_F32, MPF_MIXED and MPF_F32_KAHAN
  * unknown dev [nb] uint32 bit masks from mpf_lbm_unknown (nb = n - n_int;
  *         may be NULL when nb = 0)
  * f     dev [n][qp] state, updated in place; f_tmp dev [n][qp] scratch:
- *       double for MPF_F64 and MPF_MIXED, float for MPF_F32
+ *       double for MPF_F64 and MPF_MIXED, float for MPF_F32 and
+ *       MPF_F32_KAHAN
+ * comp  dev float [n][qp] for MPF_F32_KAHAN (NULL otherwise), in/out: the
+ *       compensation of f, so that the state is f + comp (zero for a state
+ *       given exactly in FP32).  In that mode the stencil sums gather the FP32
+ *       records f only, the node's own comp enters its rest population and
+ *       its self column in FP64, and the collision and the split back into
+ *       f and comp run in FP64.
+ * flags dev uint32 [1] or NULL: bit 0 when a collided node has a non-finite
+ *       density or velocity, bit 1 when |u|^2 >= 1/3 there (see the flags
+ *       word above; MPF_ERR_DIVERGED when set at the end of the call)
  * q is 15 or 19.  A W larger than 512 MiB (twice the Infinity Cache) is read
  * with non-temporal loads so that it does not evict the gathered population
  * records; the results are the same bit for bit either way. */
@@ -301,7 +358,20 @@ int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, const double*
 int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const double* v, const double* p, double vel_scale,
                         void* f, void* stream);
 int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* W,
-                const uint32_t* unknown, void* f, void* f_tmp, int n_steps, void* stream);
+                const uint32_t* unknown, void* f, void* f_tmp, void* comp, uint32_t* flags, int n_steps,
+                void* stream);
+/* Lattice units of Sec. 2.2 (Eqs. lbm_viscosity and conversion_factors) for
+ * a cloud of smallest spacing h_min: dx = h_min / 2, nu_lb = (tau+ - 1/2) / 3,
+ * dt = nu_lb dx^2 / nu, g_lb = g dt^2 / dx, vel_scale = dx / dt (physical
+ * velocity per lattice velocity) and tau- = 1/2 + Lambda / (tau+ - 1/2) from
+ * the magic parameter Lambda.  g_host [3]; host-only; MPF_ERR_ARG unless
+ * h_min > 0, nu > 0, tau+ > 1/2 and Lambda > 0. */
+typedef struct {
+  double dx, dt, nu_lb, tau_minus, vel_scale;
+  double g_lb[3];
+} mpf_lbm_units;
+int mpf_lbm_units_of(double h_min, double nu, double tau_plus, double magic, const double* g_host,
+                     mpf_lbm_units* out_host);
 /* Which populations of each boundary node n_int + b are unknown after
  * streaming, as bit masks unknown[b] (bit k for population k, bit 0 never set):
  *   MPF_UNKNOWN_NORMAL (Sec. 2.2): e_k . n_b > 0, with nrm dev [3][nb] double
@@ -331,11 +401,44 @@ int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double 
  * q_out dev double[1].  The sum is a fixed-order FP64 tree, so results are
  * bitwise reproducible. */
 size_t mpf_reduce_workspace(int64_t n_items);
-/* x[i] *= c for i < n; x dev, double (MPF_F64) or float (MPF_F32).  Used to
- * rescale a velocity field to a target flux (the warm start's flux match). */
+/* x[i] *= c for i < n; x dev, double (MPF_F64) or float (MPF_F32 and
+ * MPF_F32_KAHAN; a compensated field scales its comp with a second call).
+ * Used to rescale a velocity field to a target flux (the warm start's flux
+ * match). */
 int mpf_scale(int64_t n, void* x, int precision, double c, void* stream);
 int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx, int precision,
                     int64_t n_all, double* q_out, void* ws, size_t ws_bytes, void* stream);
+/* Permeability from the plane flux, Eq. k_definition: k / d^2 = q nu / (|g| d^2).
+ * K from the drag, Eq. K_definition: K = F_x / (6 pi r phi q mu).  g_host
+ * [3]; host-only; MPF_ERR_ARG for a zero force, d, r, phi, q or mu. */
+int mpf_permeability(double q, double nu, const double* g_host, double d, double* k_host);
+int mpf_drag_coefficient(double Fx, double r, double phi, double q, double mu, double* K_host);
+
+/* Pointwise relative difference of the two solvers' velocity fields on the
+ * same nodes, Eq. pointwise_error of Sec. 3.6 (the cross-validation):
+ *   delta[i] = |va_i - vb_i| / |vb_i|,  dv[i] = |va_i - vb_i|   (i < n)
+ * with Euclidean norms in FP64 (va = MLBM, vb = MNS in the paper); where
+ * |vb_i| = 0, delta is +inf if dv > 0 and 0 if both velocities are zero.
+ * va, vb dev [3][n] of the state types of prec_a / prec_b (float for MPF_F32
+ * and MPF_F32_KAHAN, else double); delta, dv dev double [n] or NULL.
+ * Isocontour statistics: counts[l] = number of nodes i < n_count with
+ * delta[i] > levels_host[l], for l < n_levels <= 16 (counts dev int64
+ * [n_levels], overwritten; exact integer sums).  n_levels = 0 for none. */
+int mpf_pointwise(int64_t n, const void* va, int prec_a, const void* vb, int prec_b, double* delta, double* dv,
+                  int64_t n_count, int n_levels, const double* levels_host, int64_t* counts, void* stream);
+
+/* Residual monitors of the stop control (every check; not in the step):
+ *   out[0] = max_i |v_i - v_prev_i|   over interior nodes (0 if v_prev NULL)
+ *   out[1] = max_i |v_i|              over interior nodes
+ *   out[2] = sqrt(mean_i (div v)_i^2) over interior nodes, with
+ *            (div v)_i = sum_j (wx_ij v_x + wy_ij v_y + wz_ij v_z)(sten_ij)
+ * w dev [>= 3][nl][n] (d/dx, d/dy, d/dz first, as mpf_acm_run takes them):
+ * double for MPF_F64, float otherwise; v, v_prev dev [3][n]: the state type
+ * of precision (float for MPF_F32 and MPF_F32_KAHAN, else double).  A NaN
+ * makes the maxima NaN.  out dev double [3]; ws: mpf_reduce_workspace(n)
+ * bytes.  Fixed-order FP64 sums (bitwise reproducible). */
+int mpf_residual(int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* w, const void* v,
+                 const void* v_prev, int precision, double* out, void* ws, size_t ws_bytes, void* stream);
 
 /* Hydrodynamic force on the grains, Eqs. stress_tensor_force and
  * integration_force: F = dA sum_b (-(p_b - <p>) n_b + rho nu (grad v + grad
@@ -414,7 +517,8 @@ int mpf_mlp_features(int64_t n, const double* pos, double r, double phi, float* 
 /* Network outputs y dev float [n][4] -> solver state: v = U y_{0..2} on the
  * interior nodes [0, n_int) and 0 on the grain (no slip), p = P y_3 minus its
  * node mean (fixed-order FP64 mean).  v dev [3][n], p dev [n], of the state
- * type of precision (float for MPF_F32, else double).  vmax dev double[1] or
+ * type of precision (float for MPF_F32 and MPF_F32_KAHAN, whose comp the
+ * caller zeroes, else double).  vmax dev double[1] or
  * NULL: receives max |v| (the input mpf_acm_run expects).  ws:
  * mpf_reduce_workspace(n) bytes. */
 int mpf_mlp_to_state(int64_t n, int64_t n_int, const float* y, double U, double P, int precision, void* v, void* p,

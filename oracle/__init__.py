@@ -26,7 +26,7 @@ OPS = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shif
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c11", "-shared", "-fPIC",
                                os.path.join(_HERE, "mpf_oracle.c"), "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -65,6 +65,12 @@ def _load():
         lib.mpfo_drag.argtypes = [i64, i32, vp, vp, vp, i64, vp, vp, dbl, dbl, dbl, vp]
         lib.mpfo_traction.restype = None
         lib.mpfo_traction.argtypes = [i64, i32, vp, vp, vp, i64, vp, vp, dbl, dbl, vp, vp]
+        lib.mpfo_set_threads.restype = i32
+        lib.mpfo_set_threads.argtypes = [i32]
+        lib.mpfo_pointwise.restype = None
+        lib.mpfo_pointwise.argtypes = [i64, vp, vp, vp, vp]
+        lib.mpfo_residual.restype = None
+        lib.mpfo_residual.argtypes = [i64, i32, vp, vp, i32, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -347,3 +353,30 @@ def traction(sb, wg, nrm, v, p, rho, nu):
 def drag_coefficient(Fx: float, r: float, phi: float, q: float, mu: float) -> float:
     """K = F_H,0 / (6 pi r phi q mu), Eq. K_definition."""
     return Fx / (6.0 * np.pi * r * phi * q * mu)
+
+
+def residual(n_int, sten, w, v, v_prev=None):
+    """[max |v - v_prev|, max |v|, rms div v] over the interior nodes (see
+    mpfo_residual); w [n][n_ops >= 3][nl] with d/dx, d/dy, d/dz first."""
+    sten, w, v = _c(sten, np.int32), _c(w, np.float64), _c(v, np.float64)
+    vp = None if v_prev is None else _c(v_prev, np.float64)
+    out = np.zeros(3)
+    _load().mpfo_residual(int(n_int), sten.shape[1], sten.ctypes.data, w.ctypes.data, w.shape[1], v.ctypes.data,
+                          None if vp is None else vp.ctypes.data, out.ctypes.data)
+    return out
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the MLBM oracle's node loops (default 1); the results
+    do not depend on it.  Returns the count in effect."""
+    return int(_load().mpfo_set_threads(int(n)))
+
+
+def pointwise(va, vb):
+    """(delta [n], dv [n]): the pointwise relative velocity difference of
+    Eq. pointwise_error, |v_a - v_b| / |v_b| per node (see mpfo_pointwise)."""
+    va, vb = _c(va, np.float64).reshape(-1, 3), _c(vb, np.float64).reshape(-1, 3)
+    n = len(va)
+    delta, dv = np.zeros(n), np.zeros(n)
+    _load().mpfo_pointwise(n, va.ctypes.data, vb.ctypes.data, delta.ctypes.data, dv.ctypes.data)
+    return delta, dv

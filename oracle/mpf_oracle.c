@@ -25,13 +25,28 @@
  * Layouts are the natural row-major ones: positions [N][3], stencils [m][nl],
  * weights [m][n_ops][nl], velocities [N][3], populations [N][q].
  *
- * Build: gcc -O2 -std=c11 -shared -fPIC mpf_oracle.c -o libmpf_oracle.so -lm
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -std=c11 -shared -fPIC mpf_oracle.c
+ *        -o libmpf_oracle.so -lm
+ *
+ * Threads: one by default.  mpfo_set_threads() lets the MLBM node loops run
+ * on several host threads (an OpenMP parallel loop over nodes; every node's
+ * arithmetic is the same in the same order, so results are identical for any
+ * thread count).  It exists only to time the oracle on all host cores.
  */
 #define _DEFAULT_SOURCE /* M_PI */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Host threads of the MLBM node loops (1 unless set); returns the count in
+ * effect. */
+static int g_threads = 1;
+int mpfo_set_threads(int n) {
+  g_threads = n < 1 ? 1 : n;
+  return g_threads;
+}
 
 /* ------------------------------------------------------------------ geometry */
 
@@ -517,7 +532,9 @@ int mpfo_lbm_run(int q, int64_t n, int64_t n_int, int nl, const int32_t* sten, c
   if (mpfo_lattice(q, e, wk, opp)) return -1;
   double* fpost = (double*)malloc(sizeof(double) * q * n);
   for (int step = 0; step < n_steps; ++step) {
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < n; ++i) collide(q, e, wk, opp, tau_p, tau_m, g_lb, f + i * q, fpost + i * q);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < n; ++i) {
       const int32_t* S = sten + i * nl;
       f[i * q] = fpost[i * q];
@@ -602,4 +619,57 @@ void mpfo_drag(int64_t nb, int nl, const int32_t* sb, const double* wg, const do
     for (int i = 0; i < 3; ++i) acc[i] += t[3 * b + i];
   for (int i = 0; i < 3; ++i) F[i] = dA * acc[i];
   free(t);
+}
+
+/* ------------------------------------------------------------------ stop control */
+
+/* Residual monitors of the stop control (the quantities a run reads at its
+ * checks besides k, Eq. stopCrit): over the interior nodes i < n_int,
+ *   out[0] = max_i |v_i - vprev_i| (0 when vprev is NULL),
+ *   out[1] = max_i |v_i|,
+ *   out[2] = sqrt(mean_i (div v)_i^2), (div v)_i = sum_j w^x_ij v_x(S_ij)
+ *            + w^y_ij v_y(S_ij) + w^z_ij v_z(S_ij)  (the divergence of Eq.
+ *            MNS_pressure).
+ * w [n][n_ops >= 3][nl] with d/dx, d/dy, d/dz first; v, vprev [n][3]. */
+void mpfo_residual(int64_t n_int, int nl, const int32_t* sten, const double* w, int n_ops, const double* v,
+                   const double* vprev, double* out) {
+  double dmax = 0.0, vmax = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < n_int; ++i) {
+    const double* vi = v + 3 * i;
+    double m = sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+    if (m > vmax) vmax = m;
+    if (vprev) {
+      const double* pi = vprev + 3 * i;
+      double e0 = vi[0] - pi[0], e1 = vi[1] - pi[1], e2 = vi[2] - pi[2];
+      double d = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+      if (d > dmax) dmax = d;
+    }
+    double div = 0.0;
+    for (int j = 0; j < nl; ++j) {
+      const double* u = v + 3 * (int64_t)sten[i * nl + j];
+      for (int a = 0; a < 3; ++a) div += w[(i * n_ops + a) * nl + j] * u[a];
+    }
+    s2 += div * div;
+  }
+  out[0] = dmax;
+  out[1] = vmax;
+  out[2] = n_int > 0 ? sqrt(s2 / (double)n_int) : 0.0;
+}
+
+/* ------------------------------------------------------------------ cross-validation */
+
+/* Pointwise relative difference of two velocity fields on the same nodes,
+ * Eq. pointwise_error of Sec. 3.6: delta_i = |v_a,i - v_b,i| / |v_b,i| with
+ * the Euclidean norm (a = MLBM, b = MNS in the paper), and dv_i = |v_a,i -
+ * v_b,i|.  Where |v_b,i| = 0 the quotient is +inf if dv_i > 0 and 0 if the two
+ * velocities are both zero (the no-slip grain).  v_a, v_b [n][3]; delta, dv
+ * [n]. */
+void mpfo_pointwise(int64_t n, const double* va, const double* vb, double* delta, double* dv) {
+  for (int64_t i = 0; i < n; ++i) {
+    double d0 = va[3 * i] - vb[3 * i], d1 = va[3 * i + 1] - vb[3 * i + 1], d2 = va[3 * i + 2] - vb[3 * i + 2];
+    double num = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    double den = sqrt(vb[3 * i] * vb[3 * i] + vb[3 * i + 1] * vb[3 * i + 1] + vb[3 * i + 2] * vb[3 * i + 2]);
+    dv[i] = num;
+    delta[i] = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+  }
 }

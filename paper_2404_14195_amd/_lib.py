@@ -14,7 +14,9 @@ _INC = os.path.join(os.path.dirname(_HERE), "include")
 SO_PATH = os.path.join(_HERE, "libmpf.so")
 SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip", "knn.hip"]
 
-MPF_F64, MPF_F32, MPF_MIXED = 0, 1, 2
+MPF_F64, MPF_F32, MPF_MIXED, MPF_F32_KAHAN = 0, 1, 2, 3
+MPF_ERR_DIVERGED = -4
+MPF_FLAG_NONFINITE, MPF_FLAG_LIMIT = 1, 2
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
 OP = {"dx": 0, "dy": 1, "dz": 2, "lap": 3, "dir": 4, "shift": 5, "dn": 6, "shift_row": 7, "taylor": 8}
 UNKNOWN_RULE = {"normal": 0, "solid": 1}
@@ -22,6 +24,10 @@ UNKNOWN_RULE = {"normal": 0, "solid": 1}
 
 class MPFError(RuntimeError):
     pass
+
+
+class MPFDiverged(MPFError, FloatingPointError):
+    """A run's flags word was set: a non-finite state or a stability limit."""
 
 
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
@@ -72,12 +78,17 @@ class AcmParams(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("rho", ctypes.c_double), ("dt", ctypes.c_double),
                 ("beta", ctypes.c_double), ("v_ref", ctypes.c_double), ("g", ctypes.c_double * 3),
                 ("n_p", ctypes.c_int32), ("precision", ctypes.c_int32), ("lanes", ctypes.c_int32),
-                ("edac", ctypes.c_int32)]
+                ("edac", ctypes.c_int32), ("h_min", ctypes.c_double)]
 
 
 class LbmParams(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("precision", ctypes.c_int32), ("tau_plus", ctypes.c_double),
                 ("tau_minus", ctypes.c_double), ("g_lb", ctypes.c_double * 3)]
+
+
+class LbmUnits(ctypes.Structure):
+    _fields_ = [("dx", ctypes.c_double), ("dt", ctypes.c_double), ("nu_lb", ctypes.c_double),
+                ("tau_minus", ctypes.c_double), ("vel_scale", ctypes.c_double), ("g_lb", ctypes.c_double * 3)]
 
 
 def _load():
@@ -92,13 +103,22 @@ def _load():
         "mpf_sc_cell": (i32, [dbl, vp, vp]),
         "mpf_weights_workspace": (sz, []),
         "mpf_rbffd_weights": (i32, [vp, i64, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
-        "mpf_rbffd_weights_batched": (i32, [i32, vp, i32, i32, vp, i32, vp, vp, sz, vp]),
-        "mpf_weights_autotune": (i32, [i32, i32, vp, i32, vp, i64, vp, vp, sz]),
+        "mpf_create": (i32, [vp, i32]),
+        "mpf_destroy": (i32, [vp]),
+        "mpf_rbffd_weights_batched": (i32, [vp, i32, vp, i32, i32, vp, i32, vp, vp, sz, vp]),
+        "mpf_weights_autotune": (i32, [vp, i32, i32, vp, i32, vp, i64, vp, vp, sz]),
+        "mpf_acm_dt": (i32, [dbl, dbl, vp]),
         "mpf_acm_workspace": (sz, [i64, i32]),
-        "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
+        "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
         "mpf_lbm_init": (i32, [vp, i64, dbl, vp, vp, vp]),
         "mpf_lbm_init_fields": (i32, [vp, i64, vp, vp, dbl, vp, vp]),
-        "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, i32, vp]),
+        "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
+        "mpf_lbm_units_of": (i32, [dbl, dbl, dbl, dbl, vp, vp]),
+        "mpf_permeability": (i32, [dbl, dbl, vp, dbl, vp]),
+        "mpf_drag_coefficient": (i32, [dbl, dbl, dbl, dbl, dbl, vp]),
+        "mpf_residual": (i32, [i64, i64, i32, vp, vp, vp, vp, i32, vp, vp, sz, vp]),
+        "mpf_pointwise": (i32, [i64, vp, i32, vp, i32, vp, vp, i64, i32, vp, vp, vp]),
+
         "mpf_lbm_unknown": (i32, [i32, i64, i64, vp, vp, i32, dbl, dbl, vp, vp]),
         "mpf_knn_workspace": (ctypes.c_size_t, [i64]),
         "mpf_knn": (i32, [vp, i64, i64, vp, i64, i64, i32, vp, i64, vp, ctypes.c_size_t, vp]),
@@ -143,7 +163,9 @@ def lib():
     return _LIB
 
 
-EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
+EXPORTED = ["mpf_strerror", "mpf_version", "mpf_create", "mpf_destroy", "mpf_acm_dt", "mpf_lbm_units_of",
+            "mpf_permeability", "mpf_drag_coefficient", "mpf_residual", "mpf_pointwise",
+            "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",
             "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_unknown", "mpf_lbm_moments",
             "mpf_knn_workspace", "mpf_knn", "mpf_solver_stencils", "mpf_reduce_workspace",
@@ -155,7 +177,25 @@ EXPORTED = ["mpf_strerror", "mpf_version", "mpf_sc_cell", "mpf_weights_workspace
 
 def check(rc: int, what: str):
     if rc != 0:
-        raise MPFError(f"{what}: {lib().mpf_strerror(rc).decode()} ({rc})")
+        cls = MPFDiverged if rc == MPF_ERR_DIVERGED else MPFError
+        raise cls(f"{what}: {lib().mpf_strerror(rc).decode()} ({rc})")
+
+
+_CTX = {}
+
+
+def ctx(device: int | None = None) -> ctypes.c_void_p:
+    """The library context of a HIP device (default: the current one),
+    created on first use and kept for the life of the process; it holds the
+    weight solve's autotune cache."""
+    if device is None:
+        import torch
+        device = torch.cuda.current_device()
+    if device not in _CTX:
+        c = ctypes.c_void_p()
+        check(lib().mpf_create(ctypes.byref(c), int(device)), "mpf_create")
+        _CTX[device] = c
+    return _CTX[device]
 
 
 def make_ops(ops):

@@ -8,11 +8,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import MPF_F32, MPF_F64, MPF_MIXED, AcmParams, LbmParams, WGeom, WTune, check, lib, make_ops
+from ._lib import (MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, AcmParams, LbmParams, LbmUnits, WGeom, WTune, check,
+                   ctx, lib, make_ops)
 
 # element type of the state (fields, populations) and of the stencil weights
-_ST = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64}
-_WT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float32}
+_ST = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64, MPF_F32_KAHAN: torch.float32}
+_WT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float32, MPF_F32_KAHAN: torch.float32}
 
 
 def _stream():
@@ -134,7 +135,7 @@ def rbffd_weights_batched(clouds, ops, solve=0, want64=True, want32=False, tune=
     t = None
     if tune is not None:
         t = WTune(waves_per_block=tune[0], rows_per_wave=tune[1])
-    check(lib().mpf_rbffd_weights_batched(len(clouds), geoms, nl, len(ops), make_ops(ops), int(solve),
+    check(lib().mpf_rbffd_weights_batched(ctx(), len(clouds), geoms, nl, len(ops), make_ops(ops), int(solve),
                                           None if t is None else ctypes.byref(t), _p(ws), ws.numel(), _stream()),
           "mpf_rbffd_weights_batched")
     return out
@@ -142,7 +143,7 @@ def rbffd_weights_batched(clouds, ops, solve=0, want64=True, want32=False, tune=
 
 def weights_autotune(pos, sten, ops, solve=0, sample_rows=16384, rowvec=None):
     """Time the candidate tile shapes on the first sample_rows rows; returns
-    (waves_per_block, rows_per_wave) and caches it in the library."""
+    (waves_per_block, rows_per_wave) and caches it in the device's context."""
     nl, m = sten.shape
     k = min(m, sample_rows)
     w64 = torch.empty((len(ops), nl, m), dtype=torch.float64, device=pos.device)
@@ -151,7 +152,7 @@ def weights_autotune(pos, sten, ops, solve=0, sample_rows=16384, rowvec=None):
     ws = weights_workspace(pos.device)
     t = WTune()
     torch.cuda.synchronize()
-    check(lib().mpf_weights_autotune(nl, len(ops), make_ops(ops), int(solve), ctypes.byref(g), k, ctypes.byref(t),
+    check(lib().mpf_weights_autotune(ctx(), nl, len(ops), make_ops(ops), int(solve), ctypes.byref(g), k, ctypes.byref(t),
                                      _p(ws), ws.numel()), "mpf_weights_autotune")
     return t.waves_per_block, t.rows_per_wave
 
@@ -161,7 +162,16 @@ def acm_workspace(n: int, precision: int, device) -> torch.Tensor:
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: int, ws=None):
+def acm_dt(h_min: float, nu: float) -> float:
+    """The ACM time step of Sec. 2.3, from the library."""
+    out = ctypes.c_double()
+    check(lib().mpf_acm_dt(float(h_min), float(nu), ctypes.byref(out)), "mpf_acm_dt")
+    return out.value
+
+
+def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: int, ws=None, comp=None, flags=None):
+    """comp: [4][n] float32 for MPF_F32_KAHAN; flags: [1] int32 (the uint32
+    word), or None for a call without the end-of-call check."""
     prec = prm.precision
     dt, dw = _ST[prec], _WT[prec]
     nl, n = sten.shape
@@ -172,10 +182,14 @@ def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: in
     if n > n_int:
         _need(wn, dw, (nl, n - n_int), "wn")
         _need(sn, torch.int32, (nl, n - n_int), "sn")
+    if comp is not None:
+        _need(comp, torch.float32, (4, n), "comp")
+    if flags is not None:
+        _need(flags, torch.int32, (1,), "flags")
     if ws is None:
         ws = acm_workspace(n, prec, v.device)
-    check(lib().mpf_acm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(w), _p(sn), _p(wn), _p(v), _p(p), _p(vmax),
-                          int(n_steps), _p(ws), ws.numel(), _stream()), "mpf_acm_run")
+    check(lib().mpf_acm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(w), _p(sn), _p(wn), _p(v), _p(p), _p(comp),
+                            _p(vmax), _p(flags), int(n_steps), _p(ws), ws.numel(), _stream()), "mpf_acm_run")
 
 
 def record_len(q: int) -> int:
@@ -201,8 +215,19 @@ def lbm_init_fields(prm: LbmParams, f, v, p, vel_scale: float):
           "mpf_lbm_init_fields")
 
 
-def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int):
-    """unknown: [n - n_int] int32 bit masks from lbm_unknown."""
+def lbm_units(h_min: float, nu: float, tau_plus: float, g, magic: float) -> dict:
+    """Lattice units of Sec. 2.2 (Eq. conversion_factors), from the library."""
+    out = LbmUnits()
+    gg = (ctypes.c_double * 3)(*[float(x) for x in g])
+    check(lib().mpf_lbm_units_of(float(h_min), float(nu), float(tau_plus), float(magic), gg, ctypes.byref(out)),
+          "mpf_lbm_units_of")
+    return dict(dx=out.dx, dt=out.dt, nu_lb=out.nu_lb, g_lb=list(out.g_lb), tau_minus=out.tau_minus,
+                vel_scale=out.vel_scale)
+
+
+def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int, comp=None, flags=None):
+    """unknown: [n - n_int] int32 bit masks from lbm_unknown; comp: [n][qp]
+    float32 for MPF_F32_KAHAN; flags: [1] int32 or None."""
     dt = _ST[prm.precision]
     nl, n = sten.shape
     _need(W, _WT[prm.precision], (prm.q - 1, nl, n), "W")
@@ -210,8 +235,12 @@ def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int
     _need(f_tmp, dt, (n, record_len(prm.q)), "f_tmp")
     if n > n_int:
         _need(unknown, torch.int32, (n - n_int,), "unknown")
+    if comp is not None:
+        _need(comp, torch.float32, (n, record_len(prm.q)), "comp")
+    if flags is not None:
+        _need(flags, torch.int32, (1,), "flags")
     check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(unknown), _p(f), _p(f_tmp),
-                            int(n_steps), _stream()), "mpf_lbm_run")
+                            _p(comp), _p(flags), int(n_steps), _stream()), "mpf_lbm_run")
 
 
 def lbm_unknown(q: int, pos, n_int: int, nrm=None, rule: str = "normal", dx: float = 0.0, r: float = 0.0):
@@ -253,6 +282,61 @@ def flux_planes(s_idx, s_w, vx, n_all: int, q_out=None, ws=None):
     check(lib().mpf_flux_planes(ns, nl, _p(s_idx), _p(s_w), _p(vx), precision_of(vx.dtype), int(n_all), _p(q_out),
                               _p(ws), ws.numel(), _stream()), "mpf_flux_planes")
     return q_out
+
+
+def pointwise(va, vb, n_count=None, levels=(), delta=None, dv=None):
+    """Eq. pointwise_error on the device: (delta [n], dv [n], counts) with
+    counts[l] the number of the first n_count nodes (default all) whose delta
+    exceeds levels[l] (host ints).  va, vb [3][n] float32 or float64."""
+    n = va.shape[1]
+    for t, name in ((va, "va"), (vb, "vb")):
+        if t.dim() != 2 or t.shape[0] != 3 or t.shape[1] != n:
+            raise ValueError(f"{name} must be [3][n]")
+    delta = torch.empty(n, dtype=torch.float64, device=va.device) if delta is None else delta
+    dv = torch.empty(n, dtype=torch.float64, device=va.device) if dv is None else dv
+    _need(delta, torch.float64, (n,), "delta")
+    _need(dv, torch.float64, (n,), "dv")
+    lv = (ctypes.c_double * max(1, len(levels)))(*[float(x) for x in levels])
+    counts = torch.empty(max(1, len(levels)), dtype=torch.int64, device=va.device)
+    check(lib().mpf_pointwise(n, _p(va), precision_of(va.dtype), _p(vb), precision_of(vb.dtype), _p(delta), _p(dv),
+                              n if n_count is None else int(n_count), len(levels), lv, _p(counts), _stream()),
+          "mpf_pointwise")
+    return delta, dv, [int(x) for x in counts.cpu().tolist()[:len(levels)]]
+
+
+def permeability(q: float, nu: float, g, d: float = 1.0) -> float:
+    """k / d^2 = q nu / (|g| d^2), Eq. k_definition, from the library."""
+    out = ctypes.c_double()
+    gg = (ctypes.c_double * 3)(*[float(x) for x in g])
+    check(lib().mpf_permeability(float(q), float(nu), gg, float(d), ctypes.byref(out)), "mpf_permeability")
+    return out.value
+
+
+def drag_coefficient(Fx: float, r: float, phi: float, q: float, mu: float) -> float:
+    """K = F_x / (6 pi r phi q mu), Eq. K_definition, from the library."""
+    out = ctypes.c_double()
+    check(lib().mpf_drag_coefficient(float(Fx), float(r), float(phi), float(q), float(mu), ctypes.byref(out)),
+          "mpf_drag_coefficient")
+    return out.value
+
+
+def residual(sten, w, v, n_int: int, v_prev=None, precision=None, out=None, ws=None):
+    """[max |v - v_prev|, max |v|, rms div v] over the interior nodes
+    (device double [3]); w [>=3][nl][n] holds d/dx, d/dy, d/dz first."""
+    nl, n = sten.shape
+    if precision is None:
+        precision = MPF_F64 if w.dtype == torch.float64 else (MPF_F32 if v.dtype == torch.float32 else MPF_MIXED)
+    _need(w, _WT[precision], name="w")
+    _need(v, _ST[precision], (3, n), "v")
+    if w.dim() != 3 or w.shape[0] < 3 or tuple(w.shape[1:]) != (nl, n):
+        raise ValueError("w must be [>=3][nl][n]")
+    if v_prev is not None:
+        _need(v_prev, _ST[precision], (3, n), "v_prev")
+    out = torch.empty(3, dtype=torch.float64, device=v.device) if out is None else out
+    ws = reduce_workspace(n, v.device) if ws is None else ws
+    check(lib().mpf_residual(n, int(n_int), nl, _p(sten), _p(w), _p(v), _p(v_prev), int(precision), _p(out), _p(ws),
+                             ws.numel(), _stream()), "mpf_residual")
+    return out
 
 
 def drag(v, p, sb, wg, nrm, rho: float, nu: float, dA: float, F_out=None, ws=None):

@@ -19,6 +19,15 @@
 // (device double, updated with an integer atomicMax on the bit pattern, which
 // orders non-negative doubles), so no host round trip enters a step.
 //
+// Compensated FP32 state (MPF_F32_KAHAN): every interior value carries an
+// FP32 compensation term (v and v' as records [n][4] beside the value
+// records, p as a plain array), gathered by nobody but its own node.  The
+// predictor adds dt R to v_hi + v_lo, the pressure pass -coef div v to
+// p_hi + p_lo, the velocity pass -dt/rho grad p to v'_hi + v'_lo, each with
+// the error-free two-sum of Knuth, so that an increment below half an ulp of
+// the FP32 value moves lo instead of vanishing; the stencil sums themselves
+// read the FP32 values only, as in MPF_F32.
+//
 // Each node's stencil sum is split over LPN adjacent lanes (lane sl takes
 // columns sl, sl + LPN, ...) and closed with a fixed butterfly, which shortens
 // the chain of dependent gathers per lane.  One launch per pass: measured on
@@ -112,12 +121,25 @@ struct Fields {
   T* p;         // [n] the caller's pressure
   T* P1;        // [n] second pressure buffer (damped pressure equation only)
   T* VP;        // [n][4] v' records
+  T* VL;        // [n][4] compensation of V (compensated state only, else null)
+  T* VPL;       // [n][4] compensation of VP
+  T* PL;        // [n] compensation of p (the caller's comp row 3)
   double* vmax;
+  uint32_t* flags;  // or null
   T nu, dt, dt_rho, g0, g1, g2;
   double dtd, rho, beta, v_ref;
+  double dt_h;  // dt / h_min for the Courant check, 0 for none
 };
 
-template <typename T, typename TW, int LPN, int NLC>
+// Knuth's two-sum: s + e == a + b exactly, s = fl(a + b).  Only additions, so
+// no contraction into fused multiply-adds can change it.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i, int sl) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   const int64_t n = F.n, os = (int64_t)nl * n;
@@ -149,16 +171,28 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
     const T vi[3] = {ri.x, ri.y, ri.z};
     const T g[3] = {F.g0, F.g1, F.g2};
     T out[3];
+    if constexpr (KAHAN) {
+      const auto rl = load4(F.VL, i);
+      const T lo[3] = {rl.x, rl.y, rl.z};
+      T ol[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T adv = vi[0] * d[a][0] + vi[1] * d[a][1] + vi[2] * d[a][2];
-      out[a] = vi[a] + F.dt * (F.nu * d[a][3] - adv + g[a]);
+      for (int a = 0; a < 3; ++a) {
+        const T adv = vi[0] * d[a][0] + vi[1] * d[a][1] + vi[2] * d[a][2];
+        two_sum(vi[a], lo[a] + F.dt * (F.nu * d[a][3] - adv + g[a]), out[a], ol[a]);
+      }
+      store4(F.VPL, i, ol[0], ol[1], ol[2]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T adv = vi[0] * d[a][0] + vi[1] * d[a][1] + vi[2] * d[a][2];
+        out[a] = vi[a] + F.dt * (F.nu * d[a][3] - adv + g[a]);
+      }
     }
     store4(F.VP, i, out[0], out[1], out[2]);
   }
 }
 
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* __restrict__ vsrc,
                                               const T* pin, T* pout, T coef, int64_t i, int sl) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
@@ -170,11 +204,19 @@ __device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* _
     div += (T)F.w[at] * r.x + (T)F.w[os + at] * r.y + (T)F.w[2 * os + at] * r.z;
   });
   div = group_sum<LPN>(div);
-  if (sl == 0) pout[i] = pin[i] - coef * div;  // in place (pin == pout) for the plain method
+  if (sl != 0) return;
+  if constexpr (KAHAN) {
+    T hi, lo;
+    two_sum(pin[i], F.PL[i] - coef * div, hi, lo);
+    pout[i] = hi;
+    F.PL[i] = lo;
+  } else {
+    pout[i] = pin[i] - coef * div;  // in place (pin == pout) for the plain method
+  }
 }
 
 // The damped pressure equation: p_new = p - coef div v - dt v_i . grad p + dt nu lap p.
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __device__ __forceinline__ void pressure_edac_node(const Fields<T, TW>& F, const T* __restrict__ vsrc,
                                                    const T* __restrict__ pin, T* __restrict__ pout, T coef,
                                                    int64_t i, int sl) {
@@ -201,7 +243,14 @@ __device__ __forceinline__ void pressure_edac_node(const Fields<T, TW>& F, const
   if (sl == 0) {
     const auto ri = load4(vsrc, i);
     const T adv = ri.x * gx + ri.y * gy + ri.z * gz;
-    pout[i] = pin[i] - coef * div + F.dt * (F.nu * lp - adv);
+    if constexpr (KAHAN) {
+      T hi, lo;
+      two_sum(pin[i], F.PL[i] - coef * div + F.dt * (F.nu * lp - adv), hi, lo);
+      pout[i] = hi;
+      F.PL[i] = lo;
+    } else {
+      pout[i] = pin[i] - coef * div + F.dt * (F.nu * lp - adv);
+    }
   }
 }
 
@@ -218,7 +267,7 @@ __device__ __forceinline__ void neumann_node(const Fields<T, TW>& F, T* P, int64
 }
 
 // returns |v_i| (valid in every lane of the node's group)
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, const T* __restrict__ P, int64_t i,
                                                 int sl) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
@@ -235,25 +284,45 @@ __device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, const T*
   const auto rp = load4(F.VP, i);
   const T vpi[3] = {rp.x, rp.y, rp.z};
   T va[3];
+  if constexpr (KAHAN) {
+    const auto rl = load4(F.VPL, i);
+    const T lo[3] = {rl.x, rl.y, rl.z};
+    T vl[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    gp[a] = group_sum<LPN>(gp[a]);
-    va[a] = vpi[a] - F.dt_rho * gp[a];
-    m2 += (double)va[a] * (double)va[a];
+    for (int a = 0; a < 3; ++a) {
+      gp[a] = group_sum<LPN>(gp[a]);
+      two_sum(vpi[a], lo[a] - F.dt_rho * gp[a], va[a], vl[a]);
+      m2 += (double)va[a] * (double)va[a];
+    }
+    if (sl == 0) store4(F.VL, i, vl[0], vl[1], vl[2]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gp[a] = group_sum<LPN>(gp[a]);
+      va[a] = vpi[a] - F.dt_rho * gp[a];
+      m2 += (double)va[a] * (double)va[a];
+    }
   }
   if (sl == 0) store4(F.V, i, va[0], va[1], va[2]);
   return sqrt(m2);
 }
 
+// C from the running max; the first thread of the launch also raises flags
+// bit 1 when the pressure waves' Courant number C dt / h_min exceeds 1.
 template <typename T, typename TW>
 __device__ __forceinline__ T coupling_coef(const Fields<T, TW>& F) {
   const double vm = *F.vmax;
   const double C = F.beta * (vm > F.v_ref ? vm : F.v_ref);
+  if (F.flags && F.dt_h > 0.0 && blockIdx.x == 0 && threadIdx.x == 0 && C * F.dt_h > 1.0)
+    atomicOr(F.flags, MPF_FLAG_LIMIT);
   return (T)(F.dtd * (C * C) * F.rho);
 }
 
 // Block max of |v| into the running max (exact, so any order gives the same).
-__device__ __forceinline__ void block_max_into(double mag, double* lds, double* vmax) {
+// A NaN magnitude is taken as +inf before the reduction (fmax would drop it),
+// so a non-finite state always shows up as C = inf, and as flags bit 0.
+__device__ __forceinline__ void block_max_into(double mag, double* lds, double* vmax, uint32_t* flags) {
+  if (!(mag <= __builtin_huge_val())) mag = __builtin_huge_val();
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mag = fmax(mag, __shfl_xor(mag, off));
   if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x / kWave] = mag;
@@ -261,7 +330,7 @@ __device__ __forceinline__ void block_max_into(double mag, double* lds, double* 
   if (threadIdx.x == 0) {
     double m = lds[0];
     for (int t = 1; t < (int)(blockDim.x / kWave); ++t) m = fmax(m, lds[t]);
-    if (m != m) m = __builtin_inf();  // a non-finite state shows up as C = inf
+    if (flags && !(m < __builtin_huge_val())) atomicOr(flags, MPF_FLAG_NONFINITE);
     atomicMax(reinterpret_cast<unsigned long long*>(vmax), (unsigned long long)__double_as_longlong(m));
   }
   __syncthreads();
@@ -269,29 +338,31 @@ __device__ __forceinline__ void block_max_into(double mag, double* lds, double* 
 
 // ---------------------------------------------------------------- one launch per pass
 
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_predictor(Fields<T, TW> F) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;  // whole LPN groups exit together
-  predictor_node<T, TW, LPN, NLC>(F, i, (int)(g % LPN));
+  predictor_node<T, TW, LPN, NLC, KAHAN>(F, i, (int)(g % LPN));
 }
 
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_pressure(Fields<T, TW> F, const T* __restrict__ vsrc, T* P) {
+  const T coef = coupling_coef(F);
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_node<T, TW, LPN, NLC>(F, vsrc, P, P, coupling_coef(F), i, (int)(g % LPN));
+  pressure_node<T, TW, LPN, NLC, KAHAN>(F, vsrc, P, P, coef, i, (int)(g % LPN));
 }
 
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_pressure_edac(Fields<T, TW> F, const T* __restrict__ vsrc,
                                                           const T* __restrict__ pin, T* __restrict__ pout) {
+  const T coef = coupling_coef(F);
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_edac_node<T, TW, LPN, NLC>(F, vsrc, pin, pout, coupling_coef(F), i, (int)(g % LPN));
+  pressure_edac_node<T, TW, LPN, NLC, KAHAN>(F, vsrc, pin, pout, coef, i, (int)(g % LPN));
 }
 
 template <typename T, typename TW, int LPN, int NLC>
@@ -303,14 +374,14 @@ __global__ __launch_bounds__(kBlock) void k_neumann(Fields<T, TW> F, T* P) {
   neumann_node<T, TW, LPN, NLC>(F, P, b, (int)(g % LPN));
 }
 
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F, const T* __restrict__ P) {
   __shared__ double red[kBlock / kWave];
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   double mag = 0.0;
-  if (i < F.n_int) mag = velocity_node<T, TW, LPN, NLC>(F, P, i, (int)(g % LPN));
-  block_max_into(mag, red, F.vmax);
+  if (i < F.n_int) mag = velocity_node<T, TW, LPN, NLC, KAHAN>(F, P, i, (int)(g % LPN));
+  block_max_into(mag, red, F.vmax, F.flags);
 }
 
 template <typename T>
@@ -342,24 +413,24 @@ int default_lanes(int64_t n_int) {
   return 1;
 }
 
-template <typename T, typename TW, int LPN, int NLC>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 int run_launches(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   T* cur = F.p;  // the pressure of the current iteration (alternates with F.P1 when damped)
   for (int s = 0; s < n_steps; ++s) {
-    hipLaunchKernelGGL((k_predictor<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F);
+    hipLaunchKernelGGL((k_predictor<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), 0, st, F);
     for (int it = 0; it < n_p; ++it) {
       const T* vsrc = it == 0 ? F.VP : F.V;
       if (edac) {
         T* nxt = cur == F.p ? F.P1 : F.p;
-        hipLaunchKernelGGL((k_pressure_edac<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, vsrc,
+        hipLaunchKernelGGL((k_pressure_edac<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), 0, st, F, vsrc,
                            (const T*)cur, nxt);
         cur = nxt;
       } else {
-        hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, vsrc, cur);
+        hipLaunchKernelGGL((k_pressure<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), 0, st, F, vsrc, cur);
       }
       hipLaunchKernelGGL((k_neumann<T, TW, LPN, NLC>), dim3(gb), dim3(kBlock), 0, st, F, cur);
-      hipLaunchKernelGGL((k_velocity<T, TW, LPN, NLC>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)cur);
+      hipLaunchKernelGGL((k_velocity<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), 0, st, F, (const T*)cur);
     }
   }
   if (cur != F.p)
@@ -371,44 +442,66 @@ int run_launches(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t 
 // stencils of 30 nodes (the measured size) and of 25 (the paper's choice in
 // its convergence study) get fully unrolled column loops, which lets every
 // lane issue all its index, weight and gather loads early
-template <typename T, typename TW, int LPN>
+template <typename T, typename TW, int LPN, bool KAHAN>
 int launch_nl(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
-  if (F.nl == 30) return run_launches<T, TW, LPN, 30>(F, n_steps, n_p, edac, st);
-  if (F.nl == 25) return run_launches<T, TW, LPN, 25>(F, n_steps, n_p, edac, st);
-  return run_launches<T, TW, LPN, 0>(F, n_steps, n_p, edac, st);
+  if (F.nl == 30) return run_launches<T, TW, LPN, 30, KAHAN>(F, n_steps, n_p, edac, st);
+  if (F.nl == 25) return run_launches<T, TW, LPN, 25, KAHAN>(F, n_steps, n_p, edac, st);
+  return run_launches<T, TW, LPN, 0, KAHAN>(F, n_steps, n_p, edac, st);
 }
 
+template <typename T, typename TW, bool KAHAN>
+int launch_lanes(Fields<T, TW>& F, int lanes, int n_steps, int n_p, bool edac, hipStream_t st) {
+  switch (lanes) {
+    case 1: return launch_nl<T, TW, 1, KAHAN>(F, n_steps, n_p, edac, st);
+    case 2: return launch_nl<T, TW, 2, KAHAN>(F, n_steps, n_p, edac, st);
+    case 4: return launch_nl<T, TW, 4, KAHAN>(F, n_steps, n_p, edac, st);
+    case 8: return launch_nl<T, TW, 8, KAHAN>(F, n_steps, n_p, edac, st);
+    default: return launch_nl<T, TW, 16, KAHAN>(F, n_steps, n_p, edac, st);
+  }
+}
+
+// comp (compensated state only): [4][n] floats, v_lo rows 0-2 and p_lo row 3
 template <typename T, typename TW>
 int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* w,
-        const int32_t* sn, const TW* wn, T* v, T* p, double* vmax, int n_steps, void* ws, hipStream_t st) {
+        const int32_t* sn, const TW* wn, T* v, T* p, T* comp, double* vmax, uint32_t* flags, int n_steps, void* ws,
+        hipStream_t st) {
   Fields<T, TW> F;
   F.n = n; F.n_int = n_int; F.nb = n - n_int; F.nl = nl;
   F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.p = p;
   F.V = reinterpret_cast<T*>(ws);
   F.VP = F.V + 4 * n;
   F.P1 = F.VP + 4 * n;
+  F.VL = comp ? F.P1 + n : nullptr;
+  F.VPL = comp ? F.VL + 4 * n : nullptr;
+  F.PL = comp ? comp + 3 * n : nullptr;
   F.vmax = vmax;
+  F.flags = flags;
   F.nu = (T)prm->nu; F.dt = (T)prm->dt; F.dt_rho = (T)(prm->dt / prm->rho);
   F.g0 = (T)prm->g[0]; F.g1 = (T)prm->g[1]; F.g2 = (T)prm->g[2];
   F.dtd = prm->dt; F.rho = prm->rho; F.beta = prm->beta; F.v_ref = prm->v_ref;
+  F.dt_h = prm->h_min > 0.0 ? prm->dt / prm->h_min : 0.0;
   // the run works on node records: v [3][n] -> V [n][4] now and back at the
-  // end; v' is zero on the boundary for the whole run
+  // end (likewise the compensation of v); v' is zero on the boundary for the
+  // whole run
   const unsigned gn = grid_for(n, kBlock);
   hipLaunchKernelGGL(to_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)v, F.V);
   hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(4 * n, kBlock)), dim3(kBlock), 0, st, F.VP, 4 * n);
+  if (comp) {
+    hipLaunchKernelGGL(to_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)comp, F.VL);
+    hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(4 * n, kBlock)), dim3(kBlock), 0, st, F.VPL, 4 * n);
+  }
   const bool edac = prm->edac != 0;
   int lanes = prm->lanes;
   if (lanes == 0) lanes = default_lanes<T>(n_int);
   int rc;
-  switch (lanes) {
-    case 1: rc = launch_nl<T, TW, 1>(F, n_steps, prm->n_p, edac, st); break;
-    case 2: rc = launch_nl<T, TW, 2>(F, n_steps, prm->n_p, edac, st); break;
-    case 4: rc = launch_nl<T, TW, 4>(F, n_steps, prm->n_p, edac, st); break;
-    case 8: rc = launch_nl<T, TW, 8>(F, n_steps, prm->n_p, edac, st); break;
-    default: rc = launch_nl<T, TW, 16>(F, n_steps, prm->n_p, edac, st); break;
-  }
+  if constexpr (sizeof(T) == sizeof(float))  // the compensated state is FP32
+    rc = comp ? launch_lanes<T, TW, true>(F, lanes, n_steps, prm->n_p, edac, st)
+              : launch_lanes<T, TW, false>(F, lanes, n_steps, prm->n_p, edac, st);
+  else
+    rc = launch_lanes<T, TW, false>(F, lanes, n_steps, prm->n_p, edac, st);
   if (rc) return rc;
   hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.V, v);
+  if (comp) hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.VL, comp);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
@@ -416,33 +509,49 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
 }  // namespace
 }  // namespace mpf
 
+extern "C" int mpf_acm_dt(double h_min, double nu, double* dt_host) {
+  if (!dt_host || !(h_min > 0.0) || !(nu > 0.0)) return MPF_ERR_ARG;
+  *dt_host = 0.1 * h_min * h_min / (2.0 * nu);
+  return MPF_OK;
+}
+
 extern "C" size_t mpf_acm_workspace(int64_t n, int precision) {
+  if (n < 1) return 256;
+  // V and V' records [n][4], a second pressure [n]; compensated: also the
+  // compensation records of V and V' [n][4] each
+  if (precision == MPF_F32_KAHAN) return 17 * (size_t)n * sizeof(float) + 256;
   const size_t es = precision == MPF_F32 ? sizeof(float) : sizeof(double);
-  return n > 0 ? 9 * (size_t)n * es + 256 : 256;  // V and V' records [n][4], a second pressure [n]
+  return 9 * (size_t)n * es + 256;
 }
 
 extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
-                           const void* w, const int32_t* sn, const void* wn, void* v, void* p, double* vmax,
-                           int n_steps, void* ws, size_t ws_bytes, void* stream) {
+                           const void* w, const int32_t* sn, const void* wn, void* v, void* p, void* comp,
+                           double* vmax, uint32_t* flags, int n_steps, void* ws, size_t ws_bytes, void* stream) {
   using namespace mpf;
   if (!prm || !sten || !w || !v || !p || !vmax || n < 1 || n_int < 0 || n_int > n || nl < 2 || n_steps < 0 ||
-      prm->n_p < 1 || !(prm->dt > 0.0) || !(prm->rho > 0.0))
+      prm->n_p < 1 || !(prm->dt > 0.0) || !(prm->rho > 0.0) || !(prm->h_min >= 0.0))
     return MPF_ERR_ARG;
   if (n > n_int && (!sn || !wn)) return MPF_ERR_ARG;
-  if (prm->precision != MPF_F64 && prm->precision != MPF_F32 && prm->precision != MPF_MIXED) return MPF_ERR_ARG;
+  const int prec = prm->precision;
+  if (prec != MPF_F64 && prec != MPF_F32 && prec != MPF_MIXED && prec != MPF_F32_KAHAN) return MPF_ERR_ARG;
+  if ((prec == MPF_F32_KAHAN) != (comp != nullptr)) return MPF_ERR_ARG;
   if (prm->edac != 0 && prm->edac != 1) return MPF_ERR_ARG;
   if (prm->lanes != 0 && prm->lanes != 1 && prm->lanes != 2 && prm->lanes != 4 && prm->lanes != 8 &&
       prm->lanes != 16)
     return MPF_ERR_ARG;
-  if (!ws || ws_bytes < mpf_acm_workspace(n, prm->precision)) return MPF_ERR_WORKSPACE;
+  if (!ws || ws_bytes < mpf_acm_workspace(n, prec)) return MPF_ERR_WORKSPACE;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);
-  if (prm->precision == MPF_F64)
-    return run<double, double>(prm, n, n_int, nl, sten, (const double*)w, sn, (const double*)wn, (double*)v,
-                               (double*)p, vmax, n_steps, ws, st);
-  if (prm->precision == MPF_MIXED)
-    return run<double, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (double*)v,
-                              (double*)p, vmax, n_steps, ws, st);
-  return run<float, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (float*)v, (float*)p, vmax,
-                    n_steps, ws, st);
+  int rc;
+  if (prec == MPF_F64)
+    rc = run<double, double>(prm, n, n_int, nl, sten, (const double*)w, sn, (const double*)wn, (double*)v,
+                             (double*)p, nullptr, vmax, flags, n_steps, ws, st);
+  else if (prec == MPF_MIXED)
+    rc = run<double, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (double*)v, (double*)p,
+                            nullptr, vmax, flags, n_steps, ws, st);
+  else
+    rc = run<float, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (float*)v, (float*)p,
+                           (float*)comp, vmax, flags, n_steps, ws, st);
+  if (rc) return rc;
+  return check_flags(flags, st);
 }

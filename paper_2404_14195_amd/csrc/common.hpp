@@ -21,6 +21,22 @@ constexpr int kWave = 64;
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// End of a *_run given a flags word: wait for the stream, read the word and
+// report MPF_ERR_DIVERGED when a kernel has set any bit.  No flags, no wait.
+inline int check_flags(const uint32_t* flags, hipStream_t st) {
+  if (!flags) return MPF_OK;
+  uint32_t h = 0;
+  MPF_HIP(hipMemcpyAsync(&h, flags, sizeof(h), hipMemcpyDeviceToHost, st));
+  MPF_HIP(hipStreamSynchronize(st));
+  return h ? MPF_ERR_DIVERGED : MPF_OK;
+}
+
+// Precisions whose state (fields, populations) is stored in FP32.
+inline bool state_is_f32(int precision) { return precision == MPF_F32 || precision == MPF_F32_KAHAN; }
+inline bool precision_ok(int precision) {
+  return precision == MPF_F64 || precision == MPF_F32 || precision == MPF_MIXED || precision == MPF_F32_KAHAN;
+}
+
 inline unsigned grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);

@@ -15,6 +15,16 @@
 // mask, built once by lbm_unknown), then collide (Eqs. macro_var, feq,
 // LBM_collision, force_lbm) and write the next post-collision state.  Weights
 // stream coalesced from [k][j][node].
+//
+// Compensated FP32 state (MPF_F32_KAHAN): next to the FP32 records f lives a
+// caller-owned FP32 record comp per node, so the state is f + comp.  The
+// column loop is the FP32 one (neighbours contribute their FP32 records);
+// the tile's epilogue adds the node's own comp through its rest population
+// and its self column (W_k0 comp_k) in FP64, bounces back and collides in
+// FP64, and splits the result into the FP32 value and the FP32 remainder.
+// An update smaller than half an ulp of f then moves comp instead of being
+// rounded away every step, which is what stalls a plain FP32 state short of
+// its fixed point.
 #include <type_traits>
 
 #include "common.hpp"
@@ -55,9 +65,11 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
-// TRT collision of one node's shifted populations, in place.
+// TRT collision of one node's shifted populations, in place.  Returns the
+// flags bits of the node: MPF_FLAG_NONFINITE for a non-finite density or
+// velocity, MPF_FLAG_LIMIT for |u|^2 >= 1/3 (the lattice speed of sound).
 template <typename T, int Q>
-__device__ __forceinline__ void collide(T (&f)[Q], const Prm<T>& pr) {
+__device__ __forceinline__ uint32_t collide(T (&f)[Q], const Prm<T>& pr) {
   using L = Lattice<Q>;
   T drho = T(0), j0 = T(0), j1 = T(0), j2 = T(0);
 #pragma unroll
@@ -72,6 +84,9 @@ __device__ __forceinline__ void collide(T (&f)[Q], const Prm<T>& pr) {
   const T u0 = j0 * ir, u1 = j1 * ir, u2 = j2 * ir;
   const T uu = u0 * u0 + u1 * u1 + u2 * u2;
   const T F0 = rho * pr.g0, F1 = rho * pr.g1, F2 = rho * pr.g2;
+  // x - x is 0 for a finite x and NaN otherwise
+  const uint32_t bits = !(drho - drho == T(0) && uu - uu == T(0)) ? MPF_FLAG_NONFINITE
+                                                                  : (uu >= T(1) / T(3) ? MPF_FLAG_LIMIT : 0u);
   // each opposite pair (k, kb) is relaxed together and in place: the TRT
   // update of f_k involves only f_k and f_kb, so no full f^eq, F or output
   // arrays stay live (fewer registers for the FP64 state)
@@ -96,21 +111,93 @@ __device__ __forceinline__ void collide(T (&f)[Q], const Prm<T>& pr) {
       f[kb] = fb - (fp - ep) * pr.itp - (fmb - emb) * pr.itm + Fkb;
     }
   }
+  return bits;
 }
 
-// src may equal dst: each thread reads and writes only its own node
-template <typename T, int Q>
-__global__ __launch_bounds__(kBlock) void lbm_collide(int64_t n, const T* src, T* dst,
-                                                      Prm<T> pr) {
+// The compensated state collides and streams in FP64.
+template <typename T, bool KAHAN>
+struct Compute {
+  using type = T;
+};
+template <>
+struct Compute<float, true> {
+  using type = double;
+};
+
+// Record of QP values at rec (16-byte aligned) into r[].
+template <typename T, int QP>
+__device__ __forceinline__ void load_rec(const T* __restrict__ rec, T (&r)[QP]) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  const V* p = reinterpret_cast<const V*>(rec);
+#pragma unroll
+  for (int v = 0; v < QP / VN; ++v) {
+    V x = p[v];
+    if constexpr (VN == 4) {
+      r[4 * v] = x.x; r[4 * v + 1] = x.y; r[4 * v + 2] = x.z; r[4 * v + 3] = x.w;
+    } else {
+      r[2 * v] = x.x; r[2 * v + 1] = x.y;
+    }
+  }
+}
+
+template <typename T, int QP>
+__device__ __forceinline__ void store_rec(T* __restrict__ rec, const T (&r)[QP]) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  V* p = reinterpret_cast<V*>(rec);
+#pragma unroll
+  for (int v = 0; v < QP / VN; ++v) {
+    V x;
+    if constexpr (VN == 4) {
+      x.x = r[4 * v]; x.y = r[4 * v + 1]; x.z = r[4 * v + 2]; x.w = r[4 * v + 3];
+    } else {
+      x.x = r[2 * v]; x.y = r[2 * v + 1];
+    }
+    p[v] = x;
+  }
+}
+
+// hi = fl32(x), lo = fl32(x - hi): the FP32 pair of a compensated value.
+template <int QP>
+__device__ __forceinline__ void split_store(const double (&x)[QP], float* __restrict__ hi_rec,
+                                            float* __restrict__ lo_rec) {
+  float hi[QP], lo[QP];
+#pragma unroll
+  for (int k = 0; k < QP; ++k) {
+    hi[k] = (float)x[k];
+    lo[k] = (float)(x[k] - (double)hi[k]);
+  }
+  store_rec<float, QP>(hi_rec, hi);
+  store_rec<float, QP>(lo_rec, lo);
+}
+
+__device__ __forceinline__ void raise_flags(uint32_t* flags, uint32_t bits) {
+  if (flags && bits) atomicOr(flags, bits);
+}
+
+// src may equal dst: each thread reads and writes only its own node.  With
+// a compensation record comp (compensated state; CT = double) the node's
+// value is src + comp, collided in FP64 and split back into dst and comp.
+template <typename T, typename CT, int Q>
+__global__ __launch_bounds__(kBlock) void lbm_collide(int64_t n, const T* src, T* dst, T* comp, Prm<CT> pr,
+                                                      uint32_t* flags) {
   constexpr int QP = Pad<Q>::QP;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  T f[Q];
+  CT f[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) f[k] = src[i * QP + k];
-  collide<T, Q>(f, pr);
+  for (int k = 0; k < Q; ++k) f[k] = (CT)src[i * QP + k] + (comp ? (CT)comp[i * QP + k] : CT(0));
+  raise_flags(flags, collide<CT, Q>(f, pr));
+  if constexpr (sizeof(CT) != sizeof(T)) {
+    double x[QP];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) dst[i * QP + k] = f[k];
+    for (int k = 0; k < QP; ++k) x[k] = k < Q ? (double)f[k] : 0.0;
+    split_store<QP>(x, dst + i * QP, comp + i * QP);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) dst[i * QP + k] = f[k];
+  }
 }
 
 // Blocks take 64-node tiles; hardware hands workgroups to the 8 XCDs round
@@ -144,17 +231,13 @@ inline unsigned tiles_grid(int64_t n) {
 // streaming them then costs 6-50 %; weights far larger than it are read from
 // HBM anyway, and streaming them keeps the gathered population records in the
 // caches (6 % faster at 1.26-2.5 GB of weights, all precisions).
-template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W>
-__global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(int64_t n, int64_t n_int, int nl,
-                                                       const int32_t* __restrict__ sten,
-                                                       const TW* __restrict__ W,
-                                                       const uint32_t* __restrict__ unknown,
-                                                       const T* __restrict__ src, T* __restrict__ dst, Prm<T> pr) {
-  using L = Lattice<Q>;
+template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W, bool KAHAN>
+__global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(
+    int64_t n, int64_t n_int, int nl, const int32_t* __restrict__ sten, const TW* __restrict__ W,
+    const uint32_t* __restrict__ unknown, const T* __restrict__ src, T* __restrict__ dst, T* __restrict__ comp,
+    Prm<typename Compute<T, KAHAN>::type> pr, uint32_t* __restrict__ flags) {
+  using CT = typename Compute<T, KAHAN>::type;
   constexpr int QP = Pad<Q>::QP;
-  using V = typename Vec16<T>::type;
-  constexpr int VN = Vec16<T>::n;
-  constexpr int NV = QP / VN;
   constexpr int NW = step_waves<TW, T>();
   __shared__ T part[NW][Q - 1][kTile];
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -172,17 +255,8 @@ __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(int64_
   for (int j = wv; j < nl; j += NW) {
     const int64_t at = (int64_t)j * n + ic;
     const int64_t s = sten[at];
-    const V* rec = reinterpret_cast<const V*>(src + s * QP);
     T r[QP];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      V x = rec[v];
-      if constexpr (VN == 4) {
-        r[4 * v] = x.x; r[4 * v + 1] = x.y; r[4 * v + 2] = x.z; r[4 * v + 3] = x.w;
-      } else {
-        r[2 * v] = x.x; r[2 * v + 1] = x.y;
-      }
-    }
+    load_rec<T, QP>(src + s * QP, r);
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const TW* wk = W + (k - 1) * ks + at;
@@ -196,20 +270,25 @@ __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(int64_
   for (int k = 1; k < Q; ++k) part[wv][k - 1][lane] = acc[k];
   __syncthreads();
   if (wv != 0 || !live) return;
-  T f[QP];
-  f[0] = src[ic * QP];
+  CT f[QP];
+  T lo[QP];
+  if constexpr (KAHAN) load_rec<T, QP>(comp + ic * QP, lo);
+  f[0] = (CT)src[ic * QP];
+  if constexpr (KAHAN) f[0] += (CT)lo[0];
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
-    T sum = part[0][k - 1][lane];
+    CT sum = (CT)part[0][k - 1][lane];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) sum += part[w][k - 1][lane];
+    for (int w = 1; w < NW; ++w) sum += (CT)part[w][k - 1][lane];
+    // the node's own remainder through its self column (column 0)
+    if constexpr (KAHAN) sum += (CT)W[(k - 1) * ks + ic] * (CT)lo[k];
     f[k] = sum;
   }
 #pragma unroll
-  for (int k = Q; k < QP; ++k) f[k] = T(0);
+  for (int k = Q; k < QP; ++k) f[k] = CT(0);
   if (i >= n_int) {
     const uint32_t mask = unknown[i - n_int];
-    T g[Q];
+    CT g[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) g[k] = f[k];
 #pragma unroll
@@ -217,23 +296,17 @@ __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(int64_
       if (mask >> k & 1u) f[k] = g[lat_opp(k)];
   }
   if (COLLIDE) {
-    T c[Q];
+    CT c[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) c[k] = f[k];
-    collide<T, Q>(c, pr);
+    raise_flags(flags, collide<CT, Q>(c, pr));
 #pragma unroll
     for (int k = 0; k < Q; ++k) f[k] = c[k];
   }
-  V* out = reinterpret_cast<V*>(dst + i * QP);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    V x;
-    if constexpr (VN == 4) {
-      x.x = f[4 * v]; x.y = f[4 * v + 1]; x.z = f[4 * v + 2]; x.w = f[4 * v + 3];
-    } else {
-      x.x = f[2 * v]; x.y = f[2 * v + 1];
-    }
-    out[v] = x;
+  if constexpr (KAHAN) {
+    split_store<QP>(f, dst + i * QP, comp + i * QP);
+  } else {
+    store_rec<T, QP>(dst + i * QP, f);
   }
 }
 
@@ -351,48 +424,46 @@ __global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int
 // and where streaming wins (1.26 GB).
 constexpr double kStreamWeightsBytes = 512.0 * 1024 * 1024;
 
-template <typename TW, typename T, int Q, bool STREAM_W>
+template <typename TW, typename T, int Q, bool STREAM_W, bool KAHAN>
 void launch_steps(int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W, const uint32_t* unknown,
-                  T* f, T* ft, T* cur, int n_steps, const Prm<T>& pr, hipStream_t st) {
+                  T* f, T* ft, T* comp, T* cur, int n_steps, const Prm<typename Compute<T, KAHAN>::type>& pr,
+                  uint32_t* flags, hipStream_t st) {
   const unsigned gt = tiles_grid(n);
+  const dim3 blk(step_waves<TW, T>() * kWave);
   for (int s = 0; s < n_steps - 1; ++s) {
     T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W>), dim3(gt), dim3(step_waves<TW, T>() * kWave), 0, st, n, n_int, nl, sten,
-                       W, unknown, (const T*)cur, nxt, pr);
+    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W, KAHAN>), dim3(gt), blk, 0, st, n, n_int, nl, sten, W,
+                       unknown, (const T*)cur, nxt, comp, pr, flags);
     cur = nxt;
   }
-  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W>), dim3(gt), dim3(step_waves<TW, T>() * kWave), 0, st, n, n_int, nl, sten,
-                     W, unknown, (const T*)cur, f, pr);
+  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W, KAHAN>), dim3(gt), blk, 0, st, n, n_int, nl, sten, W,
+                     unknown, (const T*)cur, f, comp, pr, flags);
 }
 
-template <typename TW, typename T, int Q>
+template <typename TW, typename T, int Q, bool KAHAN>
 int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W,
-        const uint32_t* unknown, T* f, T* ft, int n_steps, hipStream_t st) {
-  Prm<T> pr{(T)(1.0 / prm->tau_plus), (T)(1.0 / prm->tau_minus), (T)prm->g_lb[0], (T)prm->g_lb[1],
-            (T)prm->g_lb[2]};
+        const uint32_t* unknown, T* f, T* ft, T* comp, uint32_t* flags, int n_steps, hipStream_t st) {
+  using CT = typename Compute<T, KAHAN>::type;
+  Prm<CT> pr{(CT)(1.0 / prm->tau_plus), (CT)(1.0 / prm->tau_minus), (CT)prm->g_lb[0], (CT)prm->g_lb[1],
+             (CT)prm->g_lb[2]};
   const unsigned g = grid_for(n, kBlock);
   // collide so that after n_steps - 1 fused passes the current state sits in
   // ft, and the last (stream-only) pass lands in f
-  T* cur;
-  if ((n_steps - 1) % 2 == 0) {
-    hipLaunchKernelGGL((lbm_collide<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, ft, pr);
-    cur = ft;
-  } else {
-    hipLaunchKernelGGL((lbm_collide<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, f, pr);
-    cur = f;
-  }
+  T* cur = (n_steps - 1) % 2 == 0 ? ft : f;
+  hipLaunchKernelGGL((lbm_collide<T, CT, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, cur, comp, pr, flags);
   if ((double)(Q - 1) * nl * n * sizeof(TW) > kStreamWeightsBytes)
-    launch_steps<TW, T, Q, true>(n, n_int, nl, sten, W, unknown, f, ft, cur, n_steps, pr, st);
+    launch_steps<TW, T, Q, true, KAHAN>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr, flags, st);
   else
-    launch_steps<TW, T, Q, false>(n, n_int, nl, sten, W, unknown, f, ft, cur, n_steps, pr, st);
+    launch_steps<TW, T, Q, false, KAHAN>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr, flags, st);
   MPF_LAUNCH_CHECK();
-  return MPF_OK;
+  return check_flags(flags, st);
 }
 
-// Populations are double for MPF_F64 and MPF_MIXED, float for MPF_F32.
+// Populations are double for MPF_F64 and MPF_MIXED, float for MPF_F32 and
+// MPF_F32_KAHAN.
 template <int Q, typename F>
 int with_state(int precision, F&& fn) {
-  if (precision == MPF_F32) return fn(float{});
+  if (state_is_f32(precision)) return fn(float{});
   if (precision == MPF_F64 || precision == MPF_MIXED) return fn(double{});
   return MPF_ERR_ARG;
 }
@@ -443,26 +514,30 @@ extern "C" int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const d
 }
 
 extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
-                           const void* W, const uint32_t* unknown, void* f, void* f_tmp, int n_steps,
-                           void* stream) {
+                           const void* W, const uint32_t* unknown, void* f, void* f_tmp, void* comp,
+                           uint32_t* flags, int n_steps, void* stream) {
   using namespace mpf;
   if (!prm || !sten || !W || !f || !f_tmp || n < 1 || n_int < 0 || n_int > n || nl < 1 || n_steps < 0)
     return MPF_ERR_ARG;
   if (n > n_int && !unknown) return MPF_ERR_ARG;
   if (!(prm->tau_plus > 0.5) || !(prm->tau_minus > 0.5)) return MPF_ERR_ARG;
-  if (prm->precision != MPF_F64 && prm->precision != MPF_F32 && prm->precision != MPF_MIXED) return MPF_ERR_ARG;
+  if (!precision_ok(prm->precision)) return MPF_ERR_ARG;
+  if ((prm->precision == MPF_F32_KAHAN) != (comp != nullptr)) return MPF_ERR_ARG;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);
   return with_q(prm->q, [&](auto qc) {
     constexpr int Q = decltype(qc)::value;
     if (prm->precision == MPF_F64)
-      return run<double, double, Q>(prm, n, n_int, nl, sten, (const double*)W, unknown, (double*)f, (double*)f_tmp,
-                                    n_steps, st);
+      return run<double, double, Q, false>(prm, n, n_int, nl, sten, (const double*)W, unknown, (double*)f,
+                                           (double*)f_tmp, nullptr, flags, n_steps, st);
     if (prm->precision == MPF_MIXED)
-      return run<float, double, Q>(prm, n, n_int, nl, sten, (const float*)W, unknown, (double*)f, (double*)f_tmp,
-                                   n_steps, st);
-    return run<float, float, Q>(prm, n, n_int, nl, sten, (const float*)W, unknown, (float*)f, (float*)f_tmp, n_steps,
-                                st);
+      return run<float, double, Q, false>(prm, n, n_int, nl, sten, (const float*)W, unknown, (double*)f,
+                                          (double*)f_tmp, nullptr, flags, n_steps, st);
+    if (prm->precision == MPF_F32_KAHAN)
+      return run<float, float, Q, true>(prm, n, n_int, nl, sten, (const float*)W, unknown, (float*)f, (float*)f_tmp,
+                                        (float*)comp, flags, n_steps, st);
+    return run<float, float, Q, false>(prm, n, n_int, nl, sten, (const float*)W, unknown, (float*)f, (float*)f_tmp,
+                                       nullptr, flags, n_steps, st);
   });
 }
 

@@ -702,7 +702,7 @@ extern "C" int mpf_mlp_features(int64_t n, const double* pos, double r, double p
 extern "C" int mpf_mlp_to_state(int64_t n, int64_t n_int, const float* y, double U, double P, int precision, void* v,
                                 void* p, double* vmax, void* ws, size_t ws_bytes, void* stream) {
   if (!y || !v || !p || n < 1 || n_int < 0 || n_int > n) return MPF_ERR_ARG;
-  if (precision != MPF_F64 && precision != MPF_F32 && precision != MPF_MIXED) return MPF_ERR_ARG;
+  if (!precision_ok(precision)) return MPF_ERR_ARG;
   if (!ws || ws_bytes < mpf_reduce_workspace(n)) return MPF_ERR_WORKSPACE;
   hipStream_t st = as_stream(stream);
   const unsigned g = grid_for(n, kBlock);
@@ -712,7 +712,7 @@ extern "C" int mpf_mlp_to_state(int64_t n, int64_t n_int, const float* y, double
   hipLaunchKernelGGL(finish_sum, dim3(1), dim3(kBlock), 0, st, (const double*)part, (int64_t)g, 1, 1.0 / (double)n,
                      mean);
   if (vmax) hipLaunchKernelGGL(zero_double, dim3(1), dim3(1), 0, st, vmax);
-  if (precision == MPF_F32)
+  if (state_is_f32(precision))
     hipLaunchKernelGGL(to_state_kernel<float>, dim3(g), dim3(kBlock), 0, st, n, n_int, y, U, P, (const double*)mean,
                        (float*)v, (float*)p, vmax);
   else

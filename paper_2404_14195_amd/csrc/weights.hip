@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <new>
 #include <tuple>
 #include <vector>
 
@@ -507,16 +508,39 @@ bool ops_need_rowvec(int n_ops, const mpf_op* ops) {
   return false;
 }
 
-// autotune cache: (device, nl, n_ops, solve) -> tile shape
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, Tune> g_tune;
-
 const Tune kDefaultTune{4, 1};
 
 }  // namespace
 }  // namespace mpf
 
+// The library context: its device and the autotune cache, (nl, n_ops,
+// solve) -> tile shape.
+struct mpf_ctx {
+  int device = 0;
+  std::mutex mu;
+  std::map<std::tuple<int, int, int>, mpf::Tune> tune;
+};
+
 using namespace mpf;
+
+extern "C" int mpf_create(mpf_ctx** out, int hip_device) {
+  if (!out) return MPF_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  MPF_HIP(hipGetDeviceCount(&count));
+  if (hip_device < 0 || hip_device >= count) return MPF_ERR_ARG;
+  MPF_HIP(hipSetDevice(hip_device));
+  mpf_ctx* c = new (std::nothrow) mpf_ctx;
+  if (!c) return MPF_ERR_HIP;
+  c->device = hip_device;
+  *out = c;
+  return MPF_OK;
+}
+
+extern "C" int mpf_destroy(mpf_ctx* ctx) {
+  delete ctx;
+  return MPF_OK;
+}
 
 extern "C" size_t mpf_weights_workspace(void) { return kWorkspaceBytes; }
 
@@ -533,9 +557,9 @@ int upload_table(const BatchArg& B, void* ws, hipStream_t st) {
 }
 }  // namespace
 
-extern "C" int mpf_rbffd_weights_batched(int n_geoms, const mpf_wgeom* geoms, int nl, int n_ops, const mpf_op* ops,
-                                         int solve, const mpf_wtune* tune, void* ws, size_t ws_bytes,
-                                         void* stream) {
+extern "C" int mpf_rbffd_weights_batched(mpf_ctx* ctx, int n_geoms, const mpf_wgeom* geoms, int nl, int n_ops,
+                                         const mpf_op* ops, int solve, const mpf_wtune* tune, void* ws,
+                                         size_t ws_bytes, void* stream) {
   if (solve != MPF_SOLVE_FP64 && solve != MPF_SOLVE_FP32_IR) return MPF_ERR_ARG;
   if (!ops || n_ops < 1 || n_ops > kMaxOps) return MPF_ERR_ARG;
   const bool rv = ops_need_rowvec(n_ops, ops);
@@ -553,12 +577,10 @@ extern "C" int mpf_rbffd_weights_batched(int n_geoms, const mpf_wgeom* geoms, in
     if (tune->waves_per_block < 1 || tune->waves_per_block > 8 || tune->rows_per_wave < 1 || tune->rows_per_wave > 64)
       return MPF_ERR_ARG;
     t = Tune{tune->waves_per_block, tune->rows_per_wave};
-  } else {
-    int dev = 0;
-    MPF_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(std::make_tuple(dev, nl, n_ops, solve));
-    if (it != g_tune.end()) t = it->second;
+  } else if (ctx) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tune.find(std::make_tuple(nl, n_ops, solve));
+    if (it != ctx->tune.end()) t = it->second;
   }
   hipStream_t st = as_stream(stream);
   rc = upload_table(B, ws, st);
@@ -566,9 +588,10 @@ extern "C" int mpf_rbffd_weights_batched(int n_geoms, const mpf_wgeom* geoms, in
   return solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
 }
 
-extern "C" int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
-                                    int64_t sample_rows, mpf_wtune* out, void* ws, size_t ws_bytes) {
-  if (!sample || !out || sample_rows < 1) return MPF_ERR_ARG;
+extern "C" int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_op* ops, int solve,
+                                    const mpf_wgeom* sample, int64_t sample_rows, mpf_wtune* out, void* ws,
+                                    size_t ws_bytes) {
+  if (!ctx || !sample || !out || sample_rows < 1) return MPF_ERR_ARG;
   if (solve != MPF_SOLVE_FP64 && solve != MPF_SOLVE_FP32_IR) return MPF_ERR_ARG;
   if (!nl_supported(nl)) return MPF_ERR_UNSUPPORTED;
   if (!ws || ws_bytes < mpf_weights_workspace()) return MPF_ERR_WORKSPACE;
@@ -580,6 +603,7 @@ extern "C" int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int so
   BatchArg B;
   rc = make_batch(1, &g, ops_need_rowvec(n_ops, ops), B);
   if (rc) return rc;
+  MPF_HIP(hipSetDevice(ctx->device));
   hipStream_t st = nullptr;
   MPF_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   rc = upload_table(B, ws, st);
@@ -612,11 +636,9 @@ extern "C" int mpf_weights_autotune(int nl, int n_ops, const mpf_op* ops, int so
   (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
   if (err) return err;
-  int dev = 0;
-  MPF_HIP(hipGetDevice(&dev));
   {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(dev, nl, n_ops, solve)] = best;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tune[std::make_tuple(nl, n_ops, solve)] = best;
   }
   out->waves_per_block = best.waves;
   out->rows_per_wave = best.rows;
@@ -634,5 +656,5 @@ extern "C" int mpf_rbffd_weights(const double* pos, int64_t n_nodes, const int32
   if (!nl_supported(nl)) return MPF_ERR_UNSUPPORTED;
   if (m == 0) return MPF_OK;
   mpf_wgeom g{pos, n_nodes, sten, m, rowvec, w64, w32, info};
-  return mpf_rbffd_weights_batched(1, &g, nl, n_ops, ops, MPF_SOLVE_FP64, nullptr, ws, ws_bytes, stream);
+  return mpf_rbffd_weights_batched(nullptr, 1, &g, nl, n_ops, ops, MPF_SOLVE_FP64, nullptr, ws, ws_bytes, stream);
 }

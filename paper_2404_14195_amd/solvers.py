@@ -1,8 +1,11 @@
 """Device-resident drivers for the two meshless solvers.
 
 They hold the node cloud, stencils, weights and state in HBM and call the C
-ABI (``api``) for every step of the computation; the host only launches and,
-at checks, reads back one or three doubles."""
+ABI (``api``) for every step of the computation, the unit conversions and the
+reductions to k and K included; the host only launches and, at checks, reads
+back one or three doubles.  Each run call hands the library a flags word (a
+non-finite state or a stability limit) and raises MPFDiverged when it comes
+back set, unless the solver's ``check`` is False."""
 from __future__ import annotations
 
 import math
@@ -14,10 +17,10 @@ import torch
 import nodecloud
 
 from . import api
-from ._lib import MPF_F32, MPF_F64, MPF_MIXED, AcmParams, LbmParams
+from ._lib import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, AcmParams, LbmParams
 
 # state element type per precision (MPF_MIXED: FP32 weights, FP64 state)
-_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64}
+_DT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64, MPF_F32_KAHAN: torch.float32}
 
 
 class Discretization:
@@ -62,11 +65,11 @@ class ACMSolver:
     """Artificial-compressibility Navier-Stokes (Sec. 2.3) on a Discretization."""
 
     def __init__(self, disc: Discretization, precision: int = MPF_F64, nu=1.0, rho=1.0, dt=None, beta=10.0,
-                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False):
-        self.d, self.precision = disc, precision
-        dt = 0.1 * disc.cloud.h_min ** 2 / (2.0 * nu) if dt is None else dt
+                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False, check: bool = True):
+        self.d, self.precision, self.check = disc, precision, check
+        dt = api.acm_dt(disc.cloud.h_min, nu) if dt is None else dt
         self.prm = AcmParams(nu=nu, rho=rho, dt=dt, beta=beta, v_ref=v_ref, g=(ctypesarr(g)), n_p=n_p,
-                             precision=precision, lanes=lanes, edac=int(bool(edac)))
+                             precision=precision, lanes=lanes, edac=int(bool(edac)), h_min=disc.cloud.h_min)
         self.g = tuple(g)
         w64, w32, info = api.rbffd_weights(disc.pos, disc.sten, [("dx",), ("dy",), ("dz",), ("lap",)],
                                            want64=True, want32=precision != MPF_F64)
@@ -81,13 +84,30 @@ class ACMSolver:
         self.v = torch.zeros((3, disc.n), dtype=dtp, device=disc.device)
         self.p = torch.zeros(disc.n, dtype=dtp, device=disc.device)
         self.vmax = torch.zeros(1, dtype=torch.float64, device=disc.device)
+        # compensation terms of v (rows 0-2) and p (row 3) of the compensated FP32 state
+        self.comp = torch.zeros((4, disc.n), dtype=torch.float32, device=disc.device) \
+            if precision == MPF_F32_KAHAN else None
+        self.flags = torch.zeros(1, dtype=torch.int32, device=disc.device)
         self.ws = api.acm_workspace(disc.n, precision, disc.device)
         self.steps = 0
 
     def run(self, n_steps: int):
         api.acm_run(self.prm, self.d.n_int, self.d.sten, self.w, self.d.sn, self.wn, self.v, self.p, self.vmax,
-                    n_steps, self.ws)
+                    n_steps, self.ws, comp=self.comp, flags=self.flags if self.check else None)
         self.steps += n_steps
+
+    def clear_compensation(self):
+        """After the state was set from outside (a warm start): the FP32
+        values are the state, their compensation is zero."""
+        if self.comp is not None:
+            self.comp.zero_()
+
+    def scale_velocity(self, c: float):
+        """v *= c with its compensation and the running max (flux match)."""
+        api.scale(self.v, c)
+        if self.comp is not None:
+            api.scale(self.comp[:3], c)
+        api.scale(self.vmax, c)
 
     @property
     def time_step(self) -> float:
@@ -99,8 +119,7 @@ class ACMSolver:
 
     def permeability(self) -> float:
         """k/d^2 = q nu / (|g| d^2), Eq. k_definition."""
-        q = float(self.flux().item())
-        return q * self.prm.nu / math.sqrt(sum(x * x for x in self.g))
+        return api.permeability(float(self.flux().item()), self.prm.nu, self.g)
 
     def drag(self):
         """(F [3], K) with K = F_x / (6 pi r phi q mu), Eq. K_definition."""
@@ -108,8 +127,12 @@ class ACMSolver:
         F = api.drag(self.v, self.p, d.sb, self.wg, d.nrm, self.prm.rho, self.prm.nu, d.area / d.nb, ws=d.red_ws)
         F = F.cpu().numpy()
         q = float(self.flux().item())
-        K = F[0] / (6.0 * math.pi * d.cloud.r * d.phi * q * self.prm.rho * self.prm.nu)
+        K = api.drag_coefficient(F[0], d.cloud.r, d.phi, q, self.prm.rho * self.prm.nu)
         return F, K
+
+    def residual(self, v_prev=None):
+        """[max |v - v_prev|, max |v|, rms div v] over the interior (host floats)."""
+        return api.residual(self.d.sten, self.w, self.v, self.d.n_int, v_prev, self.precision).cpu().tolist()
 
     def surface_map(self):
         """Traction sigma n [3][nb] and centred pressure [nb] on the grain
@@ -125,12 +148,9 @@ def ctypesarr(g):
 
 def lbm_units(h_min: float, nu: float, tau_plus: float, g, magic: float):
     """dx = h_min / 2 (Sec. 2.2), nu_lb = (tau+ - 1/2)/3 (Eq. lbm_viscosity),
-    dt and g_lb from Eq. conversion_factors, tau- from the magic parameter."""
-    dx = 0.5 * h_min
-    nu_lb = (tau_plus - 0.5) / 3.0
-    dt = nu_lb * dx * dx / nu
-    return dict(dx=dx, dt=dt, nu_lb=nu_lb, g_lb=[x * dt * dt / dx for x in g],
-                tau_minus=0.5 + magic / (tau_plus - 0.5), vel_scale=dx / dt)
+    dt and g_lb from Eq. conversion_factors, tau- from the magic parameter:
+    the library's mpf_lbm_units_of."""
+    return api.lbm_units(h_min, nu, tau_plus, g, magic)
 
 
 def lattice_vectors(q: int):
@@ -165,8 +185,9 @@ class MLBMSolver:
     Sec. 3.3)."""
 
     def __init__(self, disc: Discretization, q=19, precision: int = MPF_F64, nu=1.0, tau_plus=1.0, magic=0.25,
-                 g=(1.0, 0.0, 0.0), dx=None, W=None, streaming: str = "shift", rule: str = "normal"):
-        self.d, self.q, self.precision = disc, q, precision
+                 g=(1.0, 0.0, 0.0), dx=None, W=None, streaming: str = "shift", rule: str = "normal",
+                 check: bool = True):
+        self.d, self.q, self.precision, self.check = disc, q, precision, check
         h = disc.cloud.h_min if dx is None else 2.0 * dx
         self.units = u = lbm_units(h, nu, tau_plus, g, magic)
         self.nu, self.g = nu, tuple(g)
@@ -185,6 +206,10 @@ class MLBMSolver:
         dtp = _DT[precision]
         self.f = torch.empty((disc.n, api.record_len(q)), dtype=dtp, device=disc.device)
         self.f_tmp = torch.empty_like(self.f)
+        # compensation records of the compensated FP32 state (zero: the
+        # equilibrium below is its FP32 value)
+        self.comp = torch.zeros_like(self.f) if precision == MPF_F32_KAHAN else None
+        self.flags = torch.zeros(1, dtype=torch.int32, device=disc.device)
         api.lbm_init(self.prm, self.f)
         self.steps = 0
         self._v = torch.empty((3, disc.n), dtype=torch.float64, device=disc.device)
@@ -195,10 +220,13 @@ class MLBMSolver:
         """Start from the equilibrium of fields v [3][n], p [n] (device double,
         physical units): a warm start."""
         api.lbm_init_fields(self.prm, self.f, v, p, self.units["vel_scale"])
+        if self.comp is not None:
+            self.comp.zero_()
         self.steps = 0
 
     def run(self, n_steps: int):
-        api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.unknown, self.f, self.f_tmp, n_steps)
+        api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.unknown, self.f, self.f_tmp, n_steps,
+                    comp=self.comp, flags=self.flags if self.check else None)
         self.steps += n_steps
 
     @property
@@ -207,14 +235,21 @@ class MLBMSolver:
         return self.units["dt"]
 
     def populations(self):
-        """Host copy of the state as f [n][q] (unshifted)."""
-        return self.f[:, :self.q].double().cpu().numpy() + lattice_weights(self.q)
+        """Host copy of the state as f [n][q] (unshifted; the compensated
+        state adds its remainder in FP64)."""
+        f = self.f[:, :self.q].double().cpu().numpy()
+        if self.comp is not None:
+            f = f + self.comp[:, :self.q].double().cpu().numpy()
+        return f + lattice_weights(self.q)
 
     def set_populations(self, f):
         """Load f [n][q] (unshifted, host) into the device state."""
         buf = np.zeros(tuple(self.f.shape))
         buf[:, :self.q] = np.asarray(f) - lattice_weights(self.q)
         self.f.copy_(torch.as_tensor(buf, dtype=self.f.dtype, device=self.f.device))
+        if self.comp is not None:  # the FP32 remainder of the given values
+            rem = buf - self.f.double().cpu().numpy()
+            self.comp.copy_(torch.as_tensor(rem, dtype=torch.float32, device=self.f.device))
 
     def macros(self):
         return api.lbm_moments(self.prm, self.f, self.units["vel_scale"], self._v, self._p)
@@ -222,7 +257,7 @@ class MLBMSolver:
     def permeability(self) -> float:
         v, _ = self.macros()
         q = float(api.flux_planes(self.d.s_idx, self.d.s_w, v[0], self.d.n_all, ws=self.d.red_ws).item())
-        return q * self.nu / math.sqrt(sum(x * x for x in self.g))
+        return api.permeability(q, self.nu, self.g)
 
     def drag(self):
         d = self.d
@@ -232,7 +267,7 @@ class MLBMSolver:
             self._wg = api.rbffd_weights(d.pos, d.sb, [("dx",), ("dy",), ("dz",)])[0]
         F = api.drag(v, p, d.sb, self._wg, d.nrm, 1.0, self.nu, d.area / d.nb, ws=d.red_ws).cpu().numpy()
         q = float(api.flux_planes(d.s_idx, d.s_w, v[0], d.n_all, ws=d.red_ws).item())
-        K = F[0] / (6.0 * math.pi * d.cloud.r * d.phi * q * self.nu)
+        K = api.drag_coefficient(F[0], d.cloud.r, d.phi, q, self.nu)
         return F, K
 
     def surface_map(self):

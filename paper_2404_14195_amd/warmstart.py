@@ -105,6 +105,19 @@ def steady_fields_many(solvers, check=500, tol=1e-6, max_steps=1_000_000, log=No
     Returns [(k, steps)] in the solvers' order."""
     streams = [torch.cuda.Stream() for _ in solvers]
     torch.cuda.synchronize()  # set-up ran on the default stream
+    # no end-of-call flag check (it waits for the stream and would serialise
+    # the cells); a non-finite k below still stops the run
+    checks = [s.check for s in solvers]
+    for s in solvers:
+        s.check = False
+    try:
+        return _steady_many(solvers, streams, check, tol, max_steps, log, log_every)
+    finally:
+        for s, c in zip(solvers, checks):
+            s.check = c
+
+
+def _steady_many(solvers, streams, check, tol, max_steps, log, log_every):
     ks = [[] for _ in solvers]
     out = [None] * len(solvers)
     t_log = time.perf_counter()
@@ -217,16 +230,26 @@ class WarmStart:
         api.mlp_forward(self.master, self.packed, x, y, ws)
         return y
 
-    def state(self, disc, v, p, vmax=None):
+    def state(self, disc, v, p, vmax=None, network: bool = True):
         """Predicted state of a cell into v [3][n], p [n] (and max |v|).
 
         The network gives the shape of the field and the interpolation over
         the training radii its magnitude; the velocity is then rescaled so that
         its flux through the permeability planes equals U = k(r) |g| / nu
         exactly.  The flux is the slowest-decaying part of the iteration's
-        error, so it is the part worth pinning to the best estimate."""
+        error, so it is the part worth pinning to the best estimate.
+
+        network=False is the ablation without the network: the same magnitude
+        and flux match applied to a shapeless field, a uniform velocity along
+        the body force on the interior nodes (zero on the grain) and zero
+        pressure, so that a run from it measures what the k(r) lookup and the
+        flux matches alone give."""
         U, P = self.scales(disc.cloud.r)
-        y = self.predict(disc)
+        if network:
+            y = self.predict(disc)
+        else:
+            y = torch.zeros((disc.n, 4), dtype=torch.float32, device=self.device)
+            y[:, 0] = 1.0
         api.mlp_to_state(y, disc.n_int, U, P, v, p, vmax, disc.red_ws)
         q = float(api.flux_planes(disc.s_idx, disc.s_w, v[0], disc.n_all, ws=disc.red_ws).item())
         if q > 0.0 and math.isfinite(q):
@@ -238,7 +261,7 @@ class WarmStart:
         q = float(api.flux_planes(disc.s_idx, disc.s_w, vx, disc.n_all, ws=disc.red_ws).item())
         return U / q if q > 0.0 and math.isfinite(q) else None
 
-    def load_acm(self, solver, burn_in: int = 1000):
+    def load_acm(self, solver, burn_in: int = 1000, network: bool = True):
         """Warm-start an ACMSolver in place (v, p and the running max |v|).
 
         After burn_in steps the velocity is rescaled once more so that its
@@ -247,24 +270,25 @@ class WarmStart:
         approach to steady state has the shape of the steady flow itself, so a
         uniform rescaling removes what the shift left in it.  solver.steps
         counts the burn-in."""
-        self.state(solver.d, solver.v, solver.p, solver.vmax)
+        self.state(solver.d, solver.v, solver.p, solver.vmax, network=network)
+        solver.clear_compensation()
         solver.steps = 0
         if burn_in > 0:
             solver.run(burn_in)
             c = self._flux_factor(solver.d, solver.v[0])
             if c is not None:
-                api.scale(solver.v, c)
-                api.scale(solver.vmax, c)
+                solver.scale_velocity(c)
 
-    def load_mlbm(self, solver, burn_in: int = 1000):
+    def load_mlbm(self, solver, burn_in: int = 1000, network: bool = True):
         """Warm-start an MLBMSolver: equilibrium populations of the predicted
         fields, then after burn_in steps the same flux match as load_acm (the
         populations are rebuilt as the equilibrium of the rescaled
-        velocity and the current pressure).  solver.steps counts the burn-in."""
+        velocity and the current pressure).  solver.steps counts the burn-in.
+        network=False: the ablation of state()."""
         d = solver.d
         v = torch.empty((3, d.n), dtype=torch.float64, device=self.device)
         p = torch.empty(d.n, dtype=torch.float64, device=self.device)
-        self.state(d, v, p)
+        self.state(d, v, p, network=network)
         solver.set_fields(v, p)
         if burn_in > 0:
             solver.run(burn_in)
@@ -286,6 +310,61 @@ class WarmStart:
         self.radii, self.logU, self.logP = list(sd["radii"]), list(sd["logU"]), list(sd["logP"])
 
 
+def solve_warm(model, make_solver, kind: str = "mlbm", band: float = 0.1, burn_in: int = 1000, check: int = 500,
+               tol: float = 1e-7, max_steps: int = 1_000_000, network: bool = True):
+    """Steady solve of one cell from the learned prediction, with the plain
+    cold-started solver as its fallback.
+
+    make_solver() builds a fresh solver of the cell (from rest).  The warm
+    run loads the prediction (``load_mlbm`` or ``load_acm``: prediction,
+    burn-in, flux match) and then runs until k changes by at most tol
+    (relative) per check.  It is abandoned, and a fresh solver is run from
+    rest to the same criterion instead, when the library reports a diverged
+    state (MPFDiverged: a non-finite value or a stability limit), when k is
+    not finite, or when k at any check leaves the band |k / U - 1| <= band
+    around the network's own magnitude estimate U = k(r) (the prediction is
+    then not the cell's flow).  Returns a dict with the solver used, k,
+    steps, the (steps, k) history of the run that finished, and
+    fallback/reason."""
+    from ._lib import MPFDiverged
+    if kind not in ("mlbm", "acm"):
+        raise ValueError("kind is 'mlbm' or 'acm'")
+    s = make_solver()
+    U, _ = model.scales(s.d.cloud.r)
+
+    def in_band(k):
+        return math.isfinite(k) and abs(k / U - 1.0) <= band
+
+    def settle(solver, hist, guard):
+        while solver.steps < max_steps:
+            solver.run(check)
+            k = solver.permeability()
+            hist.append((solver.steps, k))
+            if not guard(k):
+                return f"k = {k:.6e} after {solver.steps} steps"
+            if len(hist) > 2 and abs(hist[-1][1] - hist[-2][1]) <= tol * abs(k):
+                return None
+        raise RuntimeError(f"k not steady after {solver.steps} steps")
+
+    reason = None
+    hist = []
+    try:
+        (model.load_mlbm if kind == "mlbm" else model.load_acm)(s, burn_in=burn_in, network=network)
+        k0 = s.permeability()
+        hist.append((s.steps, k0))
+        reason = None if in_band(k0) else f"prediction k = {k0:.6e}, U(r) = {U:.6e}"
+        if reason is None:
+            reason = settle(s, hist, in_band)
+    except MPFDiverged as e:
+        reason = f"diverged: {e}"
+    if reason is None:
+        return {"solver": s, "k": hist[-1][1], "steps": s.steps, "history": hist, "fallback": False, "reason": None}
+    s = make_solver()  # the plain solver from rest
+    hist = []
+    settle(s, hist, math.isfinite)
+    return {"solver": s, "k": hist[-1][1], "steps": s.steps, "history": hist, "fallback": True, "reason": reason}
+
+
 def training_radii(n: int, seed: int = 5, lo: float = 0.15, hi: float = 0.48, held_out=(0.18, 0.3, 0.33, 0.47),
                    gap: float = 0.01):
     """n radii in [lo, hi], one uniform draw in each of n equal strata
@@ -303,4 +382,4 @@ def training_radii(n: int, seed: int = 5, lo: float = 0.15, hi: float = 0.48, he
     return out
 
 
-__all__ = ["WarmStart", "steady_fields", "training_radii", "MPF_F32", "MPF_MIXED"]
+__all__ = ["WarmStart", "solve_warm", "steady_fields", "training_radii", "MPF_F32", "MPF_MIXED"]

@@ -132,3 +132,72 @@ def test_steady_fields_many_equals_one_at_a_time():
     one = [steady_fields(MLBMSolver(d, q=19, precision=MPF_MIXED), tol=1e-6) for d in discs]
     many = steady_fields_many([MLBMSolver(d, q=19, precision=MPF_MIXED) for d in discs], tol=1e-6)
     assert many == one
+
+
+def test_network_beats_the_ablation(trained, held_out):
+    """What the trained network gains: the same start without it (a uniform
+    velocity scaled to the same U(r), the same 1,000-step burn-in and the same
+    second flux match) needs more steps to stay within 1e-3 of the cold run's
+    steady k than the network's prediction does."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    cold = MLBMSolver(held_out, q=19, precision=MPF_MIXED)
+    nc_, kc = trajectory(cold)
+    k_ref = kc[-1]
+    res = {}
+    for name, network in (("network", True), ("ablation", False)):
+        s = MLBMSolver(held_out, q=19, precision=MPF_MIXED)
+        trained.load_mlbm(s, network=network)
+        ns, ks = trajectory(s)
+        res[name] = (steps_to_band(ns, ks, k_ref), ks[0], ks[-1])
+    print(f"[warm-start ablation] k_ref={k_ref:.8e}; steps to 1e-3: cold {steps_to_band(nc_, kc, k_ref)}, "
+          f"network {res['network'][0]}, no network {res['ablation'][0]}; initial k: network "
+          f"{res['network'][1]:.6e}, no network {res['ablation'][1]:.6e}", flush=True)
+    assert res["ablation"][2] == pytest.approx(k_ref, rel=1e-5)  # same steady state either way
+    assert res["network"][0] is not None and res["ablation"][0] is not None
+    assert res["network"][0] < res["ablation"][0]
+
+
+def _copy(model):
+    from paper_2404_14195_amd.warmstart import WarmStart
+    m = WarmStart(seed=0)
+    m.load_state_dict(model.state_dict())
+    return m
+
+
+def test_cold_fallback_on_corrupted_predictions(trained, held_out):
+    """solve_warm falls back to the plain solver from rest when the
+    prediction is bad, and then gives the cold run's k bit for bit:
+    (a) NaN network parameters (written on the host): the burn-in's flags
+    word reports the non-finite state; (b) a magnitude estimate three times
+    too large: the flux match makes the start consistent with it, but k
+    leaves the 10 % band around it as the run relaxes.  The intact model
+    does not fall back."""
+    from paper_2404_14195_amd import MPF_MIXED
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    from paper_2404_14195_amd.warmstart import solve_warm
+    make = lambda: MLBMSolver(held_out, q=19, precision=MPF_MIXED)
+    cold = make()
+    hist = []
+    while True:
+        cold.run(500)
+        hist.append(cold.permeability())
+        if len(hist) > 2 and abs(hist[-1] - hist[-2]) <= 1e-7 * abs(hist[-1]):
+            break
+    good = solve_warm(trained, make)
+    print(f"[fallback] intact: k={good['k']:.8e} steps={good['steps']} fallback={good['fallback']}", flush=True)
+    assert not good["fallback"] and good["k"] == pytest.approx(hist[-1], rel=1e-5)
+    bad_nan = _copy(trained)
+    m = bad_nan.master.cpu()
+    m[::7] = float("nan")
+    bad_nan.master.copy_(m)
+    from paper_2404_14195_amd import api
+    api.mlp_pack(bad_nan.master, bad_nan.packed)
+    bad_big = _copy(trained)
+    bad_big.logU = [x + np.log(3.0) for x in bad_big.logU]
+    for name, model in (("nan", bad_nan), ("3x", bad_big)):
+        r = solve_warm(model, make)
+        print(f"[fallback] {name}: fallback={r['fallback']} reason={r['reason']} k={r['k']:.8e} steps={r['steps']}",
+              flush=True)
+        assert r["fallback"]
+        assert r["k"] == hist[-1] and r["steps"] == cold.steps  # the plain cold run, bit for bit

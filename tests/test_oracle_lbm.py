@@ -307,3 +307,21 @@ def test_trt_relaxes_odd_and_even_modes_at_their_own_rates(q, tau_plus, magic):
         assert np.abs(m.f - expect).max() < 1e-15
     # the two rates are distinguishable in every case above
     assert abs(1.0 / tau_minus - 1.0 / tau_plus) * eps * np.abs(odd).max() > 1e-7
+
+
+def test_threads_do_not_change_the_oracle():
+    """The MLBM oracle's node loops may run on several host threads (to time
+    it on all cores); every node's arithmetic is unchanged, so the state is
+    identical bit for bit."""
+    c = nc.sphere_cloud(0.3, 0.05, 0.3, 0.1, seed=1)
+    S = nc.solver_stencils(c, 30)
+    out = []
+    try:
+        for th in (1, 4):
+            assert O.set_threads(th) == th
+            m = O.MLBM(c.pos, c.n_int, S, c.nrm, q=19, h_min=c.h_min)
+            m.run(30)
+            out.append(m.f.copy())
+    finally:
+        O.set_threads(1)
+    assert np.array_equal(out[0], out[1])

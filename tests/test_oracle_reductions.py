@@ -134,3 +134,60 @@ def test_traction_pointwise_closed_forms(small_cloud, small_stencils, grad_bnd):
     dA = O.area(c.r) / c.n_bnd
     F = O.drag(S[c.n_int:], grad_bnd, c.nrm, v, np.zeros(c.n), rho, nu, dA)
     assert np.abs(F - dA * t.sum(0)).max() <= 1e-14 * np.abs(F).max()
+
+
+def test_residual_monitors_closed_forms():
+    """mpfo_residual on the grain-free periodic fill: the divergence of the
+    linear field v = (aX, bY, cZ) is a + b + c at every node whose stencil
+    does not wrap (the derivative weights are exact on linear fields), and the
+    two maxima are plain maxima of |v| and |v - v_prev|.  A wrong weight row,
+    a missing component or a sum of squares without the root fails one of
+    them."""
+    c = nc.sphere_cloud(0.0, 0.05, 0.0, 0.05, seed=5)
+    S = nc.stencils(c.pos, 30)
+    d_raw = c.pos[S] - c.pos[S[:, :1]]
+    safe = np.all(np.abs(d_raw - nc.min_image(d_raw)) < 1e-12, axis=(1, 2))
+    w, _ = O.weights(c.pos, S, [("dx",), ("dy",), ("dz",), ("lap",)])
+    X, Y, Z = (c.pos - 0.5).T
+    a, b, cc = 0.9, -0.4, 0.25
+    v = np.stack([a * X, b * Y, cc * Z], 1)
+    # only the seam-free nodes as the "interior": reorder them first
+    order = np.concatenate([np.flatnonzero(safe), np.flatnonzero(~safe)])
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    S2, w2, v2 = inv[S[order]], w[order], v[order]
+    n_int = int(safe.sum())
+    assert n_int > 100
+    vp = v2 + 1e-3 * np.sin(np.arange(len(v2)))[:, None]
+    out = O.residual(n_int, S2, w2, v2, vp)
+    assert out[2] == pytest.approx(abs(a + b + cc), rel=1e-12)
+    assert out[1] == np.linalg.norm(v2[:n_int], axis=1).max()
+    assert out[0] == np.linalg.norm((v2 - vp)[:n_int], axis=1).max()
+    assert O.residual(n_int, S2, w2, v2)[0] == 0.0
+    # a divergence-free field (Y, Z, X) has zero divergence on those nodes
+    assert O.residual(n_int, S2, w2, np.stack([Y, Z, X], 1)[order])[2] < 1e-12
+
+
+def test_pointwise_difference_closed_forms():
+    """Eq. pointwise_error: a perturbation of size eps orthogonal to v_b gives
+    delta = eps / |v_b| exactly; delta is invariant under a common scaling
+    and zero for equal fields; the no-slip grain (both zero) gives 0 and a
+    non-zero difference over a zero velocity gives inf.  Swapping the two
+    fields changes the denominator, so the formula's orientation is pinned
+    too."""
+    rng = np.random.default_rng(7)
+    vb = rng.normal(size=(50, 3))
+    e = np.cross(vb, rng.normal(size=(50, 3)))  # orthogonal to v_b
+    e *= (0.01 * np.linalg.norm(vb, axis=1) / np.linalg.norm(e, axis=1))[:, None]
+    va = vb + e
+    d, dv = O.pointwise(va, vb)
+    assert np.allclose(d, 0.01, rtol=1e-13, atol=0)
+    assert np.allclose(dv, np.linalg.norm(e, axis=1), rtol=1e-12, atol=0)  # va - vb = e up to rounding
+    d3, _ = O.pointwise(3.7 * va, 3.7 * vb)
+    assert np.allclose(d3, d, rtol=1e-14, atol=0)
+    assert not O.pointwise(vb, vb)[0].any()
+    ds, _ = O.pointwise(vb, va)  # |v_a| = sqrt(1 + 1e-4) |v_b|
+    assert np.allclose(ds, 0.01 / np.sqrt(1 + 1e-4), rtol=1e-13, atol=0)
+    z = np.zeros((2, 3))
+    dz, _ = O.pointwise(np.array([[0.0, 0, 0], [1e-3, 0, 0]]), z)
+    assert dz[0] == 0.0 and dz[1] == np.inf
