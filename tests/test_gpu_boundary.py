@@ -220,3 +220,29 @@ def test_acm_kahan_parity_500_steps(api, disc_small, small_cloud):
     assert k_g == pytest.approx(k_o, rel=1e-6)
     v_true = g.v.double().cpu().numpy() + g.comp[:3].double().cpu().numpy()
     assert np.abs(v_true.T - o.v).max() < 1e-5 * np.abs(o.v).max()
+
+
+# ----------------------------------------------------------------- pointwise difference
+
+@pytest.mark.parametrize("dta, dtb", [(np.float64, np.float64), (np.float32, np.float64), (np.float32, np.float32)])
+def test_pointwise_difference_parity(api, dta, dtb):
+    """Eq. pointwise_error element by element against the oracle on seeded
+    fields (host inputs, rounded to each side's state type first), with zero
+    rows for the no-slip nodes, and the isocontour counts exact."""
+    rng = np.random.default_rng(13)
+    n, n_int = 70_001, 60_000
+    vb = rng.normal(size=(n, 3)) * rng.uniform(0.1, 2.0, size=(n, 1))
+    va = vb + rng.normal(size=(n, 3)) * rng.uniform(1e-4, 1.0, size=(n, 1))
+    va[n_int:] = vb[n_int:] = 0.0
+    va[n_int + 3] = (1e-3, 0.0, 0.0)  # a difference over a zero velocity
+    va, vb = va.astype(dta).astype(np.float64), vb.astype(dtb).astype(np.float64)
+    tdt = {np.float64: torch.float64, np.float32: torch.float32}
+    levels = (1.0, 0.25, 0.05, 0.1, 0.01)
+    d, dv, counts = api.pointwise(dev(va.T, tdt[dta]), dev(vb.T, tdt[dtb]), n_count=n_int, levels=levels)
+    d_o, dv_o = O.pointwise(va, vb)
+    d, dv = d.cpu().numpy(), dv.cpu().numpy()
+    fin = np.isfinite(d_o)
+    assert np.array_equal(fin, np.isfinite(d)) and d[n_int + 3] == np.inf
+    assert np.abs(d[fin] - d_o[fin]).max() <= 1e-14 * np.abs(d_o[fin]).max()
+    assert np.abs(dv - dv_o).max() <= 1e-14 * np.abs(dv_o).max()
+    assert counts == [int((d_o[:n_int] > t).sum()) for t in levels]
