@@ -408,6 +408,19 @@ size_t mpf_reduce_workspace(int64_t n_items);
 int mpf_scale(int64_t n, void* x, int precision, double c, void* stream);
 int mpf_flux_planes(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx, int precision,
                     int64_t n_all, double* q_out, void* ws, size_t ws_bytes, void* stream);
+/* The same reduction without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the block partials live in a static device array
+ * of the library, 64 KiB per GPU, held until the process ends, so this call
+ * allocates nothing.  ns may be at most mpf_flux_planes_noalloc_max() (2^21
+ * samples), otherwise MPF_ERR_WORKSPACE.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.  Nothing in it needs clearing between
+ * calls (every partial is written before it is read).  Arguments and result
+ * as for mpf_flux_planes. */
+int64_t mpf_flux_planes_noalloc_max(void);
+int mpf_flux_planes_noalloc(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx,
+                            int precision, int64_t n_all, double* q_out, void* stream);
 /* Permeability from the plane flux, Eq. k_definition: k / d^2 = q nu / (|g| d^2).
  * K from the drag, Eq. K_definition: K = F_x / (6 pi r phi q mu).  g_host
  * [3]; host-only; MPF_ERR_ARG for a zero force, d, r, phi, q or mu. */

@@ -118,7 +118,8 @@ def _load():
         "mpf_drag_coefficient": (i32, [dbl, dbl, dbl, dbl, dbl, vp]),
         "mpf_residual": (i32, [i64, i64, i32, vp, vp, vp, vp, i32, vp, vp, sz, vp]),
         "mpf_pointwise": (i32, [i64, vp, i32, vp, i32, vp, vp, i64, i32, vp, vp, vp]),
-
+        "mpf_flux_planes_noalloc_max": (i64, []),
+        "mpf_flux_planes_noalloc": (i32, [i64, i32, vp, vp, vp, i32, i64, vp, vp]),
         "mpf_lbm_unknown": (i32, [i32, i64, i64, vp, vp, i32, dbl, dbl, vp, vp]),
         "mpf_knn_workspace": (ctypes.c_size_t, [i64]),
         "mpf_knn": (i32, [vp, i64, i64, vp, i64, i64, i32, vp, i64, vp, ctypes.c_size_t, vp]),
@@ -164,7 +165,8 @@ def lib():
 
 
 EXPORTED = ["mpf_strerror", "mpf_version", "mpf_create", "mpf_destroy", "mpf_acm_dt", "mpf_lbm_units_of",
-            "mpf_permeability", "mpf_drag_coefficient", "mpf_residual", "mpf_pointwise",
+            "mpf_permeability", "mpf_drag_coefficient", "mpf_residual", "mpf_flux_planes_noalloc", "mpf_pointwise",
+            "mpf_flux_planes_noalloc_max",
             "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",
             "mpf_lbm_init", "mpf_lbm_init_fields", "mpf_lbm_run", "mpf_lbm_unknown", "mpf_lbm_moments",

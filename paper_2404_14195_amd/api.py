@@ -284,6 +284,17 @@ def flux_planes(s_idx, s_w, vx, n_all: int, q_out=None, ws=None):
     return q_out
 
 
+def flux_planes_noalloc(s_idx, s_w, vx, n_all: int, q_out):
+    """flux_planes without a workspace (the library's static partials);
+    allocates nothing, so q_out [1] f64 must be given."""
+    nl, ns = s_idx.shape
+    _need(s_w, torch.float64, (nl, ns), "s_w")
+    _need(q_out, torch.float64, (1,), "q_out")
+    check(lib().mpf_flux_planes_noalloc(ns, nl, _p(s_idx), _p(s_w), _p(vx), precision_of(vx.dtype), int(n_all),
+                                        _p(q_out), _stream()), "mpf_flux_planes_noalloc")
+    return q_out
+
+
 def pointwise(va, vb, n_count=None, levels=(), delta=None, dv=None):
     """Eq. pointwise_error on the device: (delta [n], dv [n], counts) with
     counts[l] the number of the first n_count nodes (default all) whose delta

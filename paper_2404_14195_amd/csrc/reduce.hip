@@ -5,6 +5,8 @@
 // tree into one partial, and one block then adds the partials in a fixed
 // order, so a rerun gives the same bits.  All accumulation is FP64 whatever
 // the precision of the fields.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace mpf {
@@ -458,6 +460,63 @@ extern "C" int mpf_pointwise(int64_t n, const void* va, int prec_a, const void* 
   else if (fa) launch_pointwise<float, double>(n, va, vb, delta, dv, n_count, n_levels, lv, counts, st);
   else if (fb) launch_pointwise<double, float>(n, va, vb, delta, dv, n_count, n_levels, lv, counts, st);
   else launch_pointwise<double, double>(n, va, vb, delta, dv, n_count, n_levels, lv, counts, st);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free flux
+// Block partial sums of mpf_flux_planes_noalloc live in a static device array
+// instead of a caller workspace.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in symbol): its device address is
+// looked up once per device with hipGetSymbolAddress, with that device
+// current, and kept in scratch_dev.
+namespace mpf {
+namespace {
+constexpr int64_t kScratchPartials = 8192;  // 64 KiB of partials: 2^21 samples
+static __device__ __align__(256) double scratch[kScratchPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_dev(double** out) {
+  int dev = 0;
+  MPF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return MPF_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    MPF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return MPF_ERR_HIP;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return MPF_OK;
+}
+}  // namespace
+}  // namespace mpf
+
+extern "C" int64_t mpf_flux_planes_noalloc_max(void) { return mpf::kScratchPartials * mpf::kRBlock; }
+
+extern "C" int mpf_flux_planes_noalloc(int64_t ns, int nl, const int32_t* s_idx, const double* s_w, const void* vx,
+                                       int precision, int64_t n_all, double* q_out, void* stream) {
+  using namespace mpf;
+  if (!q_out || ns < 0 || n_all < 1 || nl < 1 || (ns > 0 && (!s_idx || !s_w || !vx))) return MPF_ERR_ARG;
+  if (!precision_ok(precision)) return MPF_ERR_ARG;
+  if (ns > mpf_flux_planes_noalloc_max()) return MPF_ERR_WORKSPACE;
+  double* part = nullptr;
+  const int rc = scratch_dev(&part);
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  const unsigned g = grid_for(ns, kRBlock);  // every partial [0, g) is written before it is read
+  if (!state_is_f32(precision))
+    hipLaunchKernelGGL(flux_partial<double>, dim3(g), dim3(kRBlock), 0, st, ns, nl, s_idx, s_w, (const double*)vx,
+                       part);
+  else
+    hipLaunchKernelGGL(flux_partial<float>, dim3(g), dim3(kRBlock), 0, st, ns, nl, s_idx, s_w, (const float*)vx,
+                       part);
+  hipLaunchKernelGGL(finish_sum, dim3(1), dim3(256), 0, st, (const double*)part, (int64_t)g, 1, 1.0 / (double)n_all,
+                     q_out);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
