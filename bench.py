@@ -291,20 +291,21 @@ def _sweep_cell(args):
     return c
 
 
-def acm_sweep(torch, cells, steps=2000):
+def acm_sweep(torch, cells, steps=2000, nl=30):
     """ACM on the large cells across porosity: r in {0.2, 0.3, 0.4, 0.5, 0.55,
     0.6} (grains overlap their images above 1/2), h(d) = min(0.002 + 0.3 d,
-    0.008), N_L = 30: node-steps/s per precision and the permeability error of
-    FP32 and mixed against FP64 after the same steps."""
-    from paper_2404_14195_amd import MPF_F32, MPF_F64, MPF_MIXED
+    0.008), N_L = nl: node-steps/s per precision and the permeability error of
+    FP32, compensated FP32 and mixed against FP64 after the same steps (a
+    transient; the steady-state errors come from acm_steady)."""
+    from paper_2404_14195_amd import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED
     from paper_2404_14195_amd.solvers import ACMSolver, Discretization
     out = []
     for c in cells:
         t0 = time.perf_counter()
-        disc = Discretization(c, nl=30, M=64)
-        rec = {"r": c.r, "n": c.n, "n_boundary": c.n_bnd, "phi": disc.phi, "steps": steps}
-        for name, prec in (("fp64", MPF_F64), ("fp32", MPF_F32), ("mixed", MPF_MIXED)):
-            s = ACMSolver(disc, precision=prec)
+        disc = Discretization(c, nl=nl, M=64)
+        rec = {"r": c.r, "n": c.n, "n_boundary": c.n_bnd, "phi": disc.phi, "steps": steps, "nl": nl}
+        for name, prec in (("fp64", MPF_F64), ("fp32", MPF_F32), ("fp32_kahan", MPF_F32_KAHAN), ("mixed", MPF_MIXED)):
+            s = ACMSolver(disc, precision=prec, check=False)
             s.run(20)
             torch.cuda.synchronize()
             ev0 = torch.cuda.Event(enable_timing=True)
@@ -317,12 +318,52 @@ def acm_sweep(torch, cells, steps=2000):
             rec[name] = {"us_per_step": ms * 1e3 / (steps - 20), "node_steps_per_s": c.n * (steps - 20) / (ms * 1e-3),
                          "k": s.permeability()}
             del s
-        for name in ("fp32", "mixed"):
+        for name in ("fp32", "fp32_kahan", "mixed"):
             rec[name]["k_rel_err_vs_fp64"] = abs(rec[name]["k"] / rec["fp64"]["k"] - 1.0)
-        print(f"[bench] acm sweep r={c.r}: n={c.n} fp64 {rec['fp64']['us_per_step']:.0f} us/step, fp32 "
-              f"{rec['fp32']['us_per_step']:.0f}, mixed {rec['mixed']['us_per_step']:.0f}; k64={rec['fp64']['k']:.6e} "
-              f"err32={rec['fp32']['k_rel_err_vs_fp64']:.1e} errmix={rec['mixed']['k_rel_err_vs_fp64']:.1e} "
-              f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+        print(f"[bench] acm sweep r={c.r} nl={nl}: n={c.n} fp64 {rec['fp64']['us_per_step']:.0f} us/step, fp32 "
+              f"{rec['fp32']['us_per_step']:.0f}, kahan {rec['fp32_kahan']['us_per_step']:.0f}, mixed "
+              f"{rec['mixed']['us_per_step']:.0f}; k64={rec['fp64']['k']:.6e} "
+              f"err32={rec['fp32']['k_rel_err_vs_fp64']:.1e} errkahan={rec['fp32_kahan']['k_rel_err_vs_fp64']:.1e} "
+              f"errmix={rec['mixed']['k_rel_err_vs_fp64']:.1e} ({time.perf_counter() - t0:.1f}s)", file=sys.stderr,
+              flush=True)
+        out.append(rec)
+        del disc
+        torch.cuda.empty_cache()
+    return out
+
+
+def acm_steady(torch, clouds, nl=30, check=5000, tol=1e-9, max_steps=1_000_000, v_ref=1.0):
+    """The ACM's steady-state permeability per precision: every precision
+    from rest until k changes by at most tol (relative) per check, the
+    sound speed C = beta max(max|v|, v_ref) (v_ref = 1: C = 10, which settles
+    these cells), and the settled k of FP32, compensated FP32 and mixed
+    against FP64's.  clouds: [(name, cloud)]."""
+    from paper_2404_14195_amd import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization
+    say = lambda m: print(f"[bench] acm steady: {m}", file=sys.stderr, flush=True)
+    out = []
+    for cname, c in clouds:
+        disc = Discretization(c, nl=nl, M=64)
+        rec = {"cell": cname, "r": c.r, "n": c.n, "h_min": c.h_min, "nl": nl, "v_ref": v_ref, "check": check,
+               "tol": tol}
+        for name, prec in (("fp64", MPF_F64), ("fp32", MPF_F32), ("fp32_kahan", MPF_F32_KAHAN), ("mixed", MPF_MIXED)):
+            s = ACMSolver(disc, precision=prec, v_ref=v_ref)
+            t0 = time.perf_counter()
+            ks = []
+            while s.steps < max_steps:
+                s.run(check)
+                ks.append(s.permeability())
+                if len(ks) > 2 and abs(ks[-1] - ks[-2]) <= tol * abs(ks[-1]):
+                    break
+            rec[name] = {"k": ks[-1], "steps": s.steps, "seconds": time.perf_counter() - t0,
+                         "last_change": abs(ks[-1] - ks[-2]) / abs(ks[-1]) if len(ks) > 1 else None}
+            say(f"{cname} r={c.r} n={c.n} {name}: k={ks[-1]:.10e} after {s.steps} steps "
+                f"({rec[name]['seconds']:.1f}s)")
+            del s
+        for name in ("fp32", "fp32_kahan", "mixed"):
+            rec[name]["settled_rel_err_vs_fp64"] = abs(rec[name]["k"] / rec["fp64"]["k"] - 1.0)
+        say(f"{cname}: settled errors vs fp64: fp32 {rec['fp32']['settled_rel_err_vs_fp64']:.2e}, kahan "
+            f"{rec['fp32_kahan']['settled_rel_err_vs_fp64']:.2e}, mixed {rec['mixed']['settled_rel_err_vs_fp64']:.2e}")
         out.append(rec)
         del disc
         torch.cuda.empty_cache()
@@ -540,6 +581,73 @@ def hasimoto_check(torch, nc, radii=(0.1, 0.15), h0=0.012, slope=0.16, hmax=0.04
 
 # Physical times to the stopping criterion printed in Sec. 3.4 (h_min = 0.007).
 PAPER_STOP_TIME = {0.062: {"mlbm": 3.57, "acm": 3.58}, 0.6526: {"mlbm": 0.04, "acm": 0.39}}
+
+
+PAPER_ISOCONTOURS = {0.062: (0.1, 0.05, 0.01), 0.6526: (1.0, 0.25, 0.05)}
+
+
+def pointwise_study(torch, nc, radii, h=0.014, seed=1, nl=25, g=0.1, max_steps=3_000_000):
+    """The paper's pointwise comparison of the two solvers (Sec. 3.6, Eq.
+    pointwise_error) at its own setting: Gaussian clouds (Sec. 2.4) at
+    h_min = h, N_L = 25, MLBM as D3Q15 TRT with tau+ = 1 and Lambda = 1, the
+    ACM with C = 10 (v_ref = 1), |g| = 0.1, both in mixed precision from
+    rest to the paper's stopping criterion on identical nodes.  delta(x) is
+    computed on the GPU (mpf_pointwise) over the interior nodes; reported:
+    the fraction of nodes above the paper's isocontour levels, quantiles, and
+    the median by distance to the grain surface in units of h_min."""
+    import numpy as np
+    from paper_2404_14195_amd import MPF_MIXED, api
+    from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver, run_to_paper_criterion
+    say = lambda m: print(f"[bench] pointwise: {m}", file=sys.stderr, flush=True)
+    dt_mlbm_paper = (1.0 - 0.5) / 3.0 * (0.007 / 2) ** 2
+    dt_acm_paper = 0.1 * 0.007 ** 2 / 2.0
+    out = []
+    for r in radii:
+        cloud = nc.gauss_cloud(r, h, seed=seed)
+        disc = Discretization(cloud, nl=nl, M=64)
+        rec = {"r": r, "h_min": h, "n": cloud.n, "n_interior": cloud.n_int, "phi": disc.phi}
+        fields = {}
+        for name, make, dt_paper in (
+                ("mlbm", lambda: MLBMSolver(disc, q=15, precision=MPF_MIXED, magic=1.0, g=(g, 0.0, 0.0)),
+                 dt_mlbm_paper),
+                ("acm", lambda: ACMSolver(disc, precision=MPF_MIXED, v_ref=1.0, g=(g, 0.0, 0.0)), dt_acm_paper)):
+            t0 = time.perf_counter()
+            s = make()
+            every = max(1, round(1e4 * dt_paper / s.time_step))
+            res = run_to_paper_criterion(s, every=every, tol=1e-2, max_steps=max_steps,
+                                         log=lambda m: say(f"r={r} {name}: {m}"))
+            res.update(every=every, seconds=time.perf_counter() - t0)
+            F, K = s.drag()
+            res["K"] = float(K)
+            v = s.macros()[0] if name == "mlbm" else s.v
+            fields[name] = v.clone()
+            rec[name] = res
+            say(f"r={r} n={cloud.n} {name}: t={res['time']:.4f} ({res['steps']} steps), k={res['k']:.6e}, "
+                f"K={K:.4f}, {res['seconds']:.1f}s")
+            del s
+        levels = tuple(sorted(set(PAPER_ISOCONTOURS.get(r, ()) + (1.0, 0.1, 0.01)), reverse=True))
+        delta, dv, counts = api.pointwise(fields["mlbm"], fields["acm"], n_count=cloud.n_int, levels=levels)
+        dh = delta.cpu().numpy()[:cloud.n_int]
+        vn = fields["acm"].cpu().numpy()[:, :cloud.n_int]
+        dvh = dv.cpu().numpy()[:cloud.n_int]
+        dist = np.abs(nc.sphere_sdf(cloud.pos[:cloud.n_int], r)) / h
+        shells = {}
+        for lo, hi in ((0, 1), (1, 2), (2, 4), (4, 8), (8, 1e9)):
+            m = (dist >= lo) & (dist < hi)
+            if m.any():
+                shells[f"{lo}-{hi if hi < 1e9 else 'inf'}"] = {"nodes": int(m.sum()), "median": float(np.median(dh[m]))}
+        rec["delta"] = {"levels": list(levels), "fraction_above": [c / cloud.n_int for c in counts],
+                        "paper_isocontours": list(PAPER_ISOCONTOURS.get(r, ())),
+                        "quantiles": {str(q): float(np.quantile(dh, q)) for q in (0.1, 0.5, 0.9, 0.99)},
+                        "median_by_distance_in_h": shells,
+                        "velocity_rel_l2": float(np.sqrt((dvh ** 2).sum() / (vn ** 2).sum()))}
+        rec["k_mlbm_vs_acm"] = abs(rec["mlbm"]["k"] / rec["acm"]["k"] - 1)
+        rec["K_mlbm_vs_acm"] = abs(rec["mlbm"]["K"] / rec["acm"]["K"] - 1)
+        say(f"r={r}: delta " + json.dumps(rec["delta"]))
+        out.append(rec)
+        del disc, fields
+        torch.cuda.empty_cache()
+    return out
 
 
 def paper_stop_times(torch, nc, radii, hs, seed=1, nl=25, g=0.1, acm_v_ref=None, max_steps=3_000_000,
@@ -890,9 +998,17 @@ def main():
                     help="only the damped pressure equation for these sound-speed floors v_ref")
     ap.add_argument("--acm-sweep", action="store_true", help="only the ACM porosity sweep on ~2M-node cells")
     ap.add_argument("--acm-sweep-radii", type=float, nargs="+", default=[0.2, 0.3, 0.4, 0.5, 0.55, 0.6])
+    ap.add_argument("--acm-sweep-nl", type=int, nargs="+", default=[30])
+    ap.add_argument("--acm-steady", action="store_true",
+                    help="only the ACM's steady-state k per precision (the 8k-node cell and C3-shaped cells)")
+    ap.add_argument("--acm-steady-radii", type=float, nargs="+", default=[0.55])
+    ap.add_argument("--acm-steady-h0", type=float, default=0.005)
     ap.add_argument("--paper-stop", type=float, nargs="+", default=None, metavar="R",
                     help="physical time to the paper's stopping criterion on these radii (both solvers)")
     ap.add_argument("--paper-stop-h", type=float, nargs="+", default=[0.014])
+    ap.add_argument("--pointwise", type=float, nargs="+", default=None, metavar="R",
+                    help="only the paper's pointwise solver difference (Eq. pointwise_error) on these radii")
+    ap.add_argument("--pointwise-h", type=float, default=0.014)
     ap.add_argument("--paper-stop-solvers", nargs="+", default=["mlbm", "acm"])
     ap.add_argument("--paper-stop-acm-vref", type=float, default=None)
     ap.add_argument("--hasimoto", action="store_true",
@@ -931,7 +1047,17 @@ def main():
                 cells = pool.map(_sweep_cell, [(r,) for r in args.acm_sweep_radii])
         print(f"[bench] acm sweep: {[c.n for c in cells]} nodes", file=sys.stderr, flush=True)
         torch.cuda.set_device(0)
-        print(json.dumps({"acm_sweep": acm_sweep(torch, cells)}))
+        print(json.dumps({"acm_sweep": [rec for nl in args.acm_sweep_nl for rec in acm_sweep(torch, cells, nl=nl)]}))
+        return
+    if args.acm_steady:
+        torch.cuda.set_device(0)
+        # the plain-ACM workload cell, and cells of the porosity sweep's shape
+        # (h(d) = min(h0 + 0.3 d, 4 h0), seed 3) at a coarser h0
+        clouds = [("acm_small", nc.config_cloud("acm_small"))] + \
+                 [(f"sweep_r{r}_h{args.acm_steady_h0}", nc.sphere_cloud(r, args.acm_steady_h0, 0.3,
+                                                                        4 * args.acm_steady_h0, seed=3))
+                  for r in args.acm_steady_radii]
+        print(json.dumps({"acm_steady": acm_steady(torch, clouds)}))
         return
     if args.weights_cell:
         torch.cuda.set_device(0)
@@ -955,6 +1081,10 @@ def main():
         print(json.dumps({"paper_stop": paper_stop_times(torch, nc, args.paper_stop, args.paper_stop_h,
                                                          acm_v_ref=args.paper_stop_acm_vref,
                                                          solvers=tuple(args.paper_stop_solvers))}))
+        return
+    if args.pointwise:
+        torch.cuda.set_device(0)
+        print(json.dumps({"pointwise": pointwise_study(torch, nc, args.pointwise, h=args.pointwise_h)}))
         return
     if args.edac_vref_sweep:
         torch.cuda.set_device(0)

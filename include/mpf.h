@@ -311,6 +311,32 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
                 const int32_t* sn, const void* wn, void* v, void* p, void* comp, double* vmax, uint32_t* flags,
                 int n_steps, void* ws, size_t ws_bytes, void* stream);
 
+/* Tile plan of the LDS-staged stencil gather.  The MLBM step works on tiles
+ * of 64 consecutive nodes; a tile's stencils (Sec. 2.1) name few distinct
+ * nodes (about 350 for 64 x 30 entries on the refined clouds here).  The
+ * plan lists each tile's distinct stencil nodes in ascending order (its
+ * halo) and every stencil entry as its 16-bit position in that list, so a
+ * step copies the halo's records into LDS with contiguous loads and gathers
+ * from LDS.  Built once per stencil set:
+ *   count dev int32 [G + 1], G = mpf_tile_count(n): halo sizes, and in
+ *         count[G] the largest (also returned in *h_max_host)
+ *   halo  dev int32 [G][h_cap]: the halo of tile t in halo[t][0, count[t])
+ *   lidx  dev uint16 [nl][n]: sten[j][i] == halo[i / 64][lidx[j][i]]
+ * sten dev [nl][n]; 1 <= nl <= 64; 64 <= h_cap <= 4096.  The call waits for
+ * the stream (it reads back the largest halo) and returns
+ * MPF_ERR_UNSUPPORTED if a tile's halo exceeds h_cap (the plan is then
+ * incomplete and must not be used). */
+typedef struct {
+  const int32_t* count;
+  const int32_t* halo;
+  const uint16_t* lidx;
+  int32_t h_cap; /* row length of halo */
+  int32_t h_max; /* the largest halo, as mpf_tile_plan returned it */
+} mpf_tiles;
+int64_t mpf_tile_count(int64_t n);
+int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* count, int32_t* halo, uint16_t* lidx,
+                  int32_t* h_max_host, void* stream);
+
 /* ------------------------------------------------------------- MLBM step
  * Meshless lattice Boltzmann steps with TRT collision (Sec. 2.2, Eqs.
  * LBM_streaming, LBM_collision, feq, macro_var, force_lbm,
@@ -339,6 +365,11 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  * flags dev uint32 [1] or NULL: bit 0 when a collided node has a non-finite
  *       density or velocity, bit 1 when |u|^2 >= 1/3 there (see the flags
  *       word above; MPF_ERR_DIVERGED when set at the end of the call)
+ * tiles host pointer to the tile plan of sten (mpf_tile_plan), or NULL: the
+ *       step then stages each tile's halo records in LDS and gathers from
+ *       there when the largest halo's records fit 64 KiB, and reads the
+ *       neighbours' records through the caches otherwise (and without a
+ *       plan).  Results are the same bit for bit either way.
  * q is 15 or 19.  A W larger than 512 MiB (twice the Infinity Cache) is read
  * with non-temporal loads so that it does not evict the gathered population
  * records; the results are the same bit for bit either way. */
@@ -358,8 +389,8 @@ int mpf_lbm_init(const mpf_lbm_params* prm, int64_t n, double rho, const double*
 int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const double* v, const double* p, double vel_scale,
                         void* f, void* stream);
 int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* W,
-                const uint32_t* unknown, void* f, void* f_tmp, void* comp, uint32_t* flags, int n_steps,
-                void* stream);
+                const uint32_t* unknown, const mpf_tiles* tiles, void* f, void* f_tmp, void* comp, uint32_t* flags,
+                int n_steps, void* stream);
 /* Lattice units of Sec. 2.2 (Eqs. lbm_viscosity and conversion_factors) for
  * a cloud of smallest spacing h_min: dx = h_min / 2, nu_lb = (tau+ - 1/2) / 3,
  * dt = nu_lb dx^2 / nu, g_lb = g dt^2 / dx, vel_scale = dx / dt (physical

@@ -380,3 +380,20 @@ def pointwise(va, vb):
     delta, dv = np.zeros(n), np.zeros(n)
     _load().mpfo_pointwise(n, va.ctypes.data, vb.ctypes.data, delta.ctypes.data, dv.ctypes.data)
     return delta, dv
+
+
+def tile_plan(sten, tile: int = 64):
+    """The tile plan of a stencil set, from its definition: tiles of `tile`
+    consecutive nodes; halo of a tile = the ascending distinct node indices
+    its stencils name; lidx[i][j] = position of sten[i][j] in the halo of
+    node i's tile.  sten [n][nl].  Returns (halos: list of arrays, lidx
+    [n][nl])."""
+    sten = np.asarray(sten)
+    n = len(sten)
+    halos, lidx = [], np.empty_like(sten)
+    for t0 in range(0, n, tile):
+        rows = sten[t0:t0 + tile]
+        h = np.unique(rows)
+        halos.append(h)
+        lidx[t0:t0 + tile] = np.searchsorted(h, rows)
+    return halos, lidx

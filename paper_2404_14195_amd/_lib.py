@@ -12,7 +12,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _INC = os.path.join(os.path.dirname(_HERE), "include")
 SO_PATH = os.path.join(_HERE, "libmpf.so")
-SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip", "knn.hip"]
+SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip", "knn.hip", "tiles.hip"]
 
 MPF_F64, MPF_F32, MPF_MIXED, MPF_F32_KAHAN = 0, 1, 2, 3
 MPF_ERR_DIVERGED = -4
@@ -86,6 +86,11 @@ class LbmParams(ctypes.Structure):
                 ("tau_minus", ctypes.c_double), ("g_lb", ctypes.c_double * 3)]
 
 
+class Tiles(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_void_p), ("halo", ctypes.c_void_p), ("lidx", ctypes.c_void_p),
+                ("h_cap", ctypes.c_int32), ("h_max", ctypes.c_int32)]
+
+
 class LbmUnits(ctypes.Structure):
     _fields_ = [("dx", ctypes.c_double), ("dt", ctypes.c_double), ("nu_lb", ctypes.c_double),
                 ("tau_minus", ctypes.c_double), ("vel_scale", ctypes.c_double), ("g_lb", ctypes.c_double * 3)]
@@ -112,7 +117,9 @@ def _load():
         "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
         "mpf_lbm_init": (i32, [vp, i64, dbl, vp, vp, vp]),
         "mpf_lbm_init_fields": (i32, [vp, i64, vp, vp, dbl, vp, vp]),
-        "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
+        "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
+        "mpf_tile_count": (i64, [i64]),
+        "mpf_tile_plan": (i32, [i64, i32, vp, i32, vp, vp, vp, vp, vp]),
         "mpf_lbm_units_of": (i32, [dbl, dbl, dbl, dbl, vp, vp]),
         "mpf_permeability": (i32, [dbl, dbl, vp, dbl, vp]),
         "mpf_drag_coefficient": (i32, [dbl, dbl, dbl, dbl, dbl, vp]),
@@ -166,6 +173,7 @@ def lib():
 
 EXPORTED = ["mpf_strerror", "mpf_version", "mpf_create", "mpf_destroy", "mpf_acm_dt", "mpf_lbm_units_of",
             "mpf_permeability", "mpf_drag_coefficient", "mpf_residual", "mpf_flux_planes_noalloc", "mpf_pointwise",
+            "mpf_tile_count", "mpf_tile_plan",
             "mpf_flux_planes_noalloc_max",
             "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",

@@ -8,8 +8,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, AcmParams, LbmParams, LbmUnits, WGeom, WTune, check,
-                   ctx, lib, make_ops)
+from ._lib import (MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, AcmParams, LbmParams, LbmUnits, Tiles, WGeom, WTune,
+                   check, ctx, lib, make_ops)
 
 # element type of the state (fields, populations) and of the stencil weights
 _ST = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64, MPF_F32_KAHAN: torch.float32}
@@ -225,9 +225,30 @@ def lbm_units(h_min: float, nu: float, tau_plus: float, g, magic: float) -> dict
                 vel_scale=out.vel_scale)
 
 
-def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int, comp=None, flags=None):
+class TilePlan:
+    """The tile plan of a stencil set (mpf_tile_plan): device arrays and the
+    mpf_tiles record that points at them."""
+
+    def __init__(self, sten, h_cap: int = 1024):
+        nl, n = sten.shape
+        _need(sten, torch.int32, name="sten")
+        G = int(lib().mpf_tile_count(n))
+        self.count = torch.empty(G + 1, dtype=torch.int32, device=sten.device)
+        self.halo = torch.empty((G, h_cap), dtype=torch.int32, device=sten.device)
+        self.lidx = torch.empty((nl, n), dtype=torch.int16, device=sten.device)  # the uint16 pattern
+        hmax = ctypes.c_int32()
+        check(lib().mpf_tile_plan(n, nl, _p(sten), int(h_cap), _p(self.count), _p(self.halo), _p(self.lidx),
+                                  ctypes.byref(hmax), _stream()), "mpf_tile_plan")
+        self.h_cap, self.h_max = int(h_cap), hmax.value
+        self.rec = Tiles(count=_p(self.count), halo=_p(self.halo), lidx=_p(self.lidx), h_cap=self.h_cap,
+                         h_max=self.h_max)
+
+
+def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int, comp=None, flags=None,
+            tiles: TilePlan | None = None):
     """unknown: [n - n_int] int32 bit masks from lbm_unknown; comp: [n][qp]
-    float32 for MPF_F32_KAHAN; flags: [1] int32 or None."""
+    float32 for MPF_F32_KAHAN; flags: [1] int32 or None; tiles: the plan of
+    sten for the LDS-staged gather, or None."""
     dt = _ST[prm.precision]
     nl, n = sten.shape
     _need(W, _WT[prm.precision], (prm.q - 1, nl, n), "W")
@@ -239,8 +260,9 @@ def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int
         _need(comp, torch.float32, (n, record_len(prm.q)), "comp")
     if flags is not None:
         _need(flags, torch.int32, (1,), "flags")
-    check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(unknown), _p(f), _p(f_tmp),
-                            _p(comp), _p(flags), int(n_steps), _stream()), "mpf_lbm_run")
+    check(lib().mpf_lbm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(W), _p(unknown),
+                            None if tiles is None else ctypes.byref(tiles.rec), _p(f), _p(f_tmp), _p(comp), _p(flags),
+                            int(n_steps), _stream()), "mpf_lbm_run")
 
 
 def lbm_unknown(q: int, pos, n_int: int, nrm=None, rule: str = "normal", dx: float = 0.0, r: float = 0.0):

@@ -231,15 +231,31 @@ inline unsigned tiles_grid(int64_t n) {
 // streaming them then costs 6-50 %; weights far larger than it are read from
 // HBM anyway, and streaming them keeps the gathered population records in the
 // caches (6 % faster at 1.26-2.5 GB of weights, all precisions).
-template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W, bool KAHAN>
+// The tile plan of the LDS-staged gather (HALO): count[t] distinct stencil
+// nodes of tile t, listed ascending in halo[t][0, count), and every stencil
+// entry as its 16-bit position in its tile's list.
+struct TileArg {
+  const int32_t* count;
+  const int32_t* halo;
+  const uint16_t* lidx;
+  int h_cap;
+};
+
+// LDS of the step kernel: the waves' partial sums, and with HALO first the
+// tile's halo records (the partial sums reuse that space afterwards).
+template <typename TW, typename T, int Q>
+constexpr size_t step_part_bytes() { return sizeof(T) * step_waves<TW, T>() * (Q - 1) * kTile; }
+
+template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W, bool KAHAN, bool HALO>
 __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(
     int64_t n, int64_t n_int, int nl, const int32_t* __restrict__ sten, const TW* __restrict__ W,
     const uint32_t* __restrict__ unknown, const T* __restrict__ src, T* __restrict__ dst, T* __restrict__ comp,
-    Prm<typename Compute<T, KAHAN>::type> pr, uint32_t* __restrict__ flags) {
+    Prm<typename Compute<T, KAHAN>::type> pr, uint32_t* __restrict__ flags, TileArg tp) {
   using CT = typename Compute<T, KAHAN>::type;
   constexpr int QP = Pad<Q>::QP;
   constexpr int NW = step_waves<TW, T>();
-  __shared__ T part[NW][Q - 1][kTile];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T(*part)[Q - 1][kTile] = reinterpret_cast<T(*)[Q - 1][kTile]>(lds_raw);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile * kTile >= n) return;  // whole block
   const int lane = threadIdx.x & (kWave - 1);
@@ -248,15 +264,34 @@ __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(
   const bool live = i < n;
   const int64_t ic = live ? i : n - 1;
   const int64_t ks = (int64_t)nl * n;  // population stride in W
+  T* recs = reinterpret_cast<T*>(lds_raw);
+  if constexpr (HALO) {
+    // the tile's halo records into LDS, 16 bytes per thread per pass:
+    // consecutive threads take consecutive pieces of ascending records
+    using V = typename Vec16<T>::type;
+    constexpr int NV = QP / Vec16<T>::n;
+    const int cnt = tp.count[tile];
+    const int32_t* hl = tp.halo + tile * tp.h_cap;
+    V* dstv = reinterpret_cast<V*>(recs);
+    for (int c = threadIdx.x; c < cnt * NV; c += NW * kWave) {
+      const int r = c / NV;
+      dstv[c] = reinterpret_cast<const V*>(src + (int64_t)hl[r] * QP)[c - r * NV];
+    }
+    __syncthreads();
+  }
   T acc[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) acc[k] = T(0);
 #pragma unroll 1
   for (int j = wv; j < nl; j += NW) {
     const int64_t at = (int64_t)j * n + ic;
-    const int64_t s = sten[at];
     T r[QP];
-    load_rec<T, QP>(src + s * QP, r);
+    if constexpr (HALO) {
+      load_rec<T, QP>(recs + (int)tp.lidx[at] * QP, r);
+    } else {
+      const int64_t s = sten[at];
+      load_rec<T, QP>(src + s * QP, r);
+    }
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const TW* wk = W + (k - 1) * ks + at;
@@ -266,6 +301,7 @@ __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(
       acc[k] += (T)w * r[k];
     }
   }
+  if constexpr (HALO) __syncthreads();  // every wave is done with the records before they are overwritten
 #pragma unroll
   for (int k = 1; k < Q; ++k) part[wv][k - 1][lane] = acc[k];
   __syncthreads();
@@ -424,25 +460,32 @@ __global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int
 // and where streaming wins (1.26 GB).
 constexpr double kStreamWeightsBytes = 512.0 * 1024 * 1024;
 
-template <typename TW, typename T, int Q, bool STREAM_W, bool KAHAN>
+// LDS staging is used when the largest halo fits this many bytes of
+// records: 64 KiB keeps three 8-wave FP32 blocks per CU at the step kernel's
+// register use, and holds halos of up to 819 FP32 or 409 FP64 records
+// (the refined clouds here: about 350 on average, 500 at most).
+constexpr size_t kHaloLdsBytes = 64 * 1024;
+
+template <typename TW, typename T, int Q, bool STREAM_W, bool KAHAN, bool HALO>
 void launch_steps(int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W, const uint32_t* unknown,
                   T* f, T* ft, T* comp, T* cur, int n_steps, const Prm<typename Compute<T, KAHAN>::type>& pr,
-                  uint32_t* flags, hipStream_t st) {
+                  uint32_t* flags, const TileArg& tp, size_t lds, hipStream_t st) {
   const unsigned gt = tiles_grid(n);
   const dim3 blk(step_waves<TW, T>() * kWave);
   for (int s = 0; s < n_steps - 1; ++s) {
     T* nxt = cur == f ? ft : f;
-    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W, KAHAN>), dim3(gt), blk, 0, st, n, n_int, nl, sten, W,
-                       unknown, (const T*)cur, nxt, comp, pr, flags);
+    hipLaunchKernelGGL((lbm_step<TW, T, Q, true, STREAM_W, KAHAN, HALO>), dim3(gt), blk, lds, st, n, n_int, nl,
+                       sten, W, unknown, (const T*)cur, nxt, comp, pr, flags, tp);
     cur = nxt;
   }
-  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W, KAHAN>), dim3(gt), blk, 0, st, n, n_int, nl, sten, W,
-                     unknown, (const T*)cur, f, comp, pr, flags);
+  hipLaunchKernelGGL((lbm_step<TW, T, Q, false, STREAM_W, KAHAN, HALO>), dim3(gt), blk, lds, st, n, n_int, nl, sten,
+                     W, unknown, (const T*)cur, f, comp, pr, flags, tp);
 }
 
 template <typename TW, typename T, int Q, bool KAHAN>
 int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W,
-        const uint32_t* unknown, T* f, T* ft, T* comp, uint32_t* flags, int n_steps, hipStream_t st) {
+        const uint32_t* unknown, const mpf_tiles* tiles, T* f, T* ft, T* comp, uint32_t* flags, int n_steps,
+        hipStream_t st) {
   using CT = typename Compute<T, KAHAN>::type;
   Prm<CT> pr{(CT)(1.0 / prm->tau_plus), (CT)(1.0 / prm->tau_minus), (CT)prm->g_lb[0], (CT)prm->g_lb[1],
              (CT)prm->g_lb[2]};
@@ -451,10 +494,29 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   // ft, and the last (stream-only) pass lands in f
   T* cur = (n_steps - 1) % 2 == 0 ? ft : f;
   hipLaunchKernelGGL((lbm_collide<T, CT, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, cur, comp, pr, flags);
-  if ((double)(Q - 1) * nl * n * sizeof(TW) > kStreamWeightsBytes)
-    launch_steps<TW, T, Q, true, KAHAN>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr, flags, st);
-  else
-    launch_steps<TW, T, Q, false, KAHAN>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr, flags, st);
+  constexpr int QP = Pad<Q>::QP;
+  const size_t part = step_part_bytes<TW, T, Q>();
+  const size_t halo_bytes = tiles ? (size_t)tiles->h_max * QP * sizeof(T) : 0;
+  const bool halo = tiles && halo_bytes <= kHaloLdsBytes;
+  const TileArg tp{tiles ? tiles->count : nullptr, tiles ? tiles->halo : nullptr, tiles ? tiles->lidx : nullptr,
+                   tiles ? tiles->h_cap : 0};
+  const size_t lds = halo ? (halo_bytes > part ? halo_bytes : part) : part;
+  const bool stream_w = (double)(Q - 1) * nl * n * sizeof(TW) > kStreamWeightsBytes;
+  if (halo) {
+    if (stream_w)
+      launch_steps<TW, T, Q, true, KAHAN, true>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr, flags,
+                                                tp, lds, st);
+    else
+      launch_steps<TW, T, Q, false, KAHAN, true>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr,
+                                                 flags, tp, lds, st);
+  } else {
+    if (stream_w)
+      launch_steps<TW, T, Q, true, KAHAN, false>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr,
+                                                 flags, tp, lds, st);
+    else
+      launch_steps<TW, T, Q, false, KAHAN, false>(n, n_int, nl, sten, W, unknown, f, ft, comp, cur, n_steps, pr,
+                                                  flags, tp, lds, st);
+  }
   MPF_LAUNCH_CHECK();
   return check_flags(flags, st);
 }
@@ -514,8 +576,8 @@ extern "C" int mpf_lbm_init_fields(const mpf_lbm_params* prm, int64_t n, const d
 }
 
 extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
-                           const void* W, const uint32_t* unknown, void* f, void* f_tmp, void* comp,
-                           uint32_t* flags, int n_steps, void* stream) {
+                           const void* W, const uint32_t* unknown, const mpf_tiles* tiles, void* f, void* f_tmp,
+                           void* comp, uint32_t* flags, int n_steps, void* stream) {
   using namespace mpf;
   if (!prm || !sten || !W || !f || !f_tmp || n < 1 || n_int < 0 || n_int > n || nl < 1 || n_steps < 0)
     return MPF_ERR_ARG;
@@ -523,20 +585,23 @@ extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, 
   if (!(prm->tau_plus > 0.5) || !(prm->tau_minus > 0.5)) return MPF_ERR_ARG;
   if (!precision_ok(prm->precision)) return MPF_ERR_ARG;
   if ((prm->precision == MPF_F32_KAHAN) != (comp != nullptr)) return MPF_ERR_ARG;
+  if (tiles && (!tiles->count || !tiles->halo || !tiles->lidx || tiles->h_cap < 64 || tiles->h_max < 1 ||
+                tiles->h_max > tiles->h_cap))
+    return MPF_ERR_ARG;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);
   return with_q(prm->q, [&](auto qc) {
     constexpr int Q = decltype(qc)::value;
     if (prm->precision == MPF_F64)
-      return run<double, double, Q, false>(prm, n, n_int, nl, sten, (const double*)W, unknown, (double*)f,
+      return run<double, double, Q, false>(prm, n, n_int, nl, sten, (const double*)W, unknown, tiles, (double*)f,
                                            (double*)f_tmp, nullptr, flags, n_steps, st);
     if (prm->precision == MPF_MIXED)
-      return run<float, double, Q, false>(prm, n, n_int, nl, sten, (const float*)W, unknown, (double*)f,
+      return run<float, double, Q, false>(prm, n, n_int, nl, sten, (const float*)W, unknown, tiles, (double*)f,
                                           (double*)f_tmp, nullptr, flags, n_steps, st);
     if (prm->precision == MPF_F32_KAHAN)
-      return run<float, float, Q, true>(prm, n, n_int, nl, sten, (const float*)W, unknown, (float*)f, (float*)f_tmp,
+      return run<float, float, Q, true>(prm, n, n_int, nl, sten, (const float*)W, unknown, tiles, (float*)f, (float*)f_tmp,
                                         (float*)comp, flags, n_steps, st);
-    return run<float, float, Q, false>(prm, n, n_int, nl, sten, (const float*)W, unknown, (float*)f, (float*)f_tmp,
+    return run<float, float, Q, false>(prm, n, n_int, nl, sten, (const float*)W, unknown, tiles, (float*)f, (float*)f_tmp,
                                        nullptr, flags, n_steps, st);
   });
 }

@@ -37,6 +37,7 @@ class Discretization:
         # interior rows: nl nearest nodes; surface rows: self + nl - 1 nearest interior nodes
         self.sten = api.solver_stencils(self.pos, self.n_int, nl)
         self._sten_host = None
+        self._tiles = None
         self.nrm = t(cloud.nrm.T, torch.float64) if self.nb else torch.zeros((3, 0), dtype=torch.float64,
                                                                                device=self.device)
         # the Neumann rows and the drag's gradient rows use the surface stencils
@@ -51,6 +52,14 @@ class Discretization:
             self.s_w = api.rbffd_weights(self.pos, self.s_idx, [("shift_row",)], rowvec=self.s_shift)[0][0].contiguous()
         self.phi, self.area = api.sc_cell(cloud.r) if cloud.r > 0 else (1.0, 0.0)
         self.red_ws = api.reduce_workspace(max(self.n, 5 * M * M), self.device)
+
+    @property
+    def tiles(self):
+        """The tile plan of the stencils for the LDS-staged gather (built on
+        first use, once per discretization)."""
+        if self._tiles is None:
+            self._tiles = api.TilePlan(self.sten)
+        return self._tiles
 
     @property
     def sten_host(self):
@@ -186,8 +195,8 @@ class MLBMSolver:
 
     def __init__(self, disc: Discretization, q=19, precision: int = MPF_F64, nu=1.0, tau_plus=1.0, magic=0.25,
                  g=(1.0, 0.0, 0.0), dx=None, W=None, streaming: str = "shift", rule: str = "normal",
-                 check: bool = True):
-        self.d, self.q, self.precision, self.check = disc, q, precision, check
+                 check: bool = True, staged: bool = True):
+        self.d, self.q, self.precision, self.check, self.staged = disc, q, precision, check, staged
         h = disc.cloud.h_min if dx is None else 2.0 * dx
         self.units = u = lbm_units(h, nu, tau_plus, g, magic)
         self.nu, self.g = nu, tuple(g)
@@ -226,7 +235,8 @@ class MLBMSolver:
 
     def run(self, n_steps: int):
         api.lbm_run(self.prm, self.d.n_int, self.d.sten, self.W, self.unknown, self.f, self.f_tmp, n_steps,
-                    comp=self.comp, flags=self.flags if self.check else None)
+                    comp=self.comp, flags=self.flags if self.check else None,
+                    tiles=self.d.tiles if self.staged else None)
         self.steps += n_steps
 
     @property

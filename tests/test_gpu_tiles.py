@@ -1,0 +1,65 @@
+"""The tile plan of the LDS-staged gather (mpf_tile_plan) against the
+oracle's definition, bit for bit, and the MLBM step with and without it:
+the staged records are the same values read from LDS, so every precision
+gives the same populations bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import nodecloud as nc
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def disc(small_cloud):
+    from paper_2404_14195_amd.solvers import Discretization
+    assert torch.cuda.is_available()
+    return Discretization(small_cloud, nl=30, M=32)
+
+
+@pytest.mark.parametrize("nl", [30, 25, 50])
+def test_tile_plan_equals_the_definition(small_cloud, nl):
+    """Halo lists and 16-bit positions equal the oracle's, on the 8k-node
+    cell (ragged last tile) and for the host fixture's stencils."""
+    from paper_2404_14195_amd import api
+    S = nc.solver_stencils(small_cloud, nl)
+    plan = api.TilePlan(torch.as_tensor(np.ascontiguousarray(S.T), dtype=torch.int32, device="cuda"))
+    halos, lidx = O.tile_plan(S, 64)
+    count = plan.count.cpu().numpy()
+    assert len(count) == len(halos) + 1 and count[-1] == max(len(h) for h in halos) == plan.h_max
+    halo = plan.halo.cpu().numpy()
+    for t, h in enumerate(halos):
+        assert count[t] == len(h) and np.array_equal(halo[t, :len(h)], h)
+    assert np.array_equal(plan.lidx.cpu().numpy().astype(np.uint16).T, lidx.astype(np.uint16))
+
+
+def test_tile_plan_rejects_a_small_cap(small_cloud):
+    from paper_2404_14195_amd import MPFError, api
+    S = nc.solver_stencils(small_cloud, 30)
+    with pytest.raises(MPFError, match="unsupported"):
+        api.TilePlan(torch.as_tensor(np.ascontiguousarray(S.T), dtype=torch.int32, device="cuda"), h_cap=64)
+
+
+@pytest.mark.parametrize("precision, q", [(0, 19), (1, 19), (2, 19), (3, 19), (1, 15), (0, 15)])
+def test_staged_step_equals_cached_gather(disc, precision, q):
+    from paper_2404_14195_amd.solvers import MLBMSolver
+    a = MLBMSolver(disc, q=q, precision=precision, staged=True)
+    b = MLBMSolver(disc, q=q, precision=precision, staged=False)
+    for s in (a, b):
+        s.run(37)
+    assert torch.equal(a.f, b.f)
+    if a.comp is not None:
+        assert torch.equal(a.comp, b.comp)

@@ -76,11 +76,11 @@ def test_host_argument_checks(lib):
     assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, None, fake, None, 1, fake, 1 << 20,
                            None) == -1
     lp = LbmParams(q=17, precision=0, tau_plus=1.0, tau_minus=1.0)
-    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, None, None, 1, None) == -1
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1
     lp.q, lp.tau_plus = 19, 0.5
-    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, None, None, 1, None) == -1
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1
     lp.tau_plus = 1.0
-    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 8, 30, fake, fake, None, fake, fake, None, None, 1, None) == -1  # no masks
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 8, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1  # no masks
     # unknown-population masks: rule, q, normals, dx and r are checked first
     assert lib.mpf_lbm_unknown(19, 10, 10, None, None, 0, 0.0, 0.0, None, None) == 0  # no boundary nodes
     assert lib.mpf_lbm_unknown(19, 10, 8, fake, None, 0, 0.0, 0.0, fake, None) == -1  # normal rule needs nrm
@@ -177,11 +177,11 @@ def test_compensated_state_and_flags_checks(lib):
     # the compensated workspace also holds the v and v' remainders
     assert lib.mpf_acm_workspace(1000, MPF_F32_KAHAN) >= 17 * 1000 * 4
     lp = LbmParams(q=19, precision=MPF_F32_KAHAN, tau_plus=1.0, tau_minus=1.0)
-    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, None, None, 1, None) == -1
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1
     lp.precision = 0
-    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, fake, None, 1, None) == -1
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, fake, None, 1, None) == -1
     lp.precision = 4
-    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, fake, fake, None, None, 1, None) == -1
+    assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1
     assert lib.mpf_scale(0, fake, MPF_F32_KAHAN, 2.0, None) == 0
 
 
@@ -252,3 +252,13 @@ def test_pointwise_host_checks(lib):
     assert lib.mpf_pointwise(10, fake, 0, fake, 0, fake, None, 10, 17, lv, fake, None) == -1  # at most 16 levels
     assert lib.mpf_pointwise(10, fake, 0, fake, 0, fake, None, 11, 2, lv, fake, None) == -1   # n_count > n
     assert lib.mpf_pointwise(10, fake, 0, fake, 0, fake, None, 10, 2, lv, None, None) == -1   # counts missing
+
+
+def test_tile_plan_host_checks(lib):
+    fake = ctypes.c_void_p(0x1000)
+    hm = ctypes.c_int32()
+    assert lib.mpf_tile_count(0) == 0 and lib.mpf_tile_count(64) == 1 and lib.mpf_tile_count(65) == 2
+    assert lib.mpf_tile_plan(100, 65, fake, 1024, fake, fake, fake, ctypes.byref(hm), None) == -1  # nl <= 64
+    assert lib.mpf_tile_plan(100, 30, fake, 63, fake, fake, fake, ctypes.byref(hm), None) == -1    # h_cap >= 64
+    assert lib.mpf_tile_plan(100, 30, fake, 4097, fake, fake, fake, ctypes.byref(hm), None) == -1
+    assert lib.mpf_tile_plan(100, 30, None, 1024, fake, fake, fake, ctypes.byref(hm), None) == -1

@@ -75,3 +75,20 @@ def test_host_fixture_tie_order_on_a_lattice(k):
     n = 8
     pts = np.array(list(itertools.product(range(n), repeat=3))) / n
     assert np.array_equal(nc.stencils(pts, k), O.knn(pts, k))
+
+
+def test_tile_plan_definition_by_brute_force():
+    """The oracle's tile plan against a pure-Python construction (set, sort,
+    list.index) on a small cloud with a ragged last tile: every halo is the
+    sorted set of its tile's stencil entries and every entry maps back."""
+    c = nc.sphere_cloud(0.3, 0.05, 0.3, 0.1, seed=1)
+    S = nc.solver_stencils(c, 20)[:300]  # 4 full tiles and a ragged one of 44
+    halos, lidx = O.tile_plan(S, 64)
+    assert len(halos) == 5
+    for t, h in enumerate(halos):
+        rows = S[64 * t:64 * t + 64]
+        ref = sorted(set(int(x) for x in rows.ravel()))
+        assert list(h) == ref
+        for i in range(len(rows)):
+            for j in range(S.shape[1]):
+                assert ref.index(int(rows[i, j])) == lidx[64 * t + i, j]

@@ -191,3 +191,25 @@ def test_pointwise_difference_closed_forms():
     z = np.zeros((2, 3))
     dz, _ = O.pointwise(np.array([[0.0, 0, 0], [1e-3, 0, 0]]), z)
     assert dz[0] == 0.0 and dz[1] == np.inf
+
+
+def test_channel_permeability_closed_form():
+    """Plane Poiseuille flow u = g z (H - z) / (2 nu) in 0 <= z <= H: the
+    sample interpolation is exact on quadratics, and the M x M midpoint
+    quadrature of Eq. k_definition integrates the profile with the midpoint
+    rule's known error, so k / d^2 = H^3 / 12 + H / (24 M^2) exactly (the
+    channel's textbook H^3 / 12 plus the quadrature term).  Pins the plane
+    flux, the solid samples counting zero, and k = q nu / |g| (a wrong nu or
+    |g| exponent shows as a factor)."""
+    H, M, g, nu = 0.5, 32, 2.5, 0.8
+    c = nc.channel_cloud(0.05, H, seed=2)
+    S = nc.stencils(c.pos, 30)
+    pp = nc.plane_plan(c, M, 30, fluid=lambda p: p[:, 2] < H)
+    pw = O.plane_weights(c.pos, pp.idx, pp.shift)
+    z = c.pos[:, 2]
+    u = g * z * (H - z) / (2 * nu)
+    u[c.n_int:] = 0.0
+    q = O.flux(pp.idx, pw, u, 5 * M * M)
+    k = O.permeability(q, nu, g)
+    assert k == pytest.approx(H ** 3 / 12 + H / (24 * M * M), rel=1e-11)
+    assert O.permeability(q, nu, g, d=2.0) == pytest.approx(k / 4, rel=1e-15)
