@@ -579,6 +579,29 @@ int mpf_mlp_train(const mpf_mlp_desc* d, float* master, void* packed, float* m, 
                   const float* t, const int64_t* rows, int64_t n_batches, int64_t B, int step0, float lr0,
                   float lr_ratio, float b1, float b2, float eps, double* loss_sum, void* ws, size_t ws_bytes,
                   void* stream);
+/* The same training step fused: one persistent kernel per step runs forward,
+ * MSE, backward and the weight gradients of 64-row tiles with the
+ * activations in LDS and the gradient sums in registers (one block per
+ * compute unit, at most 1024 blocks), then a fixed-order sum of the blocks'
+ * partial gradients.  Same network, operand and accumulation precisions as
+ * the separate calls; the derivative of SiLU is kept in FP16 between the
+ * passes and the batch's rows are summed in another order, so results agree
+ * with them to rounding, not bit for bit, and are bitwise reproducible for a
+ * given device.
+ * mpf_mlp_grad_fused: grad (dev float [param_count], overwritten) and loss
+ *   (dev double [1] or NULL: the MSE) of one batch x[rows], t[rows] of B
+ *   samples, without an optimiser step.
+ * mpf_mlp_train_fused: as mpf_mlp_train (n_batches Adam steps, loss_sum the
+ *   sum of their losses) with the fused step.
+ * ws: mpf_mlp_fused_workspace(B) bytes (the blocks' partial gradients). */
+size_t mpf_mlp_fused_workspace(const mpf_mlp_desc* d, int64_t B);
+int mpf_mlp_grad_fused(const mpf_mlp_desc* d, const float* master, const void* packed, const float* x, const float* t,
+                       const int64_t* rows, int64_t B, float* grad, double* loss, void* ws, size_t ws_bytes,
+                       void* stream);
+int mpf_mlp_train_fused(const mpf_mlp_desc* d, float* master, void* packed, float* m, float* v, float* grad,
+                        const float* x, const float* t, const int64_t* rows, int64_t n_batches, int64_t B, int step0,
+                        float lr0, float lr_ratio, float b1, float b2, float eps, double* loss_sum, void* ws,
+                        size_t ws_bytes, void* stream);
 /* rows[i] = pi(i) for i < count, pi a permutation of [0, n) fixed by seed
  * (a Feistel network with cycle walking, evaluated pointwise): the minibatch
  * order of an epoch without a host-side shuffle.  rows dev int64 [count];

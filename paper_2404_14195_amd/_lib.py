@@ -12,7 +12,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _INC = os.path.join(os.path.dirname(_HERE), "include")
 SO_PATH = os.path.join(_HERE, "libmpf.so")
-SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip", "knn.hip", "tiles.hip"]
+SOURCES = ["weights.hip", "acm.hip", "lbm.hip", "reduce.hip", "mlp.hip", "mlp_fused.hip", "knn.hip", "tiles.hip"]
 
 MPF_F64, MPF_F32, MPF_MIXED, MPF_F32_KAHAN = 0, 1, 2, 3
 MPF_ERR_DIVERGED = -4
@@ -149,6 +149,10 @@ def _load():
         "mpf_gemm_bf16": (i32, [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp]),
         "mpf_mlp_train_workspace": (sz, [vp, i64]),
         "mpf_shuffle_rows": (i32, [i64, i64, ctypes.c_uint64, vp, vp]),
+        "mpf_mlp_fused_workspace": (sz, [vp, i64]),
+        "mpf_mlp_grad_fused": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+        "mpf_mlp_train_fused": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i32, flt, flt, flt, flt, flt, vp,
+                                      vp, sz, vp]),
         "mpf_scale": (i32, [i64, vp, i32, dbl, vp]),
         "mpf_mlp_train": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i32, flt, flt, flt, flt, flt, vp, vp,
                                 sz, vp]),
@@ -182,7 +186,7 @@ EXPORTED = ["mpf_strerror", "mpf_version", "mpf_create", "mpf_destroy", "mpf_acm
             "mpf_flux_planes", "mpf_drag", "mpf_traction", "mpf_mlp_param_count", "mpf_mlp_packed_count", "mpf_mlp_workspace",
             "mpf_mlp_pack", "mpf_mlp_forward", "mpf_mlp_backward", "mpf_mlp_mse", "mpf_adam_step",
             "mpf_mlp_features", "mpf_mlp_to_state", "mpf_gemm_bf16", "mpf_mlp_train_workspace", "mpf_mlp_train",
-            "mpf_shuffle_rows", "mpf_scale"]
+            "mpf_shuffle_rows", "mpf_scale", "mpf_mlp_fused_workspace", "mpf_mlp_grad_fused", "mpf_mlp_train_fused"]
 
 
 def check(rc: int, what: str):

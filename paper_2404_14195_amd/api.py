@@ -534,6 +534,45 @@ def mlp_train(master, packed, m, v, grad, x, t, rows, batch: int, step0: int, lr
                               float(eps), _p(loss_sum), _p(ws), ws.numel(), _stream()), "mpf_mlp_train")
 
 
+def mlp_fused_workspace(batch: int, device="cuda") -> torch.Tensor:
+    nbytes = lib().mpf_mlp_fused_workspace(ctypes.byref(MLP_DESC), int(batch))
+    if nbytes == 0:
+        raise ValueError(f"unsupported MLP batch {batch}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def mlp_grad_fused(master, packed, x, t, grad, ws, rows=None, loss=None, batch=None):
+    """grad (overwritten) and loss [1] f64 of one batch (rows or the first
+    batch rows of x, t) by the fused training step."""
+    n = mlp_param_count()
+    _need(master, torch.float32, (n,), "master")
+    _need(grad, torch.float32, (n,), "grad")
+    _need(x, torch.float32, name="x")
+    _need(t, torch.float32, name="t")
+    B = (rows.shape[0] if rows is not None else x.shape[0]) if batch is None else int(batch)
+    if rows is not None:
+        _need(rows, torch.int64, name="rows")
+    if loss is not None:
+        _need(loss, torch.float64, (1,), "loss")
+    check(lib().mpf_mlp_grad_fused(ctypes.byref(MLP_DESC), _p(master), _p(packed), _p(x), _p(t), _p(rows), B, _p(grad),
+                                   _p(loss), _p(ws), ws.numel(), _stream()), "mpf_mlp_grad_fused")
+
+
+def mlp_train_fused(master, packed, m, v, grad, x, t, rows, batch: int, step0: int, lr0: float, lr_ratio: float,
+                    loss_sum, ws, b1=0.9, b2=0.999, eps=1e-8):
+    """len(rows) // batch Adam steps of the fused training step in one call."""
+    n = mlp_param_count()
+    for a_, name in ((master, "master"), (m, "m"), (v, "v"), (grad, "grad")):
+        _need(a_, torch.float32, (n,), name)
+    _need(rows, torch.int64, name="rows")
+    _need(loss_sum, torch.float64, (1,), "loss_sum")
+    nb = rows.numel() // batch
+    check(lib().mpf_mlp_train_fused(ctypes.byref(MLP_DESC), _p(master), _p(packed), _p(m), _p(v), _p(grad), _p(x),
+                                    _p(t), _p(rows), nb, int(batch), int(step0), float(lr0), float(lr_ratio),
+                                    float(b1), float(b2), float(eps), _p(loss_sum), _p(ws), ws.numel(), _stream()),
+          "mpf_mlp_train_fused")
+
+
 def shuffle_rows(n: int, count: int, seed: int, rows=None, device="cuda"):
     """rows [count] int64: the first count entries of a seeded permutation of [0, n)."""
     if rows is None:

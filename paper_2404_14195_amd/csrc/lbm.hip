@@ -254,7 +254,18 @@ __global__ __launch_bounds__((step_waves<TW, T>() * kWave)) void lbm_step(
   using CT = typename Compute<T, KAHAN>::type;
   constexpr int QP = Pad<Q>::QP;
   constexpr int NW = step_waves<TW, T>();
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+  // Without HALO the partial sums sit in a static array: the compiler then
+  // knows the LDS bound on occupancy and spends the registers it leaves on
+  // loads in flight (with dynamic LDS it aims at an occupancy the launch
+  // cannot reach, and the FP64 step slows by up to 25 %).
+  unsigned char* lds_raw;
+  if constexpr (HALO) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    lds_raw = lds_dyn;
+  } else {
+    __shared__ __align__(16) unsigned char lds_fixed[step_part_bytes<TW, T, Q>()];
+    lds_raw = lds_fixed;
+  }
   T(*part)[Q - 1][kTile] = reinterpret_cast<T(*)[Q - 1][kTile]>(lds_raw);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile * kTile >= n) return;  // whole block
@@ -500,7 +511,7 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   const bool halo = tiles && halo_bytes <= kHaloLdsBytes;
   const TileArg tp{tiles ? tiles->count : nullptr, tiles ? tiles->halo : nullptr, tiles ? tiles->lidx : nullptr,
                    tiles ? tiles->h_cap : 0};
-  const size_t lds = halo ? (halo_bytes > part ? halo_bytes : part) : part;
+  const size_t lds = halo ? (halo_bytes > part ? halo_bytes : part) : 0;  // else static
   const bool stream_w = (double)(Q - 1) * nl * n * sizeof(TW) > kStreamWeightsBytes;
   if (halo) {
     if (stream_w)

@@ -191,15 +191,17 @@ class WarmStart:
 
     # ------------------------------------------------------------ training
     def fit(self, epochs: int, batch: int = 8192, lr: float = 2e-3, lr_end: float = 1e-4, seed: int = 0,
-            log=None):
+            log=None, fused: bool = True):
         """Adam over shuffled minibatches, learning rate decayed
         geometrically from lr to lr_end.  Returns the mean loss per epoch (one
-        host read per epoch)."""
+        host read per epoch).  fused: the fused training step
+        (mpf_mlp_train_fused), else the separate forward/backward kernels."""
         if self.X is None:
             self.X = torch.cat(self._x).contiguous()
             self.T = torch.cat(self._t).contiguous()
         N = self.X.shape[0]
-        ws = api.mlp_train_workspace(batch, self.device)
+        ws = api.mlp_fused_workspace(batch, self.device) if fused else api.mlp_train_workspace(batch, self.device)
+        train = api.mlp_train_fused if fused else api.mlp_train
         loss_sum = torch.zeros(1, dtype=torch.float64, device=self.device)
         per_epoch = max(1, N // batch)
         total = epochs * per_epoch
@@ -211,8 +213,8 @@ class WarmStart:
             api.shuffle_rows(N, per_epoch * batch, (seed << 32) + self.epochs_done, perm)
             self.epochs_done += 1
             rate = lr * ratio ** (ep * per_epoch)
-            api.mlp_train(self.master, self.packed, self.m, self.v, self.grad, self.X, self.T, perm, batch,
-                          self.step, rate, ratio, loss_sum, ws)
+            train(self.master, self.packed, self.m, self.v, self.grad, self.X, self.T, perm, batch, self.step, rate,
+                  ratio, loss_sum, ws)
             self.step += per_epoch
             hist.append(loss_sum.item() / per_epoch)
             if log:

@@ -290,3 +290,83 @@ def test_shuffle_rows_is_a_seeded_permutation(api, n, count):
         assert np.array_equal(np.sort(a), np.arange(n))
     if n > 1:
         assert not np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("B", [37, 700, 70001])
+def test_fused_gradient_parity_and_determinism(api, B):
+    """The fused training step's gradient and loss of one batch (gathered
+    through rows, a ragged last tile) against the FP64 oracle within the BF16
+    tolerance, against the layered kernels to rounding, and bitwise identical
+    on a second call."""
+    theta = init_theta(16)
+    rng = np.random.default_rng(17)
+    N = B + 50
+    x = rng.normal(size=(N, 5)).astype(np.float32)
+    t = rng.normal(size=(N, 4)).astype(np.float32)
+    rows = rng.permutation(N)[:B]
+    net = Net(api, theta, B)
+    xg, tg, rg = dev(x, torch.float32), dev(t, torch.float32), dev(rows, torch.int64)
+    grad = torch.empty(theta.size, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = api.mlp_fused_workspace(B)
+    api.mlp_grad_fused(net.master, net.packed, xg, tg, grad, ws, rows=rg, loss=loss)
+    g1, l1 = grad.cpu().numpy(), loss.item()
+    api.mlp_grad_fused(net.master, net.packed, xg, tg, grad, ws, rows=rg, loss=loss)
+    assert np.array_equal(g1, grad.cpu().numpy()) and l1 == loss.item()
+    yo, cache = OM.forward(theta.astype(np.float64), x[rows].astype(np.float64))
+    l_o, d_o = OM.mse(yo, t[rows].astype(np.float64))
+    g_o = OM.backward(theta.astype(np.float64), cache, d_o)
+    names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+    errs = {nm: rel(a, b) for nm, a, b in zip(names, blocks(g1), blocks(g_o))}
+    # the layered kernels on the same batch
+    y = torch.empty((B, 4), dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    loss2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    gl = torch.empty_like(grad)
+    api.mlp_forward(net.master, net.packed, xg, y, net.ws, rows=rg, train=True)
+    api.mlp_mse(y, tg, dy, loss2, api.reduce_workspace(4 * B, "cuda"), rows=rg)
+    api.mlp_backward(net.packed, dy, gl, net.ws)
+    e_lay = {nm: rel(a, b) for nm, a, b in zip(names, blocks(g1), blocks(gl.cpu().numpy()))}
+    print(f"[mlp fused B={B}] loss {l1:.6e} (oracle {l_o:.6e}, layered {loss2.item():.6e}); vs oracle "
+          + " ".join(f"{k}={v:.2e}" for k, v in errs.items()) + "; vs layered "
+          + " ".join(f"{k}={v:.2e}" for k, v in e_lay.items()), flush=True)
+    assert l1 == pytest.approx(l_o, rel=BF16_TOL)
+    assert max(errs.values()) <= BF16_TOL
+    assert max(e_lay.values()) <= 1e-2
+
+
+def test_fused_training_tracks_the_layered_training(api):
+    """100 fused Adam steps (one host call) and 100 layered ones from the same
+    parameters on the same minibatches: both reduce the loss and end within a
+    factor 1.2 of each other."""
+    rng = np.random.default_rng(21)
+    N, B, steps = 8192, 1024, 100
+    x = rng.uniform(-0.5, 0.5, (N, 5)).astype(np.float32)
+    t = np.column_stack([np.sin(3 * x[:, 0]), x[:, 1] * x[:, 2], np.exp(-4 * (x ** 2).sum(1)), x[:, 3] - x[:, 4]])
+    t = t.astype(np.float32)
+    theta = init_theta(22)
+    xg, tg = dev(x, torch.float32), dev(t, torch.float32)
+    rows = dev(rng.integers(0, N, steps * B), torch.int64)
+    out = {}
+    for name, fused in (("fused", True), ("layered", False)):
+        net = Net(api, theta, B)
+        m = torch.zeros(theta.size, dtype=torch.float32, device="cuda")
+        v = torch.zeros_like(m)
+        grad = torch.empty_like(m)
+        ls = torch.zeros(1, dtype=torch.float64, device="cuda")
+        if fused:
+            api.mlp_train_fused(net.master, net.packed, m, v, grad, xg, tg, rows[:B * 10], B, 0, 2e-3, 1.0, ls,
+                                api.mlp_fused_workspace(B))
+            first = ls.item() / 10
+            api.mlp_train_fused(net.master, net.packed, m, v, grad, xg, tg, rows[B * 10:], B, 10, 2e-3, 1.0, ls,
+                                api.mlp_fused_workspace(B))
+        else:
+            ws = api.mlp_train_workspace(B)
+            api.mlp_train(net.master, net.packed, m, v, grad, xg, tg, rows[:B * 10], B, 0, 2e-3, 1.0, ls, ws)
+            first = ls.item() / 10
+            api.mlp_train(net.master, net.packed, m, v, grad, xg, tg, rows[B * 10:], B, 10, 2e-3, 1.0, ls, ws)
+        out[name] = (first, ls.item() / (steps - 10))
+    print(f"[mlp fused training] {out}", flush=True)
+    for first, last in out.values():
+        assert last < 0.2 * first
+    assert 1 / 1.2 <= out["fused"][1] / out["layered"][1] <= 1.2
