@@ -61,8 +61,8 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
     """Wall-clock from the initial state to the first check with
     |k - k_inf| / k_inf <= rel, per precision.
 
-    k_inf: the FP64 run (from rest) continued until k changes by less than
-    1e-8 relative per check, then Aitken-extrapolated from its last three
+    k_inf: the FP64 run (from rest) continued until its last five checks
+    agree to 1e-8 relative, then Aitken-extrapolated from its last three
     checks.  Every other run is timed into the band and then continued until
     it settles too, so that its own steady k (where rounding stalls the
     iteration) is reported against k_inf.  warm: optional {suffix: (callable
@@ -90,7 +90,10 @@ def time_to_steady(torch, disc, MLBMSolver, precisions, check=500, rel=1e-3, max
         return ns, ks, ts
 
     def settled(ks):
-        return len(ks) > 3 and abs(ks[-1] - ks[-2]) <= 1e-8 * abs(ks[-1])
+        # the last five checks within 1e-8: a warm start rings (period about
+        # 4,000 steps), and two checks that straddle a turning point of the
+        # ringing can agree to 1e-8 while k is still 2e-4 from its limit
+        return len(ks) > 5 and max(ks[-5:]) - min(ks[-5:]) <= 1e-8 * abs(ks[-1])
 
     runs = {}
     ns64, ks64, ts64 = trajectory(precisions["fp64"], settled)
