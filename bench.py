@@ -254,7 +254,7 @@ def train_warm_start(torch, nc, n_cells=16, h0=0.016, epochs=200, batch=8192):
     return ws, info
 
 
-def mlp_training_throughput(torch, api, samples=12_800_000, batch=65536, epochs=3):
+def mlp_training_throughput(torch, api, samples=12_800_000, batch=65536, epochs=3, variants=("fused", "layered")):
     """Training throughput of the warm-start network at the scale of 64 cells x
     200k nodes: features of random points in cells of random radius (computed
     by the feature kernel), smooth synthetic targets, Adam over shuffled
@@ -274,7 +274,8 @@ def mlp_training_throughput(torch, api, samples=12_800_000, batch=65536, epochs=
                          np.cos(2 * xh[:, 0]) * xh[:, 4]]).astype(np.float32)
     Td = torch.as_tensor(T, device="cuda")
     out = {"samples_per_epoch": samples, "batch": batch, "epochs": epochs}
-    for name, fused in (("fused", True), ("layered", False)):
+    for name in variants:
+        fused = name == "fused"
         ws = WarmStart(seed=1)
         ws._x, ws._t = [X], [Td]
         ws.fit(1, batch=batch, fused=fused)  # warm-up epoch (allocations, first launches)
@@ -998,6 +999,8 @@ def main():
     ap.add_argument("--no-steady", action="store_true", help="skip the time-to-steady measurement")
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
+    ap.add_argument("--mlp-profile", action="store_true",
+                    help="only the fused training step, one warm-up and one timed epoch (counter runs)")
     ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
     ap.add_argument("--xval-acm-steps", type=int, default=1_500_000, help="cap on the ACM steps of --cross-validate")
     ap.add_argument("--weights-cell", default=None, metavar="CELL",
@@ -1112,6 +1115,10 @@ def main():
         ws_model, info = train_warm_start(torch, nc)
         print(json.dumps({"cross_validation": cross_validate(torch, nc, ws_model, args.xval_acm_steps),
                           "warm_start_training": info}))
+        return
+    if args.mlp_profile:
+        torch.cuda.set_device(0)
+        print(json.dumps({"mlp_training": mlp_training_throughput(torch, api, epochs=1, variants=("fused",))}))
         return
     if args.mlp:
         torch.cuda.set_device(0)
