@@ -243,6 +243,32 @@ int mpf_rbffd_weights_batched(mpf_ctx* ctx, int n_geoms, const mpf_wgeom* geoms_
 int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
                          int64_t sample_rows, mpf_wtune* out, void* ws, size_t ws_bytes);
 
+/* Tile plan of the LDS-staged stencil gather.  The MLBM step and the ACM
+ * passes work on tiles of 64 consecutive nodes; a tile's stencils (Sec. 2.1) name few distinct
+ * nodes (about 350 for 64 x 30 entries on the refined clouds here).  The
+ * plan lists each tile's distinct stencil nodes in ascending order (its
+ * halo) and every stencil entry as its 16-bit position in that list, so a
+ * step copies the halo's records into LDS with contiguous loads and gathers
+ * from LDS.  Built once per stencil set:
+ *   count dev int32 [G + 1], G = mpf_tile_count(n): halo sizes, and in
+ *         count[G] the largest (also returned in *h_max_host)
+ *   halo  dev int32 [G][h_cap]: the halo of tile t in halo[t][0, count[t])
+ *   lidx  dev uint16 [nl][n]: sten[j][i] == halo[i / 64][lidx[j][i]]
+ * sten dev [nl][n]; 1 <= nl <= 64; 64 <= h_cap <= 4096.  The call waits for
+ * the stream (it reads back the largest halo) and returns
+ * MPF_ERR_UNSUPPORTED if a tile's halo exceeds h_cap (the plan is then
+ * incomplete and must not be used). */
+typedef struct {
+  const int32_t* count;
+  const int32_t* halo;
+  const uint16_t* lidx;
+  int32_t h_cap; /* row length of halo */
+  int32_t h_max; /* the largest halo, as mpf_tile_plan returned it */
+} mpf_tiles;
+int64_t mpf_tile_count(int64_t n);
+int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* count, int32_t* halo, uint16_t* lidx,
+                  int32_t* h_max_host, void* stream);
+
 /* ------------------------------------------------------------- ACM step
  * Explicit artificial-compressibility Navier-Stokes steps (Sec. 2.3, Eqs.
  * MNS_intermediate, MNS_pressure, MNS_velocity, MNS_C; MNS algorithm of
@@ -263,6 +289,12 @@ int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_op* ops, int
  *       (rows of boundary nodes are not read)
  * sten  dev [nl][n]
  * sn    dev [nl][nb]; wn dev [nl][nb] normal-derivative weights on sn
+ * tiles the tile plan of sten (mpf_tile_plan) or NULL: with one lane per
+ *       node and an FP32 state (MPF_F32, MPF_F32_KAHAN) the interior passes
+ *       then copy each 64-node tile's halo values into LDS and gather from
+ *       there (when four tiles' halo records fit 64 KiB, i.e. h_max <= 819);
+ *       otherwise, and for NULL, they gather through the caches.  Results
+ *       are the same bit for bit either way.
  * v     dev [3][n], p dev [n]: state, updated in place (v stays 0 on the
  *       boundary)
  * comp  dev float [4][n] for MPF_F32_KAHAN (NULL otherwise): the
@@ -308,34 +340,8 @@ typedef struct {
 int mpf_acm_dt(double h_min, double nu, double* dt_host);
 size_t mpf_acm_workspace(int64_t n, int precision);
 int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const void* w,
-                const int32_t* sn, const void* wn, void* v, void* p, void* comp, double* vmax, uint32_t* flags,
-                int n_steps, void* ws, size_t ws_bytes, void* stream);
-
-/* Tile plan of the LDS-staged stencil gather.  The MLBM step works on tiles
- * of 64 consecutive nodes; a tile's stencils (Sec. 2.1) name few distinct
- * nodes (about 350 for 64 x 30 entries on the refined clouds here).  The
- * plan lists each tile's distinct stencil nodes in ascending order (its
- * halo) and every stencil entry as its 16-bit position in that list, so a
- * step copies the halo's records into LDS with contiguous loads and gathers
- * from LDS.  Built once per stencil set:
- *   count dev int32 [G + 1], G = mpf_tile_count(n): halo sizes, and in
- *         count[G] the largest (also returned in *h_max_host)
- *   halo  dev int32 [G][h_cap]: the halo of tile t in halo[t][0, count[t])
- *   lidx  dev uint16 [nl][n]: sten[j][i] == halo[i / 64][lidx[j][i]]
- * sten dev [nl][n]; 1 <= nl <= 64; 64 <= h_cap <= 4096.  The call waits for
- * the stream (it reads back the largest halo) and returns
- * MPF_ERR_UNSUPPORTED if a tile's halo exceeds h_cap (the plan is then
- * incomplete and must not be used). */
-typedef struct {
-  const int32_t* count;
-  const int32_t* halo;
-  const uint16_t* lidx;
-  int32_t h_cap; /* row length of halo */
-  int32_t h_max; /* the largest halo, as mpf_tile_plan returned it */
-} mpf_tiles;
-int64_t mpf_tile_count(int64_t n);
-int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* count, int32_t* halo, uint16_t* lidx,
-                  int32_t* h_max_host, void* stream);
+                const int32_t* sn, const void* wn, const mpf_tiles* tiles, void* v, void* p, void* comp,
+                double* vmax, uint32_t* flags, int n_steps, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------- MLBM step
  * Meshless lattice Boltzmann steps with TRT collision (Sec. 2.2, Eqs.
@@ -581,9 +587,9 @@ int mpf_mlp_train(const mpf_mlp_desc* d, float* master, void* packed, float* m, 
                   void* stream);
 /* The same training step fused: one persistent kernel per step runs forward,
  * MSE, backward and the weight gradients of 64-row tiles with the
- * activations in LDS and the gradient sums in registers (one block per
- * compute unit, at most 1024 blocks), then a fixed-order sum of the blocks'
- * partial gradients.  Same network, operand and accumulation precisions as
+ * activations in LDS and the gradient sums in registers (one block of eight
+ * waves per compute unit, at most 1024 blocks), then a fixed-order sum of the
+ * blocks' partial gradients.  Same network, operand and accumulation precisions as
  * the separate calls; the derivative of SiLU is kept in FP16 between the
  * passes and the batch's rows are summed in another order, so results agree
  * with them to rounding, not bit for bit, and are bitwise reproducible for a
@@ -592,7 +598,10 @@ int mpf_mlp_train(const mpf_mlp_desc* d, float* master, void* packed, float* m, 
  *   (dev double [1] or NULL: the MSE) of one batch x[rows], t[rows] of B
  *   samples, without an optimiser step.
  * mpf_mlp_train_fused: as mpf_mlp_train (n_batches Adam steps, loss_sum the
- *   sum of their losses) with the fused step.
+ *   sum of their losses) with the fused step; the kernel that sums the
+ *   partial gradients also applies the Adam step (the arithmetic of
+ *   mpf_adam_step) and rewrites the packed BF16 copy (as mpf_mlp_pack), so a
+ *   step is two launches.  grad holds the last step's gradient.
  * ws: mpf_mlp_fused_workspace(B) bytes (the blocks' partial gradients). */
 size_t mpf_mlp_fused_workspace(const mpf_mlp_desc* d, int64_t B);
 int mpf_mlp_grad_fused(const mpf_mlp_desc* d, const float* master, const void* packed, const float* x, const float* t,

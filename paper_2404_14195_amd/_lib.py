@@ -114,7 +114,7 @@ def _load():
         "mpf_weights_autotune": (i32, [vp, i32, i32, vp, i32, vp, i64, vp, vp, sz]),
         "mpf_acm_dt": (i32, [dbl, dbl, vp]),
         "mpf_acm_workspace": (sz, [i64, i32]),
-        "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
+        "mpf_acm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
         "mpf_lbm_init": (i32, [vp, i64, dbl, vp, vp, vp]),
         "mpf_lbm_init_fields": (i32, [vp, i64, vp, vp, dbl, vp, vp]),
         "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]),

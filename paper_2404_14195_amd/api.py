@@ -169,9 +169,12 @@ def acm_dt(h_min: float, nu: float) -> float:
     return out.value
 
 
-def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: int, ws=None, comp=None, flags=None):
+def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: int, ws=None, comp=None, flags=None,
+            tiles: "TilePlan | None" = None):
     """comp: [4][n] float32 for MPF_F32_KAHAN; flags: [1] int32 (the uint32
-    word), or None for a call without the end-of-call check."""
+    word), or None for a call without the end-of-call check; tiles: the plan
+    of sten for the LDS-staged gather (one lane per node, FP32 state), or
+    None."""
     prec = prm.precision
     dt, dw = _ST[prec], _WT[prec]
     nl, n = sten.shape
@@ -188,8 +191,9 @@ def acm_run(prm: AcmParams, n_int: int, sten, w, sn, wn, v, p, vmax, n_steps: in
         _need(flags, torch.int32, (1,), "flags")
     if ws is None:
         ws = acm_workspace(n, prec, v.device)
-    check(lib().mpf_acm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(w), _p(sn), _p(wn), _p(v), _p(p), _p(comp),
-                            _p(vmax), _p(flags), int(n_steps), _p(ws), ws.numel(), _stream()), "mpf_acm_run")
+    check(lib().mpf_acm_run(ctypes.byref(prm), n, n_int, nl, _p(sten), _p(w), _p(sn), _p(wn),
+                            None if tiles is None else ctypes.byref(tiles.rec), _p(v), _p(p), _p(comp), _p(vmax),
+                            _p(flags), int(n_steps), _p(ws), ws.numel(), _stream()), "mpf_acm_run")
 
 
 def record_len(q: int) -> int:

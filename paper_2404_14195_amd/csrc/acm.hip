@@ -139,8 +139,11 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
-__device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i, int sl) {
+// The node functions read a stencil neighbour's velocity record or pressure
+// through gv(at) / gp(at), at = j n + i the stencil entry: from memory
+// through the caches (sten), or from the tile's halo in LDS (staged).
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN, typename GV>
+__device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i, int sl, GV&& gv) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   const int64_t n = F.n, os = (int64_t)nl * n;
   T d[3][4];
@@ -150,9 +153,8 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
     for (int o = 0; o < 4; ++o) d[a][o] = T(0);
   columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
-    const int s = F.sten[at];
     const T wx = (T)F.w[at], wy = (T)F.w[os + at], wz = (T)F.w[2 * os + at], wl = (T)F.w[3 * os + at];
-    const auto r = load4(F.V, s);  // one node's velocity: one record, one or two vector loads
+    const auto r = gv(at);  // one node's velocity: one record, one or two vector loads
     const T u[3] = {r.x, r.y, r.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -192,15 +194,15 @@ __device__ __forceinline__ void predictor_node(const Fields<T, TW>& F, int64_t i
   }
 }
 
-template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
-__device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* __restrict__ vsrc,
-                                              const T* pin, T* pout, T coef, int64_t i, int sl) {
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN, typename GV>
+__device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* pin, T* pout, T coef, int64_t i,
+                                              int sl, GV&& gv) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   const int64_t n = F.n, os = (int64_t)nl * n;
   T div = T(0);
   columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
-    const auto r = load4(vsrc, F.sten[at]);
+    const auto r = gv(at);
     div += (T)F.w[at] * r.x + (T)F.w[os + at] * r.y + (T)F.w[2 * os + at] * r.z;
   });
   div = group_sum<LPN>(div);
@@ -216,19 +218,18 @@ __device__ __forceinline__ void pressure_node(const Fields<T, TW>& F, const T* _
 }
 
 // The damped pressure equation: p_new = p - coef div v - dt v_i . grad p + dt nu lap p.
-template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN, typename GV, typename GP>
 __device__ __forceinline__ void pressure_edac_node(const Fields<T, TW>& F, const T* __restrict__ vsrc,
                                                    const T* __restrict__ pin, T* __restrict__ pout, T coef,
-                                                   int64_t i, int sl) {
+                                                   int64_t i, int sl, GV&& gv, GP&& gp) {
   const int nl = NLC ? NLC : F.nl;
   const int64_t n = F.n, os = (int64_t)nl * n;
   T div = T(0), gx = T(0), gy = T(0), gz = T(0), lp = T(0);
   columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
-    const int s = F.sten[at];
     const T wx = (T)F.w[at], wy = (T)F.w[os + at], wz = (T)F.w[2 * os + at], wl = (T)F.w[3 * os + at];
-    const auto r = load4(vsrc, s);
-    const T ps = pin[s];
+    const auto r = gv(at);
+    const T ps = gp(at);
     div += wx * r.x + wy * r.y + wz * r.z;
     gx += wx * ps;
     gy += wy * ps;
@@ -267,15 +268,14 @@ __device__ __forceinline__ void neumann_node(const Fields<T, TW>& F, T* P, int64
 }
 
 // returns |v_i| (valid in every lane of the node's group)
-template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
-__device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, const T* __restrict__ P, int64_t i,
-                                                int sl) {
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN, typename GP>
+__device__ __forceinline__ double velocity_node(const Fields<T, TW>& F, int64_t i, int sl, GP&& gpres) {
   const int nl = NLC ? NLC : F.nl;  // a constant for the common stencil size
   const int64_t n = F.n, os = (int64_t)nl * n;
   T gp[3] = {T(0), T(0), T(0)};
   columns<LPN, NLC>(nl, 0, sl, [&](int j) {
     const int64_t at = (int64_t)j * n + i;
-    const T ps = P[F.sten[at]];
+    const T ps = gpres(at);
     gp[0] += (T)F.w[at] * ps;
     gp[1] += (T)F.w[os + at] * ps;
     gp[2] += (T)F.w[2 * os + at] * ps;
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_predictor(Fields<T, TW> F) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;  // whole LPN groups exit together
-  predictor_node<T, TW, LPN, NLC, KAHAN>(F, i, (int)(g % LPN));
+  predictor_node<T, TW, LPN, NLC, KAHAN>(F, i, (int)(g % LPN), [&](int64_t at) { return load4(F.V, F.sten[at]); });
 }
 
 template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
@@ -352,7 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_pressure(Fields<T, TW> F, const T* _
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_node<T, TW, LPN, NLC, KAHAN>(F, vsrc, P, P, coef, i, (int)(g % LPN));
+  pressure_node<T, TW, LPN, NLC, KAHAN>(F, P, P, coef, i, (int)(g % LPN),
+                                        [&](int64_t at) { return load4(vsrc, F.sten[at]); });
 }
 
 template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
@@ -362,7 +363,9 @@ __global__ __launch_bounds__(kBlock) void k_pressure_edac(Fields<T, TW> F, const
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   if (i >= F.n_int) return;
-  pressure_edac_node<T, TW, LPN, NLC, KAHAN>(F, vsrc, pin, pout, coef, i, (int)(g % LPN));
+  pressure_edac_node<T, TW, LPN, NLC, KAHAN>(F, vsrc, pin, pout, coef, i, (int)(g % LPN),
+                                             [&](int64_t at) { return load4(vsrc, F.sten[at]); },
+                                             [&](int64_t at) { return pin[F.sten[at]]; });
 }
 
 template <typename T, typename TW, int LPN, int NLC>
@@ -380,7 +383,111 @@ __global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F, const T* _
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / LPN;
   double mag = 0.0;
-  if (i < F.n_int) mag = velocity_node<T, TW, LPN, NLC, KAHAN>(F, P, i, (int)(g % LPN));
+  if (i < F.n_int)
+    mag = velocity_node<T, TW, LPN, NLC, KAHAN>(F, i, (int)(g % LPN), [&](int64_t at) { return P[F.sten[at]]; });
+  block_max_into(mag, red, F.vmax, F.flags);
+}
+
+// ---------------------------------------------------------------- LDS-staged gather
+// With one lane per node, the 64 nodes of a wave are one tile of the tile
+// plan (64 consecutive nodes; mpf_tile_plan).  Each wave first copies its
+// tile's halo (the tile's distinct stencil nodes, ascending) from the gathered
+// field into LDS with contiguous loads, then reads every neighbour value from
+// LDS through its 16-bit position lidx[j][i].  FP32 state only: an FP64
+// state keeps two lanes per node on the large cells, which spreads a tile
+// over two waves.
+
+struct Halo {
+  const int32_t* count;
+  const int32_t* halo;
+  const uint16_t* lidx;
+  int h_cap;
+  int h_max;
+};
+
+// the tile's halo values of src into dst (this wave's LDS), four entries per
+// lane in flight
+template <typename R>
+__device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R* __restrict__ src, R* dst,
+                                           int lane) {
+  const int cnt = H.count[tile];
+  const int32_t* hl = H.halo + tile * H.h_cap;
+  for (int c0 = 0; c0 < cnt; c0 += 4 * kWave) {
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * kWave + lane;
+      idx[u] = c < cnt ? hl[c] : -1;
+    }
+    R v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (idx[u] >= 0) v[u] = src[idx[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (idx[u] >= 0) dst[c0 + u * kWave + lane] = v[u];
+  }
+}
+
+template <typename TW, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_predictor_st(Fields<float, TW> F, Halo H) {
+  extern __shared__ __align__(16) float4 lds_v[];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
+  float4* hv = lds_v + w * H.h_max;
+  if (tile * kWave < F.n_int) stage_halo(H, tile, reinterpret_cast<const float4*>(F.V), hv, lane);
+  __syncthreads();
+  if (i >= F.n_int) return;
+  predictor_node<float, TW, 1, NLC, KAHAN>(F, i, 0, [&](int64_t at) { return hv[H.lidx[at]]; });
+}
+
+template <typename TW, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_pressure_st(Fields<float, TW> F, const float* __restrict__ vsrc,
+                                                        float* P, Halo H) {
+  extern __shared__ __align__(16) float4 lds_v[];
+  const float coef = coupling_coef(F);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
+  float4* hv = lds_v + w * H.h_max;
+  if (tile * kWave < F.n_int) stage_halo(H, tile, reinterpret_cast<const float4*>(vsrc), hv, lane);
+  __syncthreads();
+  if (i >= F.n_int) return;
+  pressure_node<float, TW, 1, NLC, KAHAN>(F, P, P, coef, i, 0, [&](int64_t at) { return hv[H.lidx[at]]; });
+}
+
+template <typename TW, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_pressure_edac_st(Fields<float, TW> F, const float* __restrict__ vsrc,
+                                                             const float* __restrict__ pin, float* __restrict__ pout,
+                                                             Halo H) {
+  extern __shared__ __align__(16) float4 lds_v[];
+  const float coef = coupling_coef(F);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
+  float4* hv = lds_v + w * H.h_max;
+  float* hp = reinterpret_cast<float*>(lds_v + (kBlock / kWave) * H.h_max) + w * H.h_max;
+  if (tile * kWave < F.n_int) {
+    stage_halo(H, tile, reinterpret_cast<const float4*>(vsrc), hv, lane);
+    stage_halo(H, tile, pin, hp, lane);
+  }
+  __syncthreads();
+  if (i >= F.n_int) return;
+  pressure_edac_node<float, TW, 1, NLC, KAHAN>(F, vsrc, pin, pout, coef, i, 0,
+                                               [&](int64_t at) { return hv[H.lidx[at]]; },
+                                               [&](int64_t at) { return hp[H.lidx[at]]; });
+}
+
+template <typename TW, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_velocity_st(Fields<float, TW> F, const float* __restrict__ P, Halo H) {
+  extern __shared__ __align__(16) float lds_p[];
+  __shared__ double red[kBlock / kWave];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
+  float* hp = lds_p + w * H.h_max;
+  if (tile * kWave < F.n_int) stage_halo(H, tile, P, hp, lane);
+  __syncthreads();
+  double mag = 0.0;
+  if (i < F.n_int)
+    mag = velocity_node<float, TW, 1, NLC, KAHAN>(F, i, 0, [&](int64_t at) { return hp[H.lidx[at]]; });
   block_max_into(mag, red, F.vmax, F.flags);
 }
 
@@ -413,8 +520,49 @@ int default_lanes(int64_t n_int) {
   return 1;
 }
 
+// The staged passes with one lane per node and an FP32 state (H from the
+// tile plan; LDS: each of the block's four waves holds h_max halo records).
+template <typename TW, int NLC, bool KAHAN>
+int run_staged(Fields<float, TW>& F, const Halo& H, int n_steps, int n_p, bool edac, hipStream_t st) {
+  const unsigned gi = grid_for(F.n_int, kBlock), gb = grid_for(F.nb, kBlock);
+  const size_t waves = kBlock / kWave;
+  const size_t lv = waves * H.h_max * sizeof(float4), lp = waves * H.h_max * sizeof(float);
+  float* cur = F.p;
+  for (int s = 0; s < n_steps; ++s) {
+    hipLaunchKernelGGL((k_predictor_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv, st, F, H);
+    for (int it = 0; it < n_p; ++it) {
+      const float* vsrc = it == 0 ? F.VP : F.V;
+      if (edac) {
+        float* nxt = cur == F.p ? F.P1 : F.p;
+        hipLaunchKernelGGL((k_pressure_edac_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv + lp, st, F, vsrc,
+                           (const float*)cur, nxt, H);
+        cur = nxt;
+      } else {
+        hipLaunchKernelGGL((k_pressure_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv, st, F, vsrc, cur, H);
+      }
+      hipLaunchKernelGGL((k_neumann<float, TW, 1, NLC>), dim3(gb), dim3(kBlock), 0, st, F, cur);
+      hipLaunchKernelGGL((k_velocity_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lp, st, F, (const float*)cur, H);
+    }
+  }
+  if (cur != F.p)
+    hipLaunchKernelGGL(copy_field<float>, dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, st, F.n,
+                       (const float*)cur, F.p);
+  MPF_LAUNCH_CHECK();
+  return MPF_OK;
+}
+
+// Staging is used when every wave's halo fits: four waves' velocity records
+// and pressures (the damped pressure pass holds both) in 64 KiB, i.e. halos
+// of up to 819 nodes (the refined clouds here: about 350 on average, 500 at
+// most).
+constexpr size_t kAcmHaloLds = 64 * 1024;
+
 template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
-int run_launches(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
+int run_launches(Fields<T, TW>& F, const Halo* H, int n_steps, int n_p, bool edac, hipStream_t st) {
+  if constexpr (LPN == 1 && sizeof(T) == sizeof(float)) {
+    if (H && (size_t)(kBlock / kWave) * H->h_max * (sizeof(float4) + sizeof(float)) <= kAcmHaloLds)
+      return run_staged<TW, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
+  }
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   T* cur = F.p;  // the pressure of the current iteration (alternates with F.P1 when damped)
   for (int s = 0; s < n_steps; ++s) {
@@ -443,28 +591,28 @@ int run_launches(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t 
 // its convergence study) get fully unrolled column loops, which lets every
 // lane issue all its index, weight and gather loads early
 template <typename T, typename TW, int LPN, bool KAHAN>
-int launch_nl(Fields<T, TW>& F, int n_steps, int n_p, bool edac, hipStream_t st) {
-  if (F.nl == 30) return run_launches<T, TW, LPN, 30, KAHAN>(F, n_steps, n_p, edac, st);
-  if (F.nl == 25) return run_launches<T, TW, LPN, 25, KAHAN>(F, n_steps, n_p, edac, st);
-  return run_launches<T, TW, LPN, 0, KAHAN>(F, n_steps, n_p, edac, st);
+int launch_nl(Fields<T, TW>& F, const Halo* H, int n_steps, int n_p, bool edac, hipStream_t st) {
+  if (F.nl == 30) return run_launches<T, TW, LPN, 30, KAHAN>(F, H, n_steps, n_p, edac, st);
+  if (F.nl == 25) return run_launches<T, TW, LPN, 25, KAHAN>(F, H, n_steps, n_p, edac, st);
+  return run_launches<T, TW, LPN, 0, KAHAN>(F, H, n_steps, n_p, edac, st);
 }
 
 template <typename T, typename TW, bool KAHAN>
-int launch_lanes(Fields<T, TW>& F, int lanes, int n_steps, int n_p, bool edac, hipStream_t st) {
+int launch_lanes(Fields<T, TW>& F, const Halo* H, int lanes, int n_steps, int n_p, bool edac, hipStream_t st) {
   switch (lanes) {
-    case 1: return launch_nl<T, TW, 1, KAHAN>(F, n_steps, n_p, edac, st);
-    case 2: return launch_nl<T, TW, 2, KAHAN>(F, n_steps, n_p, edac, st);
-    case 4: return launch_nl<T, TW, 4, KAHAN>(F, n_steps, n_p, edac, st);
-    case 8: return launch_nl<T, TW, 8, KAHAN>(F, n_steps, n_p, edac, st);
-    default: return launch_nl<T, TW, 16, KAHAN>(F, n_steps, n_p, edac, st);
+    case 1: return launch_nl<T, TW, 1, KAHAN>(F, H, n_steps, n_p, edac, st);
+    case 2: return launch_nl<T, TW, 2, KAHAN>(F, H, n_steps, n_p, edac, st);
+    case 4: return launch_nl<T, TW, 4, KAHAN>(F, H, n_steps, n_p, edac, st);
+    case 8: return launch_nl<T, TW, 8, KAHAN>(F, H, n_steps, n_p, edac, st);
+    default: return launch_nl<T, TW, 16, KAHAN>(F, H, n_steps, n_p, edac, st);
   }
 }
 
 // comp (compensated state only): [4][n] floats, v_lo rows 0-2 and p_lo row 3
 template <typename T, typename TW>
 int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* w,
-        const int32_t* sn, const TW* wn, T* v, T* p, T* comp, double* vmax, uint32_t* flags, int n_steps, void* ws,
-        hipStream_t st) {
+        const int32_t* sn, const TW* wn, const mpf_tiles* tiles, T* v, T* p, T* comp, double* vmax, uint32_t* flags,
+        int n_steps, void* ws, hipStream_t st) {
   Fields<T, TW> F;
   F.n = n; F.n_int = n_int; F.nb = n - n_int; F.nl = nl;
   F.sten = sten; F.w = w; F.sn = sn; F.wn = wn; F.p = p;
@@ -493,12 +641,18 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   const bool edac = prm->edac != 0;
   int lanes = prm->lanes;
   if (lanes == 0) lanes = default_lanes<T>(n_int);
+  Halo hd{};
+  const Halo* H = nullptr;
+  if (tiles) {
+    hd = Halo{tiles->count, tiles->halo, tiles->lidx, tiles->h_cap, tiles->h_max};
+    H = &hd;
+  }
   int rc;
   if constexpr (sizeof(T) == sizeof(float))  // the compensated state is FP32
-    rc = comp ? launch_lanes<T, TW, true>(F, lanes, n_steps, prm->n_p, edac, st)
-              : launch_lanes<T, TW, false>(F, lanes, n_steps, prm->n_p, edac, st);
+    rc = comp ? launch_lanes<T, TW, true>(F, H, lanes, n_steps, prm->n_p, edac, st)
+              : launch_lanes<T, TW, false>(F, H, lanes, n_steps, prm->n_p, edac, st);
   else
-    rc = launch_lanes<T, TW, false>(F, lanes, n_steps, prm->n_p, edac, st);
+    rc = launch_lanes<T, TW, false>(F, H, lanes, n_steps, prm->n_p, edac, st);
   if (rc) return rc;
   hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.V, v);
   if (comp) hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.VL, comp);
@@ -525,8 +679,9 @@ extern "C" size_t mpf_acm_workspace(int64_t n, int precision) {
 }
 
 extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32_t* sten,
-                           const void* w, const int32_t* sn, const void* wn, void* v, void* p, void* comp,
-                           double* vmax, uint32_t* flags, int n_steps, void* ws, size_t ws_bytes, void* stream) {
+                           const void* w, const int32_t* sn, const void* wn, const mpf_tiles* tiles, void* v, void* p,
+                           void* comp, double* vmax, uint32_t* flags, int n_steps, void* ws, size_t ws_bytes,
+                           void* stream) {
   using namespace mpf;
   if (!prm || !sten || !w || !v || !p || !vmax || n < 1 || n_int < 0 || n_int > n || nl < 2 || n_steps < 0 ||
       prm->n_p < 1 || !(prm->dt > 0.0) || !(prm->rho > 0.0) || !(prm->h_min >= 0.0))
@@ -539,19 +694,22 @@ extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, 
   if (prm->lanes != 0 && prm->lanes != 1 && prm->lanes != 2 && prm->lanes != 4 && prm->lanes != 8 &&
       prm->lanes != 16)
     return MPF_ERR_ARG;
+  if (tiles && (!tiles->count || !tiles->halo || !tiles->lidx || tiles->h_cap < 64 || tiles->h_max < 1 ||
+                tiles->h_max > tiles->h_cap))
+    return MPF_ERR_ARG;
   if (!ws || ws_bytes < mpf_acm_workspace(n, prec)) return MPF_ERR_WORKSPACE;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);
   int rc;
   if (prec == MPF_F64)
-    rc = run<double, double>(prm, n, n_int, nl, sten, (const double*)w, sn, (const double*)wn, (double*)v,
+    rc = run<double, double>(prm, n, n_int, nl, sten, (const double*)w, sn, (const double*)wn, tiles, (double*)v,
                              (double*)p, nullptr, vmax, flags, n_steps, ws, st);
   else if (prec == MPF_MIXED)
-    rc = run<double, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (double*)v, (double*)p,
-                            nullptr, vmax, flags, n_steps, ws, st);
+    rc = run<double, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, tiles, (double*)v,
+                            (double*)p, nullptr, vmax, flags, n_steps, ws, st);
   else
-    rc = run<float, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, (float*)v, (float*)p,
-                           (float*)comp, vmax, flags, n_steps, ws, st);
+    rc = run<float, float>(prm, n, n_int, nl, sten, (const float*)w, sn, (const float*)wn, tiles, (float*)v,
+                           (float*)p, (float*)comp, vmax, flags, n_steps, ws, st);
   if (rc) return rc;
   return check_flags(flags, st);
 }

@@ -74,8 +74,9 @@ class ACMSolver:
     """Artificial-compressibility Navier-Stokes (Sec. 2.3) on a Discretization."""
 
     def __init__(self, disc: Discretization, precision: int = MPF_F64, nu=1.0, rho=1.0, dt=None, beta=10.0,
-                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False, check: bool = True):
-        self.d, self.precision, self.check = disc, precision, check
+                 v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False, check: bool = True,
+                 staged: bool = True):
+        self.d, self.precision, self.check, self.staged = disc, precision, check, staged
         dt = api.acm_dt(disc.cloud.h_min, nu) if dt is None else dt
         self.prm = AcmParams(nu=nu, rho=rho, dt=dt, beta=beta, v_ref=v_ref, g=(ctypesarr(g)), n_p=n_p,
                              precision=precision, lanes=lanes, edac=int(bool(edac)), h_min=disc.cloud.h_min)
@@ -101,8 +102,11 @@ class ACMSolver:
         self.steps = 0
 
     def run(self, n_steps: int):
+        # the tile plan matters only where the library stages (one lane per
+        # node, FP32 state); it is built once per discretization
+        tiles = self.d.tiles if self.staged and self.precision in (MPF_F32, MPF_F32_KAHAN) else None
         api.acm_run(self.prm, self.d.n_int, self.d.sten, self.w, self.d.sn, self.wn, self.v, self.p, self.vmax,
-                    n_steps, self.ws, comp=self.comp, flags=self.flags if self.check else None)
+                    n_steps, self.ws, comp=self.comp, flags=self.flags if self.check else None, tiles=tiles)
         self.steps += n_steps
 
     def clear_compensation(self):

@@ -370,3 +370,36 @@ def test_fused_training_tracks_the_layered_training(api):
     for first, last in out.values():
         assert last < 0.2 * first
     assert 1 / 1.2 <= out["fused"][1] / out["layered"][1] <= 1.2
+
+
+def test_fused_update_equals_grad_adam_and_pack(api):
+    """The fused training loop's reduction kernel also takes the Adam step and
+    rewrites the BF16 copies.  Three steps of mpf_mlp_train_fused against the
+    same steps as mpf_mlp_grad_fused + mpf_adam_step + mpf_mlp_pack: the
+    gradient sums are the same kernel's, so the parameters and moments agree
+    to the rounding of the Adam expression (1e-6), and the packed copy equals
+    mpf_mlp_pack of the fused run's own parameters bit for bit (the same
+    round-to-nearest-even of the same values, padding untouched)."""
+    rng = np.random.default_rng(23)
+    N, B = 5000, 700  # a ragged last tile
+    x = dev(rng.normal(size=(N, 5)).astype(np.float32), torch.float32)
+    t = dev(rng.normal(size=(N, 4)).astype(np.float32), torch.float32)
+    rows = dev(rng.permutation(N)[:3 * B], torch.int64)
+    theta = init_theta(24)
+    a, b = Net(api, theta, B), Net(api, theta, B)
+    ma, va, ga = (torch.zeros(theta.size, device="cuda") for _ in range(3))
+    mb, vb, gb = (torch.zeros(theta.size, device="cuda") for _ in range(3))
+    ws = api.mlp_fused_workspace(B)
+    lr = 1e-3
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for i in range(3):
+        api.mlp_grad_fused(a.master, a.packed, x, t, ga, ws, rows=rows[i * B:(i + 1) * B], loss=loss)
+        api.adam_step(a.master, ga, ma, va, i + 1, lr)
+        api.mlp_pack(a.master, a.packed)
+    loss_sum = torch.zeros(1, dtype=torch.float64, device="cuda")
+    api.mlp_train_fused(b.master, b.packed, mb, vb, gb, x, t, rows, B, 0, lr, 1.0, loss_sum, ws)
+    assert torch.allclose(a.master, b.master, rtol=1e-6, atol=1e-9)
+    assert torch.allclose(ma, mb, rtol=1e-6, atol=1e-12) and torch.allclose(va, vb, rtol=1e-6, atol=1e-15)
+    ref = torch.empty_like(b.packed)
+    api.mlp_pack(b.master, ref)
+    assert torch.equal(ref.view(torch.int16), b.packed.view(torch.int16))

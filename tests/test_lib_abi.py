@@ -66,14 +66,14 @@ def test_host_argument_checks(lib):
     bad = WTune(waves_per_block=9, rows_per_wave=1)
     assert lib.mpf_rbffd_weights_batched(None, 2, geoms, 30, 1, ops, 0, ctypes.byref(bad), fake, big, None) == -1
     prm = AcmParams(nu=1, rho=1, dt=1e-5, beta=10, v_ref=1e-3, n_p=3, precision=0)
-    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, None, fake, None, 1, fake, 0,
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, None, fake, fake, None, fake, None, 1, fake, 0,
                            None) == -5  # workspace too small
     prm.lanes = 3
-    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, None, fake, None, 1, fake, 1 << 20,
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, None, fake, fake, None, fake, None, 1, fake, 1 << 20,
                            None) == -1
     prm.lanes = 0
     prm.n_p = 0
-    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, None, fake, None, 1, fake, 1 << 20,
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, None, fake, fake, None, fake, None, 1, fake, 1 << 20,
                            None) == -1
     lp = LbmParams(q=17, precision=0, tau_plus=1.0, tau_minus=1.0)
     assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1
@@ -93,9 +93,14 @@ def test_host_argument_checks(lib):
     assert lib.mpf_flux_planes(5, 30, fake, fake, fake, 0, 0, fake, fake, 1 << 20, None) == -1
     assert lib.mpf_drag(10, fake, fake, 0, 2, 30, fake, fake, fake, 1.0, 1.0, 0.1, fake, fake, 8, None) == -5
     prm.n_p, prm.edac = 3, 2
-    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, None, fake, None, 1, fake, 1 << 20,
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, None, fake, fake, None, fake, None, 1, fake, 1 << 20,
                            None) == -1  # edac is 0 or 1
     prm.edac = 0
+    # a tile plan record is checked like the MLBM step's
+    from paper_2404_14195_amd._lib import Tiles
+    bad_tiles = Tiles(count=0x1000, halo=0x1000, lidx=0x1000, h_cap=64, h_max=65)  # h_max > h_cap
+    assert lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, ctypes.byref(bad_tiles), fake, fake,
+                           None, fake, None, 1, fake, 1 << 20, None) == -1
     assert lib.mpf_acm_workspace(1000, 0) >= 9 * 1000 * 8  # v, v' records and a second pressure
     assert lib.mpf_acm_workspace(1000, 0) >= 3 * 1000 * 8
     assert lib.mpf_acm_workspace(1000, 1) >= 3 * 1000 * 4
@@ -166,7 +171,7 @@ def test_compensated_state_and_flags_checks(lib):
     fake = ctypes.c_void_p(0x1000)
     big = 1 << 30
     prm = AcmParams(nu=1, rho=1, dt=1e-5, beta=10, v_ref=1e-3, n_p=3, precision=MPF_F32_KAHAN)
-    run = lambda comp, ws: lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, fake, fake, comp,
+    run = lambda comp, ws: lib.mpf_acm_run(ctypes.byref(prm), 10, 8, 30, fake, fake, fake, fake, None, fake, fake, comp,
                                            fake, None, 1, fake, ws, None)
     assert run(None, big) == -1              # compensated state without comp
     assert run(fake, lib.mpf_acm_workspace(10, MPF_F32_KAHAN) - 1) == -5
