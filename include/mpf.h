@@ -425,9 +425,11 @@ int mpf_lbm_unknown(int q, int64_t n, int64_t n_int, const double* pos, const do
                     double r, uint32_t* unknown, void* stream);
 /* Macroscopic fields in physical units (Eq. conversion_factors): v[3][n] =
  * vel_scale * u_lb, p[n] = vel_scale^2 (rho - 1) / 3 (not centred: the drag
- * reduction subtracts the node mean).  Outputs are double. */
-int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double vel_scale, double* v, double* p,
-                    void* stream);
+ * reduction subtracts the node mean).  Outputs are double.  comp: the FP32
+ * remainders of an MPF_F32_KAHAN state (added to f in FP64), or NULL; given
+ * for another precision, MPF_ERR_ARG. */
+int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, const void* comp, double vel_scale, double* v,
+                    double* p, void* stream);
 
 /* ------------------------------------------------------------- reductions
  * Mean x-velocity over the five cross-sections, Eq. k_definition, as the mean

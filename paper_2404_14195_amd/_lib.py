@@ -131,7 +131,7 @@ def _load():
         "mpf_knn_workspace": (ctypes.c_size_t, [i64]),
         "mpf_knn": (i32, [vp, i64, i64, vp, i64, i64, i32, vp, i64, vp, ctypes.c_size_t, vp]),
         "mpf_solver_stencils": (i32, [vp, i64, i64, i32, vp, vp, ctypes.c_size_t, vp]),
-        "mpf_lbm_moments": (i32, [vp, i64, vp, dbl, vp, vp, vp]),
+        "mpf_lbm_moments": (i32, [vp, i64, vp, vp, dbl, vp, vp, vp]),
         "mpf_reduce_workspace": (sz, [i64]),
         "mpf_flux_planes": (i32, [i64, i32, vp, vp, vp, i32, i64, vp, vp, sz, vp]),
         "mpf_drag": (i32, [i64, vp, vp, i32, i64, i32, vp, vp, vp, dbl, dbl, dbl, vp, vp, sz, vp]),

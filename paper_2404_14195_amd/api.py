@@ -286,12 +286,15 @@ def lbm_unknown(q: int, pos, n_int: int, nrm=None, rule: str = "normal", dx: flo
     return out
 
 
-def lbm_moments(prm: LbmParams, f, vel_scale: float, v=None, p=None):
+def lbm_moments(prm: LbmParams, f, vel_scale: float, v=None, p=None, comp=None):
+    """comp: the remainders [n][qp] of an MPF_F32_KAHAN state, or None."""
     _need(f, _ST[prm.precision], name="f")
     n = f.shape[0]
+    if comp is not None:
+        _need(comp, torch.float32, tuple(f.shape), "comp")
     v = torch.empty((3, n), dtype=torch.float64, device=f.device) if v is None else v
     p = torch.empty(n, dtype=torch.float64, device=f.device) if p is None else p
-    check(lib().mpf_lbm_moments(ctypes.byref(prm), n, _p(f), float(vel_scale), _p(v), _p(p), _stream()),
+    check(lib().mpf_lbm_moments(ctypes.byref(prm), n, _p(f), _p(comp), float(vel_scale), _p(v), _p(p), _stream()),
           "mpf_lbm_moments")
     return v, p
 

@@ -398,15 +398,16 @@ __global__ __launch_bounds__(kBlock) void lbm_init_fields(int64_t n, const doubl
 }
 
 template <typename T, int Q>
-__global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __restrict__ f, double vs,
-                                                      double* __restrict__ v, double* __restrict__ p) {
+__global__ __launch_bounds__(kBlock) void lbm_moments(int64_t n, const T* __restrict__ f, const T* __restrict__ comp,
+                                                      double vs, double* __restrict__ v, double* __restrict__ p) {
   using L = Lattice<Q>;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   double drho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const double fk = (double)f[i * Pad<Q>::QP + k];
+    // the compensated state is hi + lo, added in FP64
+    const double fk = (double)f[i * Pad<Q>::QP + k] + (comp ? (double)comp[i * Pad<Q>::QP + k] : 0.0);
     drho += fk;
     j0 += L::ex[k] * fk;
     j1 += L::ey[k] * fk;
@@ -641,17 +642,19 @@ extern "C" int mpf_lbm_unknown(int q, int64_t n, int64_t n_int, const double* po
   });
 }
 
-extern "C" int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, double vel_scale, double* v,
-                               double* p, void* stream) {
+extern "C" int mpf_lbm_moments(const mpf_lbm_params* prm, int64_t n, const void* f, const void* comp,
+                               double vel_scale, double* v, double* p, void* stream) {
   using namespace mpf;
   if (!prm || !f || !v || n < 1) return MPF_ERR_ARG;
+  if (comp && prm->precision != MPF_F32_KAHAN) return MPF_ERR_ARG;
   hipStream_t st = as_stream(stream);
   const unsigned g = grid_for(n, kBlock);
   return with_q(prm->q, [&](auto qc) {
     constexpr int Q = decltype(qc)::value;
     return with_state<Q>(prm->precision, [&](auto t) {
       using T = decltype(t);
-      hipLaunchKernelGGL((lbm_moments<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, vel_scale, v, p);
+      hipLaunchKernelGGL((lbm_moments<T, Q>), dim3(g), dim3(kBlock), 0, st, n, (const T*)f, (const T*)comp,
+                         vel_scale, v, p);
       MPF_LAUNCH_CHECK();
       return MPF_OK;
     });

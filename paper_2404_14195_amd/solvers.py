@@ -109,6 +109,14 @@ class ACMSolver:
                     n_steps, self.ws, comp=self.comp, flags=self.flags if self.check else None, tiles=tiles)
         self.steps += n_steps
 
+    def staged_now(self) -> bool:
+        """Whether run() takes the LDS-staged gather: a tile plan, an FP32
+        state, one lane per node (as the library picks it: above 50k
+        interior nodes) and a halo that fits (largest halo <= 819 nodes)."""
+        lanes = self.prm.lanes or (8 if self.d.n_int <= 12000 else 2 if self.d.n_int <= 50000 else 1)
+        return (self.staged and self.precision in (MPF_F32, MPF_F32_KAHAN) and lanes == 1
+                and self.d.tiles.h_max <= 819)
+
     def clear_compensation(self):
         """After the state was set from outside (a warm start): the FP32
         values are the state, their compensation is zero."""
@@ -266,7 +274,7 @@ class MLBMSolver:
             self.comp.copy_(torch.as_tensor(rem, dtype=torch.float32, device=self.f.device))
 
     def macros(self):
-        return api.lbm_moments(self.prm, self.f, self.units["vel_scale"], self._v, self._p)
+        return api.lbm_moments(self.prm, self.f, self.units["vel_scale"], self._v, self._p, comp=self.comp)
 
     def permeability(self) -> float:
         v, _ = self.macros()

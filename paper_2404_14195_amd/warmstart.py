@@ -368,19 +368,36 @@ def solve_warm(model, make_solver, kind: str = "mlbm", band: float = 0.1, burn_i
 
 
 def training_radii(n: int, seed: int = 5, lo: float = 0.15, hi: float = 0.48, held_out=(0.18, 0.3, 0.33, 0.47),
-                   gap: float = 0.01):
-    """n radii in [lo, hi], one uniform draw in each of n equal strata
-    (seeded), none within gap of a held-out radius.  The upper end stays
-    below 1/2, where neighbouring grains of the simple-cubic array touch."""
+                   gap: float = 0.01, exclude=()):
+    """n radii stratified over [lo, hi] without the gap-neighbourhoods of the
+    held-out radii and the intervals in exclude: that allowed set, of total
+    length L, is cut into n equal parts of length L / n measured along it,
+    and one uniform draw (seeded) is taken in each part.  (A stratum of
+    [lo, hi] itself can lie entirely inside an excluded neighbourhood once
+    L / n < 2 gap.)  The default range stays below 1/2, where neighbouring
+    grains of the simple-cubic array touch."""
+    cuts = [(max(lo, h - gap), min(hi, h + gap)) for h in held_out if h + gap > lo and h - gap < hi]
+    cuts += [(max(lo, a), min(hi, b)) for a, b in exclude if b > lo and a < hi]
+    cuts.sort()
+    ivals, a = [], lo
+    for c0, c1 in cuts:
+        if c0 > a:
+            ivals.append((a, c0))
+        a = max(a, c1)
+    if a < hi:
+        ivals.append((a, hi))
+    if not ivals:
+        raise ValueError("the held-out neighbourhoods cover the whole range")
+    length = sum(b - a for a, b in ivals)
     rng = np.random.default_rng(seed)
-    w = (hi - lo) / n
     out = []
     for i in range(n):
-        while True:
-            r = float(lo + (i + rng.uniform()) * w)
-            if all(abs(r - h) > gap for h in held_out):
+        u = (i + rng.uniform()) * length / n
+        for a, b in ivals:
+            if u < b - a or (a, b) == ivals[-1]:
+                out.append(float(a + min(u, b - a)))
                 break
-        out.append(r)
+            u -= b - a
     return out
 
 

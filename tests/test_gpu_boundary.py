@@ -246,3 +246,27 @@ def test_pointwise_difference_parity(api, dta, dtb):
     assert np.abs(d[fin] - d_o[fin]).max() <= 1e-14 * np.abs(d_o[fin]).max()
     assert np.abs(dv - dv_o).max() <= 1e-14 * np.abs(dv_o).max()
     assert counts == [int((d_o[:n_int] > t).sum()) for t in levels]
+
+
+def test_compensated_moments_include_the_remainder():
+    """The moments of a compensated FP32 MLBM state are those of hi + lo: the
+    velocity equals the FP64 moments of hi + lo formed on the host from the
+    two FP32 arrays (same shifted form) to 1e-13, while the FP32 values
+    alone give a velocity that differs by more than 1e-10 (relative)."""
+    import nodecloud as nc
+    from paper_2404_14195_amd import MPF_F32_KAHAN, api
+    from paper_2404_14195_amd.solvers import Discretization, MLBMSolver, lattice_vectors
+    cloud = nc.sphere_cloud(0.3, 0.04, 0.3, 0.1, seed=1)
+    d = Discretization(cloud, nl=30, M=32)
+    s = MLBMSolver(d, q=19, precision=MPF_F32_KAHAN)
+    s.run(300)
+    v, _ = s.macros()
+    v = v.cpu().numpy()
+    ft = s.f[:, :19].double().cpu().numpy() + s.comp[:, :19].double().cpu().numpy()  # shifted, FP64
+    e = np.array(lattice_vectors(19), dtype=np.float64)
+    vs = s.units["vel_scale"]
+    v_host = (vs * (ft @ e) / (1.0 + ft.sum(1))[:, None]).T
+    scale = np.abs(v_host).max()
+    assert np.abs(v - v_host).max() <= 1e-13 * scale
+    v_hi = api.lbm_moments(s.prm, s.f, vs)[0].cpu().numpy()  # the FP32 values alone
+    assert np.abs(v_hi - v_host).max() > 1e-10 * scale

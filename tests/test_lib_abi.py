@@ -81,6 +81,8 @@ def test_host_argument_checks(lib):
     assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 10, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1
     lp.tau_plus = 1.0
     assert lib.mpf_lbm_run(ctypes.byref(lp), 10, 8, 30, fake, fake, None, None, fake, fake, None, None, 1, None) == -1  # no masks
+    # remainders are only for the compensated state
+    assert lib.mpf_lbm_moments(ctypes.byref(lp), 10, fake, fake, 1.0, fake, fake, None) == -1
     # unknown-population masks: rule, q, normals, dx and r are checked first
     assert lib.mpf_lbm_unknown(19, 10, 10, None, None, 0, 0.0, 0.0, None, None) == 0  # no boundary nodes
     assert lib.mpf_lbm_unknown(19, 10, 8, fake, None, 0, 0.0, 0.0, fake, None) == -1  # normal rule needs nrm

@@ -27,9 +27,18 @@ def test_pchip_interpolates_and_matches_scipy_inside():
 
 
 def test_training_radii_are_stratified_and_avoid_held_out():
-    rs = training_radii(16, held_out=(0.3, 0.33))
-    assert len(rs) == 16 and all(0.15 <= r <= 0.48 for r in rs)
-    edges = np.linspace(0.15, 0.48, 17)
-    assert all(edges[i] <= r <= edges[i + 1] for i, r in enumerate(rs))
-    assert all(abs(r - h) > 0.01 for r in rs for h in (0.3, 0.33))
-    assert training_radii(16, held_out=(0.3, 0.33)) == rs  # seeded
+    """Stratified along the allowed set: the i-th radius lies in the i-th of n
+    equal parts of [lo, hi] minus the held-out neighbourhoods, measured along
+    that set (computed here on a fine grid, independently of the function)."""
+    for n, lo, hi, held in ((16, 0.15, 0.48, (0.3, 0.33)), (64, 0.15, 0.6, (0.18, 0.33, 0.47, 0.58)),
+                            (10, 0.2, 0.45, (0.33,))):
+        rs = training_radii(n, lo=lo, hi=hi, held_out=held)
+        assert len(rs) == n and all(lo <= r <= hi for r in rs)
+        assert all(abs(r - h) > 0.01 for r in rs for h in held)
+        grid = np.linspace(lo, hi, 2_000_001)
+        ok = np.all(np.abs(grid[:, None] - np.array(held)[None, :]) > 0.01, axis=1)
+        along = np.concatenate([[0.0], np.cumsum(ok[1:] * np.diff(grid))])  # allowed length below each grid point
+        L = along[-1]
+        pos = np.interp(rs, grid, along)
+        assert all(i * L / n - 1e-6 <= p <= (i + 1) * L / n + 1e-6 for i, p in enumerate(pos))
+        assert training_radii(n, lo=lo, hi=hi, held_out=held) == rs  # seeded
