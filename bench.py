@@ -484,13 +484,13 @@ def _c5_trajectory(s, load, check, stop, max_steps, say=None):
     return ns, ks, ts
 
 
-def c5_eval(torch, nc, model_path, acm_r=0.33, check=500, rel=1e-3):
+def c5_eval(torch, nc, model_path, acm_r=0.33, check=500, rel=1e-3, radii=C5_HELD_OUT):
     """Steps and wall-clock to |k - k_inf| / k_inf <= rel at the held-out
     radii, from rest and from the network's prediction, and from the
     magnitude lookup and flux matches without the network (the ablation).
     MLBM with the compensated FP32 state at every held-out radius; the ACM
     (compensated FP32, v_ref = 1) at acm_r.  k_inf is each solver's own
-    settled cold run (last five checks within 1e-8), Aitken-extrapolated; a
+    settled cold run (last five checks within 1e-7), Aitken-extrapolated; a
     run's time to steady is its first check from which it stays in the band
     until it is within rel / 10 of k_inf at four checks in a row (from there
     the remaining error only decays)."""
@@ -500,14 +500,17 @@ def c5_eval(torch, nc, model_path, acm_r=0.33, check=500, rel=1e-3):
     from paper_2404_14195_amd.solvers import ACMSolver, Discretization, MLBMSolver
     from paper_2404_14195_amd.warmstart import WarmStart
     say = lambda m: print(f"[bench] c5 eval: {m}", file=sys.stderr, flush=True)
-    futs = _c5_clouds([(r, 600 + i, C5_CLASS) for i, r in enumerate(C5_HELD_OUT)])
+    futs = _c5_clouds([(r, 600 + C5_HELD_OUT.index(r), C5_CLASS) for r in radii])
     torch.cuda.set_device(0)
     model = WarmStart(seed=0)
     with np.load(model_path) as z:
         model.load_state_dict({k: z[k] for k in z.files})
 
     def settled(ks):
-        return len(ks) > 5 and max(ks[-5:]) - min(ks[-5:]) <= 1e-8 * abs(ks[-1])
+        # 1e-7: on the largest cells the compensated FP32 state's k moves by
+        # about 1e-8 from check to check (the neighbours' remainders are not
+        # gathered), so a 1e-8 criterion never triggers there
+        return len(ks) > 5 and max(ks[-5:]) - min(ks[-5:]) <= 1e-7 * abs(ks[-1])
 
     def study(name, make, kinds, max_steps):
         ns, ks, ts = _c5_trajectory(make(), None, check, settled, max_steps, say)
@@ -1141,15 +1144,28 @@ def weights_batch(torch, nc, api):
 
 
 def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4, edac=False, halo=0.0):
-    """Algorithmic bytes of one ACM node-step: predictor (4 operators, v in,
-    v' out), then per coupling iteration a pressure pass (3 operators, v and p
-    in, p out; the damped pressure equation adds the Laplacian, a fourth
-    operator) and a velocity pass (3 operators, p and v' in, v out).  The
-    staged gather reads 2-byte stencil positions (s_i = 2) and, in each of the
-    1 + 2 n_p gathering passes, the tile's halo list (halo bytes per node)."""
+    """Algorithmic bytes of one interior node in one ACM step: predictor (4
+    operators, v in, v' out), then per coupling iteration a pressure pass (3
+    operators, v and p in, p out; the damped pressure equation adds the
+    Laplacian, a fourth operator) and a velocity pass (3 operators, p and v'
+    in, v out).  The staged gather reads 2-byte stencil positions (s_i = 2)
+    and, in each of the 1 + 2 n_p gathering passes, the tile's halo list
+    (halo bytes per node)."""
     ops_p = 4 if edac else 3
     return ((4 * s_w + s_i) * nl + 6 * s_f + n_p * ((ops_p * s_w + s_i) * nl + 5 * s_f)
             + n_p * ((3 * s_w + s_i) * nl + 7 * s_f) + (1 + 2 * n_p) * halo)
+
+
+def acm_bytes_per_step(disc, s_w, s_f, n_p=3, staged=False, edac=False):
+    """Algorithmic bytes of one ACM step of a discretisation: the interior
+    passes for its n_int interior nodes, and n_p Neumann passes over its nb
+    boundary nodes (their weight rows and 4-byte indices, p_b written)."""
+    halo = 0.0
+    if staged:
+        t_int = (disc.n_int + 63) // 64
+        halo = 4.0 * int(disc.tiles.count[:t_int].sum().item()) / disc.n_int
+    inner = acm_bytes_per_node_step(disc.nl, s_w, s_f, n_p, s_i=2 if staged else 4, edac=edac, halo=halo)
+    return disc.n_int * inner + disc.nb * n_p * ((s_w + 4) * disc.nl + s_f)
 
 
 def acm_and_weights(torch, nc, api):
@@ -1193,12 +1209,12 @@ def acm_and_weights(torch, nc, api):
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1)
             sz = 8 if prec == MPF_F64 else 4
-            # FP32 on this cell runs the staged gather (one lane per node)
-            halo_b = 4.0 * int(disc.tiles.count[:-1].sum().item()) / disc.n if s2.staged_now() else 0.0
-            bpn = acm_bytes_per_node_step(30, sz, sz, s_i=2 if halo_b else 4, halo=halo_b)
+            # FP32 on the large cell runs the staged gather (one lane per node)
+            bps = acm_bytes_per_step(disc, sz, sz, staged=s2.staged_now())
             rec[pname] = {"us_per_step": ms * 1e3 / steps, "node_steps_per_s": cloud.n * steps / (ms * 1e-3),
-                          "k_after": s2.permeability(), "hbm_frac": bpn * cloud.n / (ms * 1e-3 / steps) / 1e9
-                          / HBM_PEAK_GBS, "weights_ms": w_ms}
+                          "k_after": s2.permeability(), "bytes_per_step": bps,
+                          "hbm_frac": bps / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, "weights_ms": w_ms,
+                          "staged": s2.staged_now()}
             print(f"[bench] {name} {pname}: {ms * 1e3 / steps:.1f} us/step k={rec[pname]['k_after']:.6e}",
                   file=sys.stderr, flush=True)
             del s, s2
@@ -1216,11 +1232,10 @@ def acm_and_weights(torch, nc, api):
                 torch.cuda.synchronize()
                 ms = ev0.elapsed_time(ev1)
                 sz = 8 if prec == MPF_F64 else 4
-                halo_b = 4.0 * int(disc.tiles.count[:-1].sum().item()) / disc.n if s.staged_now() else 0.0
-                bpn = acm_bytes_per_node_step(30, sz, sz, edac=True, s_i=2 if halo_b else 4, halo=halo_b)
+                bps = acm_bytes_per_step(disc, sz, sz, staged=s.staged_now(), edac=True)
                 rec[pname] = {"us_per_step": ms * 1e3 / steps, "node_steps_per_s": cloud.n * steps / (ms * 1e-3),
-                              "bytes_per_node_step": bpn,
-                              "hbm_frac": bpn * cloud.n / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS}
+                              "bytes_per_step": bps, "staged": s.staged_now(),
+                              "hbm_frac": bps / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS}
                 print(f"[bench] {name} {pname}: {ms * 1e3 / steps:.1f} us/step", file=sys.stderr, flush=True)
                 del s
         out[name] = rec
@@ -1278,6 +1293,8 @@ def main():
                          "(held-out radii, warm vs cold vs the no-network ablation)")
     ap.add_argument("--c5-model", default="c5_model.npz", help="network file written by --c5 train, read by eval")
     ap.add_argument("--c5-budget-s", type=float, default=1e9, help="--c5 train starts no new cell after this time")
+    ap.add_argument("--c5-radii", type=float, nargs="+", default=list(C5_HELD_OUT),
+                    help="--c5 eval: the held-out radii to run (a subset of 0.18 0.33 0.47 0.58)")
     ap.add_argument("--mlp-profile", action="store_true",
                     help="only the fused training step, one warm-up and one timed epoch (counter runs)")
     ap.add_argument("--cross-validate", action="store_true", help="only MLBM vs ACM at steady state on one cell")
@@ -1401,7 +1418,7 @@ def main():
         print(json.dumps({"c5_train": c5_train(torch, nc, args.c5_model, budget_s=args.c5_budget_s)}))
         return
     if args.c5 == "eval":
-        print(json.dumps({"c5_eval": c5_eval(torch, nc, args.c5_model)}))
+        print(json.dumps({"c5_eval": c5_eval(torch, nc, args.c5_model, radii=tuple(args.c5_radii))}))
         return
     if args.mlp_profile:
         torch.cuda.set_device(0)

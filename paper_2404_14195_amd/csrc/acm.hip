@@ -406,26 +406,24 @@ struct Halo {
 };
 
 // the tile's halo values of src into dst (this wave's LDS), four entries per
-// lane in flight
+// lane in flight (entries past the halo load a valid one and are not stored;
+// named temporaries, so that nothing is placed in scratch)
 template <typename R>
 __device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R* __restrict__ src, R* dst,
                                            int lane) {
   const int cnt = H.count[tile];
   const int32_t* hl = H.halo + tile * H.h_cap;
-  for (int c0 = 0; c0 < cnt; c0 += 4 * kWave) {
-    int idx[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = c0 + u * kWave + lane;
-      idx[u] = c < cnt ? hl[c] : -1;
-    }
-    R v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (idx[u] >= 0) v[u] = src[idx[u]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (idx[u] >= 0) dst[c0 + u * kWave + lane] = v[u];
+  for (int c0 = lane; c0 < cnt; c0 += 4 * kWave) {
+    const int c1 = c0 + kWave, c2 = c0 + 2 * kWave, c3 = c0 + 3 * kWave;
+    const int i0 = hl[c0];
+    const int i1 = hl[c1 < cnt ? c1 : c0];
+    const int i2 = hl[c2 < cnt ? c2 : c0];
+    const int i3 = hl[c3 < cnt ? c3 : c0];
+    const R v0 = src[i0], v1 = src[i1], v2 = src[i2], v3 = src[i3];
+    dst[c0] = v0;
+    if (c1 < cnt) dst[c1] = v1;
+    if (c2 < cnt) dst[c2] = v2;
+    if (c3 < cnt) dst[c3] = v3;
   }
 }
 
