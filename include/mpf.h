@@ -289,12 +289,13 @@ int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* co
  *       (rows of boundary nodes are not read)
  * sten  dev [nl][n]
  * sn    dev [nl][nb]; wn dev [nl][nb] normal-derivative weights on sn
- * tiles the tile plan of sten (mpf_tile_plan) or NULL: with one lane per
- *       node and an FP32 state (MPF_F32, MPF_F32_KAHAN) the interior passes
- *       then copy each 64-node tile's halo values into LDS and gather from
- *       there (when four tiles' halo records fit 64 KiB, i.e. h_max <= 819);
- *       otherwise, and for NULL, they gather through the caches.  Results
- *       are the same bit for bit either way.
+ * tiles the tile plan of sten (mpf_tile_plan) or NULL: with one or two
+ *       lanes per node the interior passes then copy each 64-node tile's
+ *       halo values into LDS and gather from there, when a block's halos fit
+ *       64 KiB (h_max <= 819 for FP32 at one lane and for an FP64 state at
+ *       two, 1638 for FP32 at two, 409 for an FP64 state at one); otherwise,
+ *       and for NULL, they gather through the caches.  Results are the same
+ *       bit for bit either way.
  * v     dev [3][n], p dev [n]: state, updated in place (v stays 0 on the
  *       boundary)
  * comp  dev float [4][n] for MPF_F32_KAHAN (NULL otherwise): the

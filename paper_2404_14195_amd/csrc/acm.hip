@@ -40,6 +40,7 @@ namespace mpf {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kTile = 64;  // nodes per tile of the tile plan (mpf_tile_plan)
 
 template <int LPN, typename T>
 __device__ __forceinline__ T group_sum(T x) {
@@ -389,13 +390,12 @@ __global__ __launch_bounds__(kBlock) void k_velocity(Fields<T, TW> F, const T* _
 }
 
 // ---------------------------------------------------------------- LDS-staged gather
-// With one lane per node, the 64 nodes of a wave are one tile of the tile
-// plan (64 consecutive nodes; mpf_tile_plan).  Each wave first copies its
-// tile's halo (the tile's distinct stencil nodes, ascending) from the gathered
-// field into LDS with contiguous loads, then reads every neighbour value from
-// LDS through its 16-bit position lidx[j][i].  FP32 state only: an FP64
-// state keeps two lanes per node on the large cells, which spreads a tile
-// over two waves.
+// A tile of the tile plan is 64 consecutive nodes (mpf_tile_plan): one wave
+// at one lane per node, two waves at two.  The tile's threads first copy its
+// halo (the tile's distinct stencil nodes, ascending) from the gathered field
+// into LDS with contiguous loads, then read every neighbour value from LDS
+// through its 16-bit position lidx[j][i].  The summation order is that of the
+// cached gather, so results are the same bit for bit.
 
 struct Halo {
   const int32_t* count;
@@ -405,16 +405,16 @@ struct Halo {
   int h_max;
 };
 
-// the tile's halo values of src into dst (this wave's LDS), four entries per
-// lane in flight (entries past the halo load a valid one and are not stored;
-// named temporaries, so that nothing is placed in scratch)
-template <typename R>
-__device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R* __restrict__ src, R* dst,
-                                           int lane) {
+// the tile's halo values of src into dst (this tile's LDS), four entries per
+// thread in flight; the tile's GT threads share the copy (entries past the
+// halo load a valid one and are not stored; named temporaries, so that
+// nothing is placed in scratch)
+template <int GT, typename R>
+__device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R* __restrict__ src, R* dst, int t) {
   const int cnt = H.count[tile];
   const int32_t* hl = H.halo + tile * H.h_cap;
-  for (int c0 = lane; c0 < cnt; c0 += 4 * kWave) {
-    const int c1 = c0 + kWave, c2 = c0 + 2 * kWave, c3 = c0 + 3 * kWave;
+  for (int c0 = t; c0 < cnt; c0 += 4 * GT) {
+    const int c1 = c0 + GT, c2 = c0 + 2 * GT, c3 = c0 + 3 * GT;
     const int i0 = hl[c0];
     const int i1 = hl[c1 < cnt ? c1 : c0];
     const int i2 = hl[c2 < cnt ? c2 : c0];
@@ -427,65 +427,82 @@ __device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R*
   }
 }
 
-template <typename TW, int NLC, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_predictor_st(Fields<float, TW> F, Halo H) {
-  extern __shared__ __align__(16) float4 lds_v[];
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
-  float4* hv = lds_v + w * H.h_max;
-  if (tile * kWave < F.n_int) stage_halo(H, tile, reinterpret_cast<const float4*>(F.V), hv, lane);
+// Thread layout of a staged pass with LPN lanes per node: a tile of 64 nodes
+// is 64 LPN consecutive threads (one wave at LPN = 1, two at LPN = 2); a block
+// holds kBlock / (64 LPN) tiles, each with h_max halo values in LDS.
+template <int LPN>
+struct StagedIdx {
+  static constexpr int GT = kTile * LPN;  // threads per tile
+  int64_t g, i, tile;
+  int sl, t, slot;
+  __device__ StagedIdx() {
+    g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    i = g / LPN;
+    sl = (int)(g % LPN);
+    tile = i / kTile;
+    t = threadIdx.x % GT;
+    slot = threadIdx.x / GT;
+  }
+};
+
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_predictor_st(Fields<T, TW> F, Halo H) {
+  using R = typename Rec<T>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const StagedIdx<LPN> x;
+  R* hv = reinterpret_cast<R*>(lds_raw) + x.slot * H.h_max;
+  if (x.tile * kTile < F.n_int) stage_halo<StagedIdx<LPN>::GT>(H, x.tile, reinterpret_cast<const R*>(F.V), hv, x.t);
   __syncthreads();
-  if (i >= F.n_int) return;
-  predictor_node<float, TW, 1, NLC, KAHAN>(F, i, 0, [&](int64_t at) { return hv[H.lidx[at]]; });
+  if (x.i >= F.n_int) return;
+  predictor_node<T, TW, LPN, NLC, KAHAN>(F, x.i, x.sl, [&](int64_t at) { return hv[H.lidx[at]]; });
 }
 
-template <typename TW, int NLC, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_pressure_st(Fields<float, TW> F, const float* __restrict__ vsrc,
-                                                        float* P, Halo H) {
-  extern __shared__ __align__(16) float4 lds_v[];
-  const float coef = coupling_coef(F);
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
-  float4* hv = lds_v + w * H.h_max;
-  if (tile * kWave < F.n_int) stage_halo(H, tile, reinterpret_cast<const float4*>(vsrc), hv, lane);
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_pressure_st(Fields<T, TW> F, const T* __restrict__ vsrc, T* P, Halo H) {
+  using R = typename Rec<T>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const T coef = coupling_coef(F);
+  const StagedIdx<LPN> x;
+  R* hv = reinterpret_cast<R*>(lds_raw) + x.slot * H.h_max;
+  if (x.tile * kTile < F.n_int) stage_halo<StagedIdx<LPN>::GT>(H, x.tile, reinterpret_cast<const R*>(vsrc), hv, x.t);
   __syncthreads();
-  if (i >= F.n_int) return;
-  pressure_node<float, TW, 1, NLC, KAHAN>(F, P, P, coef, i, 0, [&](int64_t at) { return hv[H.lidx[at]]; });
+  if (x.i >= F.n_int) return;
+  pressure_node<T, TW, LPN, NLC, KAHAN>(F, P, P, coef, x.i, x.sl, [&](int64_t at) { return hv[H.lidx[at]]; });
 }
 
-template <typename TW, int NLC, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_pressure_edac_st(Fields<float, TW> F, const float* __restrict__ vsrc,
-                                                             const float* __restrict__ pin, float* __restrict__ pout,
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_pressure_edac_st(Fields<T, TW> F, const T* __restrict__ vsrc,
+                                                             const T* __restrict__ pin, T* __restrict__ pout,
                                                              Halo H) {
-  extern __shared__ __align__(16) float4 lds_v[];
-  const float coef = coupling_coef(F);
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
-  float4* hv = lds_v + w * H.h_max;
-  float* hp = reinterpret_cast<float*>(lds_v + (kBlock / kWave) * H.h_max) + w * H.h_max;
-  if (tile * kWave < F.n_int) {
-    stage_halo(H, tile, reinterpret_cast<const float4*>(vsrc), hv, lane);
-    stage_halo(H, tile, pin, hp, lane);
+  using R = typename Rec<T>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const T coef = coupling_coef(F);
+  const StagedIdx<LPN> x;
+  constexpr int tiles = kBlock / StagedIdx<LPN>::GT;
+  R* hv = reinterpret_cast<R*>(lds_raw) + x.slot * H.h_max;
+  T* hp = reinterpret_cast<T*>(reinterpret_cast<R*>(lds_raw) + tiles * H.h_max) + x.slot * H.h_max;
+  if (x.tile * kTile < F.n_int) {
+    stage_halo<StagedIdx<LPN>::GT>(H, x.tile, reinterpret_cast<const R*>(vsrc), hv, x.t);
+    stage_halo<StagedIdx<LPN>::GT>(H, x.tile, pin, hp, x.t);
   }
   __syncthreads();
-  if (i >= F.n_int) return;
-  pressure_edac_node<float, TW, 1, NLC, KAHAN>(F, vsrc, pin, pout, coef, i, 0,
-                                               [&](int64_t at) { return hv[H.lidx[at]]; },
-                                               [&](int64_t at) { return hp[H.lidx[at]]; });
+  if (x.i >= F.n_int) return;
+  pressure_edac_node<T, TW, LPN, NLC, KAHAN>(F, vsrc, pin, pout, coef, x.i, x.sl,
+                                             [&](int64_t at) { return hv[H.lidx[at]]; },
+                                             [&](int64_t at) { return hp[H.lidx[at]]; });
 }
 
-template <typename TW, int NLC, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_velocity_st(Fields<float, TW> F, const float* __restrict__ P, Halo H) {
-  extern __shared__ __align__(16) float lds_p[];
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_velocity_st(Fields<T, TW> F, const T* __restrict__ P, Halo H) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double red[kBlock / kWave];
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x, tile = i / kWave;
-  float* hp = lds_p + w * H.h_max;
-  if (tile * kWave < F.n_int) stage_halo(H, tile, P, hp, lane);
+  const StagedIdx<LPN> x;
+  T* hp = reinterpret_cast<T*>(lds_raw) + x.slot * H.h_max;
+  if (x.tile * kTile < F.n_int) stage_halo<StagedIdx<LPN>::GT>(H, x.tile, P, hp, x.t);
   __syncthreads();
   double mag = 0.0;
-  if (i < F.n_int)
-    mag = velocity_node<float, TW, 1, NLC, KAHAN>(F, i, 0, [&](int64_t at) { return hp[H.lidx[at]]; });
+  if (x.i < F.n_int)
+    mag = velocity_node<T, TW, LPN, NLC, KAHAN>(F, x.i, x.sl, [&](int64_t at) { return hp[H.lidx[at]]; });
   block_max_into(mag, red, F.vmax, F.flags);
 }
 
@@ -518,48 +535,51 @@ int default_lanes(int64_t n_int) {
   return 1;
 }
 
-// The staged passes with one lane per node and an FP32 state (H from the
-// tile plan; LDS: each of the block's four waves holds h_max halo records).
-template <typename TW, int NLC, bool KAHAN>
-int run_staged(Fields<float, TW>& F, const Halo& H, int n_steps, int n_p, bool edac, hipStream_t st) {
-  const unsigned gi = grid_for(F.n_int, kBlock), gb = grid_for(F.nb, kBlock);
-  const size_t waves = kBlock / kWave;
-  const size_t lv = waves * H.h_max * sizeof(float4), lp = waves * H.h_max * sizeof(float);
-  float* cur = F.p;
+// The staged passes (H from the tile plan; LDS: each of the block's
+// kBlock / (64 LPN) tiles holds h_max halo values).
+template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
+int run_staged(Fields<T, TW>& F, const Halo& H, int n_steps, int n_p, bool edac, hipStream_t st) {
+  using R = typename Rec<T>::type;
+  const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
+  const size_t tiles = kBlock / (kTile * LPN);
+  const size_t lv = tiles * H.h_max * sizeof(R), lp = tiles * H.h_max * sizeof(T);
+  T* cur = F.p;
   for (int s = 0; s < n_steps; ++s) {
-    hipLaunchKernelGGL((k_predictor_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv, st, F, H);
+    hipLaunchKernelGGL((k_predictor_st<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv, st, F, H);
     for (int it = 0; it < n_p; ++it) {
-      const float* vsrc = it == 0 ? F.VP : F.V;
+      const T* vsrc = it == 0 ? F.VP : F.V;
       if (edac) {
-        float* nxt = cur == F.p ? F.P1 : F.p;
-        hipLaunchKernelGGL((k_pressure_edac_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv + lp, st, F, vsrc,
-                           (const float*)cur, nxt, H);
+        T* nxt = cur == F.p ? F.P1 : F.p;
+        hipLaunchKernelGGL((k_pressure_edac_st<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv + lp, st, F,
+                           vsrc, (const T*)cur, nxt, H);
         cur = nxt;
       } else {
-        hipLaunchKernelGGL((k_pressure_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv, st, F, vsrc, cur, H);
+        hipLaunchKernelGGL((k_pressure_st<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), lv, st, F, vsrc, cur, H);
       }
-      hipLaunchKernelGGL((k_neumann<float, TW, 1, NLC>), dim3(gb), dim3(kBlock), 0, st, F, cur);
-      hipLaunchKernelGGL((k_velocity_st<TW, NLC, KAHAN>), dim3(gi), dim3(kBlock), lp, st, F, (const float*)cur, H);
+      hipLaunchKernelGGL((k_neumann<T, TW, LPN, NLC>), dim3(gb), dim3(kBlock), 0, st, F, cur);
+      hipLaunchKernelGGL((k_velocity_st<T, TW, LPN, NLC, KAHAN>), dim3(gi), dim3(kBlock), lp, st, F, (const T*)cur,
+                         H);
     }
   }
   if (cur != F.p)
-    hipLaunchKernelGGL(copy_field<float>, dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, st, F.n,
-                       (const float*)cur, F.p);
+    hipLaunchKernelGGL(copy_field<T>, dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, st, F.n, (const T*)cur, F.p);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
 
-// Staging is used when every wave's halo fits: four waves' velocity records
-// and pressures (the damped pressure pass holds both) in 64 KiB, i.e. halos
-// of up to 819 nodes (the refined clouds here: about 350 on average, 500 at
-// most).
+// Staging is used with one or two lanes per node when the block's halos fit:
+// its tiles' velocity records and pressures (the damped pressure pass holds
+// both) in 64 KiB: halos of up to 819 nodes for FP32 at one lane (four tiles
+// per block), 1,638 for FP32 and 409 for FP64 at two lanes (two tiles; the
+// refined clouds here: about 350 on average, 573 at most at N_L = 30).
 constexpr size_t kAcmHaloLds = 64 * 1024;
 
 template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 int run_launches(Fields<T, TW>& F, const Halo* H, int n_steps, int n_p, bool edac, hipStream_t st) {
-  if constexpr (LPN == 1 && sizeof(T) == sizeof(float)) {
-    if (H && (size_t)(kBlock / kWave) * H->h_max * (sizeof(float4) + sizeof(float)) <= kAcmHaloLds)
-      return run_staged<TW, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
+  if constexpr (LPN <= 2) {
+    using R = typename Rec<T>::type;
+    if (H && (size_t)(kBlock / (kTile * LPN)) * H->h_max * (sizeof(R) + sizeof(T)) <= kAcmHaloLds)
+      return run_staged<T, TW, LPN, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
   }
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   T* cur = F.p;  // the pressure of the current iteration (alternates with F.P1 when damped)

@@ -17,7 +17,7 @@ import torch
 import nodecloud
 
 from . import api
-from ._lib import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, AcmParams, LbmParams
+from ._lib import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED, AcmParams, LbmParams, MPFError
 
 # state element type per precision (MPF_MIXED: FP32 weights, FP64 state)
 _DT = {MPF_F64: torch.float64, MPF_F32: torch.float32, MPF_MIXED: torch.float64, MPF_F32_KAHAN: torch.float32}
@@ -58,7 +58,10 @@ class Discretization:
         """The tile plan of the stencils for the LDS-staged gather (built on
         first use, once per discretization)."""
         if self._tiles is None:
-            self._tiles = api.TilePlan(self.sten)
+            try:
+                self._tiles = api.TilePlan(self.sten)
+            except MPFError:  # a halo over the default capacity: the largest the plan takes
+                self._tiles = api.TilePlan(self.sten, h_cap=4096)
         return self._tiles
 
     @property
@@ -102,20 +105,25 @@ class ACMSolver:
         self.steps = 0
 
     def run(self, n_steps: int):
-        # the tile plan matters only where the library stages (one lane per
-        # node, FP32 state); it is built once per discretization
-        tiles = self.d.tiles if self.staged and self.precision in (MPF_F32, MPF_F32_KAHAN) else None
+        # the tile plan is built once per discretization; the library stages
+        # where the lanes per node and the halos allow it
+        tiles = self.d.tiles if self.staged else None
         api.acm_run(self.prm, self.d.n_int, self.d.sten, self.w, self.d.sn, self.wn, self.v, self.p, self.vmax,
                     n_steps, self.ws, comp=self.comp, flags=self.flags if self.check else None, tiles=tiles)
         self.steps += n_steps
 
     def staged_now(self) -> bool:
-        """Whether run() takes the LDS-staged gather: a tile plan, an FP32
-        state, one lane per node (as the library picks it: above 50k
-        interior nodes) and a halo that fits (largest halo <= 819 nodes)."""
-        lanes = self.prm.lanes or (8 if self.d.n_int <= 12000 else 2 if self.d.n_int <= 50000 else 1)
-        return (self.staged and self.precision in (MPF_F32, MPF_F32_KAHAN) and lanes == 1
-                and self.d.tiles.h_max <= 819)
+        """Whether run() takes the LDS-staged gather: a tile plan, one or two
+        lanes per node (as the library picks them: 2 above 12k interior
+        nodes, 1 above 50k, and 2 again above 500k for an FP64 state) and a
+        block's halos within 64 KiB."""
+        n_int, fp64 = self.d.n_int, self.precision in (MPF_F64, MPF_MIXED)
+        lanes = self.prm.lanes or (8 if n_int <= 12000 else 2 if n_int <= 50000 else
+                                   2 if fp64 and n_int > 500000 else 1)
+        if not self.staged or lanes > 2:
+            return False
+        rec, val = (32, 8) if fp64 else (16, 4)
+        return (256 // (64 * lanes)) * self.d.tiles.h_max * (rec + val) <= 64 * 1024
 
     def clear_compensation(self):
         """After the state was set from outside (a warm start): the FP32

@@ -65,17 +65,19 @@ def test_staged_step_equals_cached_gather(disc, precision, q):
         assert torch.equal(a.comp, b.comp)
 
 
-@pytest.mark.parametrize("precision", [1, 3])
+@pytest.mark.parametrize("precision, lanes", [(1, 1), (1, 2), (3, 1), (3, 2), (0, 2), (2, 2)])
 @pytest.mark.parametrize("edac", [False, True])
-def test_staged_acm_equals_cached_gather(disc, precision, edac):
-    """The ACM passes with one lane per node and an FP32 state (plain and
-    compensated), with and without the damped pressure equation: staged and
-    cached gathers give the same fields bit for bit (same values, same
-    summation order), including the running max |v|."""
+def test_staged_acm_equals_cached_gather(disc, precision, lanes, edac):
+    """The ACM passes at one and two lanes per node, in every precision (FP32
+    and compensated FP32 at both; FP64 and mixed, whose 40-byte halo entries
+    fit four 64-node tiles only up to 409 entries, at two), with and without
+    the damped pressure equation: staged and cached gathers give the same
+    fields bit for bit (same values, same summation order), including the
+    running max |v|."""
     from paper_2404_14195_amd.solvers import ACMSolver
-    a = ACMSolver(disc, precision=precision, lanes=1, edac=edac, staged=True)
-    b = ACMSolver(disc, precision=precision, lanes=1, edac=edac, staged=False)
-    assert disc.tiles.h_max * 4 * 20 <= 64 * 1024  # the halo fits: the staged passes run
+    a = ACMSolver(disc, precision=precision, lanes=lanes, edac=edac, staged=True)
+    b = ACMSolver(disc, precision=precision, lanes=lanes, edac=edac, staged=False)
+    assert a.staged_now()  # the halo fits: the staged passes run
     for s in (a, b):
         s.run(60)
     assert torch.equal(a.v, b.v) and torch.equal(a.p, b.p) and torch.equal(a.vmax, b.vmax)
