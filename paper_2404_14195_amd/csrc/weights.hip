@@ -10,7 +10,12 @@
 // subtracts its multiple, keeping the multiplier in column c.  Right-hand
 // sides then go through forward and backward substitution over the stored
 // factors in chunks of RB, so the O(N^3) factorisation is done once per row
-// whatever the number of operators.  Everything runs on the vector ALU: a
+// whatever the number of operators.  With at most RB operators the
+// right-hand sides instead ride along as extra columns of a Gauss-Jordan
+// elimination (every row, not only those below the pivot, is reduced; in
+// this row-per-lane layout that costs no extra instructions) and each pivot
+// lane ends holding its unknown, with no substitution sweeps.  Everything
+// runs on the vector ALU: a
 // pivoted 40 x 40 LU per row is not a dense contraction MFMA tiles would
 // serve.
 //
@@ -154,6 +159,111 @@ __device__ __forceinline__ float bcastf(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// Scaled local coordinates of stencil column `lane` (zero beyond NL):
+// xi_j = minimg(x_j - x_c) / delta, delta the distance from the centre to
+// stencil column 1 (Eq. rbfScaling).
+template <int NL>
+__device__ __forceinline__ void local_coords(const double* __restrict__ pos, int64_t n_nodes,
+                                             const int32_t* __restrict__ sten, int64_t m, int64_t row, int lane,
+                                             double& xi0, double& xi1, double& xi2, double& delta) {
+  const int sj = sten[(int64_t)(lane < NL ? lane : 0) * m + row];
+  const int sc = sten[row];
+  double d0 = min_image(pos[sj] - pos[sc]);
+  double d1 = min_image(pos[n_nodes + sj] - pos[n_nodes + sc]);
+  double d2 = min_image(pos[2 * n_nodes + sj] - pos[2 * n_nodes + sc]);
+  const double q0 = bcast(d0, 1), q1 = bcast(d1, 1), q2 = bcast(d2, 1);
+  delta = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+  xi0 = d0 / delta; xi1 = d1 / delta; xi2 = d2 / delta;
+  if (lane >= NL) xi0 = xi1 = xi2 = 0.0;
+}
+
+// Row `lane` of M = [A P; P^T 0] (Eq. augmentedSystem; zero beyond N).
+template <int NL>
+__device__ __forceinline__ void assemble_row(int lane, double xi0, double xi1, double xi2, double (&a)[NL + 10]) {
+  constexpr int N = NL + 10;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    double x0 = bcast(xi0, k), x1 = bcast(xi1, k), x2 = bcast(xi2, k);
+    a[k] = lane < NL ? cube_dist(xi0, xi1, xi2, x0, x1, x2) : (lane < N ? mono(lane - NL, x0, x1, x2) : 0.0);
+  }
+#pragma unroll
+  for (int l = 0; l < 10; ++l) a[NL + l] = lane < NL ? mono(l, xi0, xi1, xi2) : 0.0;
+}
+
+// Store weight j (the stencil column this lane solved for; none if j >= NL)
+// of operator o: FP64 as solved, FP32 with the centre weight set so that the
+// FP32 row sums to the operator's value on constants (1 for shifts and the
+// Taylor row, 0 for derivatives), the sum taken in FP64 over the wave.
+template <int NL>
+__device__ __forceinline__ void store_weights(const OpsArg& ops, int o, int j, double x, double* __restrict__ w64,
+                                              float* __restrict__ w32, int64_t m, int64_t row) {
+  if (w64 && j < NL) w64[((int64_t)o * NL + j) * m + row] = x;
+  if (w32) {
+    float xf = (float)x;
+    double part = (j >= 1 && j < NL) ? (double)xf : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    const int kd = ops.kind[o];
+    const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW || kd == MPF_OP_TAYLOR) ? 1.0 : 0.0;
+    if (j == 0) xf = (float)(target - part);
+    if (j < NL) w32[((int64_t)o * NL + j) * m + row] = xf;
+  }
+}
+
+// Up to RB operators: Gauss-Jordan elimination of the augmented matrix
+// [M | b_1 .. b_RB] with partial pivoting, rows in place.  Each pivot row is
+// broadcast once and every other row (above and below) subtracts its
+// multiple, right-hand sides included, so after the last column the pivot
+// row of column c holds M'_cc x_c = b'_c and no substitution sweeps follow.
+// The pivot choice is the LU's (same keys, same order), so the two agree to
+// rounding.
+template <int NL>
+__device__ __forceinline__ void solve_row_gj(const double* __restrict__ pos, int64_t n_nodes,
+                                             const int32_t* __restrict__ sten, int64_t m, int64_t row,
+                                             const OpsArg& ops, const double* __restrict__ rowvec,
+                                             double* __restrict__ w64, float* __restrict__ w32,
+                                             int32_t* __restrict__ info, int lane) {
+  constexpr int N = NL + 10;
+  static_assert(N <= kWave, "system does not fit one wave");
+  double xi0, xi1, xi2, delta;
+  local_coords<NL>(pos, n_nodes, sten, m, row, lane, xi0, xi1, xi2, delta);
+  const double rho = sqrt(xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
+  double a[N];
+  assemble_row<NL>(lane, xi0, xi1, xi2, a);
+  double rvv[3] = {0.0, 0.0, 0.0};
+  if (rowvec) { rvv[0] = rowvec[row]; rvv[1] = rowvec[m + row]; rvv[2] = rowvec[2 * m + row]; }
+  double b[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    b[r] = (r < ops.n && lane < N) ? rhs_entry<NL>(ops.kind[r], ops.vec[r], rvv, lane, xi0, xi1, xi2, rho, delta)
+                                   : 0.0;
+
+  int pcol = (lane < N) ? 1 << 20 : -1;  // column at which this lane became pivot
+  int bad = 0;
+  double dinv = 0.0;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    const unsigned key = (pcol > c) ? (unsigned)__double2hiint(fabs(a[c])) : 0u;
+    const int p = pivot_lane(key);
+    if (p < 0 || !(fabs(bcast(a[c], p)) > 0.0)) { bad = c + 1; break; }
+    const double inv = 1.0 / bcast(a[c], p);
+    if (lane == p) { pcol = c; dinv = inv; }
+    // every row but the pivot's; a zero multiplier leaves a row as it is
+    const double l = lane != p ? a[c] * inv : 0.0;
+#pragma unroll
+    for (int k = c + 1; k < N; ++k) a[k] = fma(-l, bcast(a[k], p), a[k]);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) b[r] = fma(-l, bcast(b[r], p), b[r]);
+  }
+  const int j = (!bad && lane < N) ? pcol : kWave;  // the unknown this lane holds
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (r >= ops.n) break;
+    store_weights<NL>(ops, r, bad ? lane : j, bad ? __builtin_nan("") : b[r] * dinv, w64, w32, m, row);
+  }
+  if (lane == 0) info[row] = bad;
+}
+
 template <int NL>
 __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, int64_t n_nodes,
                                                const int32_t* __restrict__ sten, int64_t m, int64_t row,
@@ -163,31 +273,11 @@ __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, i
   constexpr int N = NL + 10;
   static_assert(N <= kWave, "system does not fit one wave");
 
-  // --- scaled local coordinates xi_j = minimg(x_j - x_c) / delta, with
-  // delta the distance from the centre to stencil column 1
   double xi0, xi1, xi2, delta;
-  {
-    const int sj = sten[(int64_t)(lane < NL ? lane : 0) * m + row];
-    const int sc = sten[row];
-    double d0 = min_image(pos[sj] - pos[sc]);
-    double d1 = min_image(pos[n_nodes + sj] - pos[n_nodes + sc]);
-    double d2 = min_image(pos[2 * n_nodes + sj] - pos[2 * n_nodes + sc]);
-    const double q0 = bcast(d0, 1), q1 = bcast(d1, 1), q2 = bcast(d2, 1);
-    delta = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
-    xi0 = d0 / delta; xi1 = d1 / delta; xi2 = d2 / delta;
-    if (lane >= NL) xi0 = xi1 = xi2 = 0.0;
-  }
+  local_coords<NL>(pos, n_nodes, sten, m, row, lane, xi0, xi1, xi2, delta);
   const double rho = sqrt(xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
-
-  // --- assemble row `lane` of M
   double a[N];
-#pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    double x0 = bcast(xi0, k), x1 = bcast(xi1, k), x2 = bcast(xi2, k);
-    a[k] = lane < NL ? cube_dist(xi0, xi1, xi2, x0, x1, x2) : (lane < N ? mono(lane - NL, x0, x1, x2) : 0.0);
-  }
-#pragma unroll
-  for (int l = 0; l < 10; ++l) a[NL + l] = lane < NL ? mono(l, xi0, xi1, xi2) : 0.0;
+  assemble_row<NL>(lane, xi0, xi1, xi2, a);
 
   // --- LU with partial pivoting, rows in place
   int pcol = (lane < N) ? 1 << 20 : -1;  // column at which this lane became pivot
@@ -247,22 +337,10 @@ __device__ __forceinline__ void solve_row_fp64(const double* __restrict__ pos, i
 #pragma unroll
       for (int r = 0; r < RB; ++r) x[r] = __builtin_nan("");
     }
-    // store w[o][j][row]; FP32 copy with the self weight fixing the row sum
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      int o = o0 + r;
-      if (o >= ops.n) break;
-      if (w64 && lane < NL) w64[((int64_t)o * NL + lane) * m + row] = x[r];
-      if (w32) {
-        float xf = (float)x[r];
-        double part = (lane >= 1 && lane < NL) ? (double)xf : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-        const int kd = ops.kind[o];
-        const double target = (kd == MPF_OP_SHIFT || kd == MPF_OP_SHIFT_ROW || kd == MPF_OP_TAYLOR) ? 1.0 : 0.0;
-        if (lane == 0) xf = (float)(target - part);
-        if (lane < NL) w32[((int64_t)o * NL + lane) * m + row] = xf;
-      }
+      if (o0 + r >= ops.n) break;
+      store_weights<NL>(ops, o0 + r, lane, x[r], w64, w32, m, row);
     }
   }
   if (lane == 0) info[row] = bad;
@@ -418,7 +496,12 @@ __device__ __forceinline__ bool solve_row_ir(const double* __restrict__ pos, int
   return true;
 }
 
-template <int NL, bool IR>
+// How a launch solves its rows: LU with substitution sweeps (any number of
+// operators), Gauss-Jordan (at most RB operators), or FP32 factors with
+// FP64-residual refinement (LU in FP64 for the rows it cannot settle).
+enum Path { kPathLU = 0, kPathGJ = 1, kPathIR = 2 };
+
+template <int NL, int PATH>
 __global__ __launch_bounds__(512) void weights_batched(const GeomArg* __restrict__ table, int n_geoms, int64_t total,
                                                        OpsArg ops, int rows_per_wave) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -430,11 +513,16 @@ __global__ __launch_bounds__(512) void weights_batched(const GeomArg* __restrict
     while (g + 1 < n_geoms && r >= table[g + 1].row0) ++g;
     const GeomArg G = table[g];
     const int64_t row = r - G.row0;
-    bool done = false;
-    if (IR) done = solve_row_ir<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
-    if (!done) {
-      solve_row_fp64<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
-      if (IR && lane == 0 && G.info[row] == 0) G.info[row] = -1;
+    if constexpr (PATH == kPathGJ) {
+      solve_row_gj<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
+    } else {
+      bool done = false;
+      if (PATH == kPathIR)
+        done = solve_row_ir<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
+      if (!done) {
+        solve_row_fp64<NL>(G.pos, G.n_nodes, G.sten, G.m, row, ops, G.rowvec, G.w64, G.w32, G.info, lane);
+        if (PATH == kPathIR && lane == 0 && G.info[row] == 0) G.info[row] = -1;
+      }
     }
   }
 }
@@ -443,30 +531,36 @@ struct Tune {
   int waves, rows;  // waves per block, consecutive rows per wave
 };
 
-template <int NL, bool IR>
+template <int NL, int PATH>
 int launch(const BatchArg& B, const OpsArg& ops, const Tune& t, const void* ws, hipStream_t st) {
   const int64_t rows_per_block = (int64_t)t.waves * t.rows;
   const int64_t blocks = (B.total + rows_per_block - 1) / rows_per_block;
   const GeomArg* table = reinterpret_cast<const GeomArg*>(reinterpret_cast<const char*>(ws) + kTableOffset);
-  hipLaunchKernelGGL((weights_batched<NL, IR>), dim3((unsigned)blocks), dim3(t.waves * kWave), 0, st, table, B.n_geoms,
-                     B.total, ops, t.rows);
+  hipLaunchKernelGGL((weights_batched<NL, PATH>), dim3((unsigned)blocks), dim3(t.waves * kWave), 0, st, table,
+                     B.n_geoms, B.total, ops, t.rows);
   MPF_LAUNCH_CHECK();
   return MPF_OK;
 }
 
-template <bool IR>
-int dispatch(int nl, const BatchArg& B, const OpsArg& ops, const Tune& t, const void* ws, hipStream_t st) {
+template <int PATH>
+int dispatch_nl(int nl, const BatchArg& B, const OpsArg& ops, const Tune& t, const void* ws, hipStream_t st) {
   switch (nl) {
-    case 20: return launch<20, IR>(B, ops, t, ws, st);
-    case 25: return launch<25, IR>(B, ops, t, ws, st);
-    case 27: return launch<27, IR>(B, ops, t, ws, st);
-    case 30: return launch<30, IR>(B, ops, t, ws, st);
-    case 35: return launch<35, IR>(B, ops, t, ws, st);
-    case 40: return launch<40, IR>(B, ops, t, ws, st);
-    case 45: return launch<45, IR>(B, ops, t, ws, st);
-    case 50: return launch<50, IR>(B, ops, t, ws, st);
+    case 20: return launch<20, PATH>(B, ops, t, ws, st);
+    case 25: return launch<25, PATH>(B, ops, t, ws, st);
+    case 27: return launch<27, PATH>(B, ops, t, ws, st);
+    case 30: return launch<30, PATH>(B, ops, t, ws, st);
+    case 35: return launch<35, PATH>(B, ops, t, ws, st);
+    case 40: return launch<40, PATH>(B, ops, t, ws, st);
+    case 45: return launch<45, PATH>(B, ops, t, ws, st);
+    case 50: return launch<50, PATH>(B, ops, t, ws, st);
     default: return MPF_ERR_UNSUPPORTED;
   }
+}
+
+int dispatch(int solve, int nl, const BatchArg& B, const OpsArg& ops, const Tune& t, const void* ws,
+             hipStream_t st) {
+  if (solve != MPF_SOLVE_FP64) return dispatch_nl<kPathIR>(nl, B, ops, t, ws, st);
+  return ops.n <= RB ? dispatch_nl<kPathGJ>(nl, B, ops, t, ws, st) : dispatch_nl<kPathLU>(nl, B, ops, t, ws, st);
 }
 bool nl_supported(int nl) {
   return nl == 20 || nl == 25 || nl == 27 || nl == 30 || nl == 35 || nl == 40 || nl == 45 || nl == 50;
@@ -585,7 +679,7 @@ extern "C" int mpf_rbffd_weights_batched(mpf_ctx* ctx, int n_geoms, const mpf_wg
   hipStream_t st = as_stream(stream);
   rc = upload_table(B, ws, st);
   if (rc) return rc;
-  return solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
+  return dispatch(solve, nl, B, a, t, ws, st);
 }
 
 extern "C" int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_op* ops, int solve,
@@ -619,10 +713,10 @@ extern "C" int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_o
   for (int w : waves) {
     for (int rr : rows) {
       Tune t{w, rr};
-      rc = solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
+      rc = dispatch(solve, nl, B, a, t, ws, st);
       if (rc) { err = rc; break; }
       (void)hipEventRecord(e0, st);
-      rc = solve == MPF_SOLVE_FP64 ? dispatch<false>(nl, B, a, t, ws, st) : dispatch<true>(nl, B, a, t, ws, st);
+      rc = dispatch(solve, nl, B, a, t, ws, st);
       (void)hipEventRecord(e1, st);
       if (rc) { err = rc; break; }
       if (hipEventSynchronize(e1) != hipSuccess) { err = MPF_ERR_HIP; break; }
