@@ -618,7 +618,8 @@ def acm_sweep(torch, cells, steps=2000, nl=30):
     return out
 
 
-def acm_steady(torch, clouds, nl=30, check=5000, tol=1e-9, max_steps=1_000_000, v_ref=1.0, max_seconds=240.0):
+def acm_steady(torch, clouds, nl=30, check=5000, tol=1e-9, max_steps=1_000_000, v_ref=1.0, max_seconds=240.0,
+               edac=False):
     """The ACM's steady-state permeability per precision: every precision
     from rest until k changes by at most tol (relative) per check, or its
     last five checks agree to 1e-8 (the compensated state's k moves by about
@@ -626,7 +627,8 @@ def acm_steady(torch, clouds, nl=30, check=5000, tol=1e-9, max_steps=1_000_000, 
     C = beta max(max|v|, v_ref) (v_ref = 1: C = 10, which settles these
     cells), and the settled k of FP32, compensated FP32 and mixed against
     FP64's.  A precision that has not settled after max_seconds is recorded
-    as such.  clouds: [(name, cloud)]."""
+    as such.  edac: the damped pressure equation (with v_ref = 100, C = 1000,
+    it settles on the incompressible state).  clouds: [(name, cloud)]."""
     from paper_2404_14195_amd import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED
     from paper_2404_14195_amd._lib import MPFDiverged
     from paper_2404_14195_amd.solvers import ACMSolver, Discretization
@@ -635,9 +637,9 @@ def acm_steady(torch, clouds, nl=30, check=5000, tol=1e-9, max_steps=1_000_000, 
     for cname, c in clouds:
         disc = Discretization(c, nl=nl, M=64)
         rec = {"cell": cname, "r": c.r, "n": c.n, "h_min": c.h_min, "nl": nl, "v_ref": v_ref, "check": check,
-               "tol": tol}
+               "tol": tol, "edac": edac}
         for name, prec in (("fp64", MPF_F64), ("fp32", MPF_F32), ("fp32_kahan", MPF_F32_KAHAN), ("mixed", MPF_MIXED)):
-            s = ACMSolver(disc, precision=prec, v_ref=v_ref)
+            s = ACMSolver(disc, precision=prec, v_ref=v_ref, edac=edac)
             t0 = time.perf_counter()
             ks, t_say, settled = [], t0, False
             try:
@@ -1340,6 +1342,9 @@ def main():
                     help="only the ACM's steady-state k per precision (the 8k-node cell and C3-shaped cells)")
     ap.add_argument("--acm-steady-radii", type=float, nargs="+", default=[0.55])
     ap.add_argument("--acm-steady-h0", type=float, default=0.005)
+    ap.add_argument("--acm-steady-vref", type=float, default=1.0)
+    ap.add_argument("--acm-steady-edac", action="store_true", help="the damped pressure equation")
+    ap.add_argument("--acm-steady-max-s", type=float, default=240.0, help="time cap per precision and cell")
     ap.add_argument("--acm-steady-skip-small", action="store_true",
                     help="leave out the 8k-node cell (with v_ref = 1 its run develops the growing pressure mode)")
     ap.add_argument("--paper-stop", type=float, nargs="+", default=None, metavar="R",
@@ -1400,7 +1405,8 @@ def main():
                  [(f"sweep_r{r}_h{args.acm_steady_h0}", nc.sphere_cloud(r, args.acm_steady_h0, 0.3,
                                                                         4 * args.acm_steady_h0, seed=3))
                   for r in args.acm_steady_radii]
-        print(json.dumps({"acm_steady": acm_steady(torch, clouds)}))
+        print(json.dumps({"acm_steady": acm_steady(torch, clouds, v_ref=args.acm_steady_vref, edac=args.acm_steady_edac,
+                                                   max_seconds=args.acm_steady_max_s)}))
         return
     if args.weights_cell:
         torch.cuda.set_device(0)

@@ -92,6 +92,27 @@ __device__ __forceinline__ double mono(int l, double x, double y, double z) {
   }
 }
 
+// The monomial p_l of a lane-dependent l without branches: p_l = f1 f2 with
+// each factor one of 1, x, y, z, picked by 0/1 coefficients, so the value is
+// the same as mono(l, ...) bit for bit (one coefficient is 1, the rest 0).
+struct MonoPick {
+  double c1[4], c2[4];  // coefficients of (1, x, y, z) in f1 and f2
+  __device__ __forceinline__ explicit MonoPick(int l) {
+    const int i1 = l < 4 ? l : (l < 7 ? 1 : (l < 9 ? 2 : 3));
+    const int i2 = l < 4 ? 0 : (l == 4 ? 1 : (l == 5 ? 2 : (l == 6 ? 3 : (l == 7 ? 2 : 3))));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c1[q] = q == i1 ? 1.0 : 0.0;
+      c2[q] = q == i2 ? 1.0 : 0.0;
+    }
+  }
+  __device__ __forceinline__ double operator()(double x, double y, double z) const {
+    const double f1 = fma(c1[1], x, fma(c1[2], y, fma(c1[3], z, c1[0])));
+    const double f2 = fma(c2[1], x, fma(c2[2], y, fma(c2[3], z, c2[0])));
+    return f1 * f2;
+  }
+};
+
 __device__ __forceinline__ double cube_dist(double ax, double ay, double az, double bx, double by, double bz) {
   double dx = ax - bx, dy = ay - by, dz = az - bz;
   double r = sqrt(dx * dx + dy * dy + dz * dz);
@@ -181,10 +202,11 @@ __device__ __forceinline__ void local_coords(const double* __restrict__ pos, int
 template <int NL>
 __device__ __forceinline__ void assemble_row(int lane, double xi0, double xi1, double xi2, double (&a)[NL + 10]) {
   constexpr int N = NL + 10;
+  const MonoPick pick(lane >= NL && lane < N ? lane - NL : 0);
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     double x0 = bcast(xi0, k), x1 = bcast(xi1, k), x2 = bcast(xi2, k);
-    a[k] = lane < NL ? cube_dist(xi0, xi1, xi2, x0, x1, x2) : (lane < N ? mono(lane - NL, x0, x1, x2) : 0.0);
+    a[k] = lane < NL ? cube_dist(xi0, xi1, xi2, x0, x1, x2) : (lane < N ? pick(x0, x1, x2) : 0.0);
   }
 #pragma unroll
   for (int l = 0; l < 10; ++l) a[NL + l] = lane < NL ? mono(l, xi0, xi1, xi2) : 0.0;
@@ -208,6 +230,17 @@ __device__ __forceinline__ void store_weights(const OpsArg& ops, int o, int j, d
     if (j == 0) xf = (float)(target - part);
     if (j < NL) w32[((int64_t)o * NL + j) * m + row] = xf;
   }
+}
+
+// 1/d from the hardware's approximate reciprocal and two Newton steps
+// r <- r + r (1 - d r): within an ulp or so of the rounded quotient, for the
+// normal, moderate pivots of these scaled systems.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
 }
 
 // Up to RB operators: Gauss-Jordan elimination of the augmented matrix
@@ -245,8 +278,9 @@ __device__ __forceinline__ void solve_row_gj(const double* __restrict__ pos, int
   for (int c = 0; c < N; ++c) {
     const unsigned key = (pcol > c) ? (unsigned)__double2hiint(fabs(a[c])) : 0u;
     const int p = pivot_lane(key);
-    if (p < 0 || !(fabs(bcast(a[c], p)) > 0.0)) { bad = c + 1; break; }
-    const double inv = 1.0 / bcast(a[c], p);
+    const double piv = bcast(a[c], p);
+    if (p < 0 || !(fabs(piv) > 0.0)) { bad = c + 1; break; }
+    const double inv = recip(piv);
     if (lane == p) { pcol = c; dinv = inv; }
     // every row but the pivot's; a zero multiplier leaves a row as it is
     const double l = lane != p ? a[c] * inv : 0.0;
