@@ -319,8 +319,9 @@ int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* co
  * lanes: how many adjacent lanes share one node's stencil sum (1, 2, 4, 8 or
  * 16; 0 lets the library pick from n_int and the state's precision: 8 up to
  * 12000 interior nodes, 2 up to 50000, then 1, and 2 again above 500000 for
- * an FP64 state).  Results agree to rounding (the order of the partial sums
- * differs).
+ * an FP64 state; 2 in place of 1 when a tile plan is given whose halos fit
+ * LDS at two lanes but not at one).  Results agree to rounding (the order of
+ * the partial sums differs).
  * edac: 0 for the method as written; 1 for the entropically damped pressure
  * equation, which Sec. 2.3 names as the remedy for the stagnant-region
  * pressure oscillations of Sec. 3.6.  Its pressure update is

@@ -570,16 +570,22 @@ int run_staged(Fields<T, TW>& F, const Halo& H, int n_steps, int n_p, bool edac,
 // Staging is used with one or two lanes per node when the block's halos fit:
 // its tiles' velocity records and pressures (the damped pressure pass holds
 // both) in 64 KiB: halos of up to 819 nodes for FP32 at one lane (four tiles
-// per block), 1,638 for FP32 and 409 for FP64 at two lanes (two tiles; the
-// refined clouds here: about 350 on average, 573 at most at N_L = 30).
+// per block) and for FP64 at two (two tiles), 1,638 for FP32 at two lanes,
+// 409 for FP64 at one (the refined clouds here: about 350 on average, 573 at
+// most at N_L = 30, up to 1,100 at N_L = 50).
 constexpr size_t kAcmHaloLds = 64 * 1024;
+
+template <typename T>
+bool halo_fits(int lanes, int h_max) {
+  using R = typename Rec<T>::type;
+  return (lanes == 1 || lanes == 2) &&
+         (size_t)(kBlock / (kTile * lanes)) * (size_t)h_max * (sizeof(R) + sizeof(T)) <= kAcmHaloLds;
+}
 
 template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 int run_launches(Fields<T, TW>& F, const Halo* H, int n_steps, int n_p, bool edac, hipStream_t st) {
   if constexpr (LPN <= 2) {
-    using R = typename Rec<T>::type;
-    if (H && (size_t)(kBlock / (kTile * LPN)) * H->h_max * (sizeof(R) + sizeof(T)) <= kAcmHaloLds)
-      return run_staged<T, TW, LPN, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
+    if (H && halo_fits<T>(LPN, H->h_max)) return run_staged<T, TW, LPN, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
   }
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   T* cur = F.p;  // the pressure of the current iteration (alternates with F.P1 when damped)
@@ -657,13 +663,18 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
     hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(4 * n, kBlock)), dim3(kBlock), 0, st, F.VPL, 4 * n);
   }
   const bool edac = prm->edac != 0;
-  int lanes = prm->lanes;
-  if (lanes == 0) lanes = default_lanes<T>(n_int);
   Halo hd{};
   const Halo* H = nullptr;
   if (tiles) {
     hd = Halo{tiles->count, tiles->halo, tiles->lidx, tiles->h_cap, tiles->h_max};
     H = &hd;
+  }
+  int lanes = prm->lanes;
+  if (lanes == 0) {
+    lanes = default_lanes<T>(n_int);
+    // a one-lane pass whose halos do not fit LDS gathers through the caches;
+    // two lanes per node halve the tiles per block, and staged they beat it
+    if (H && lanes == 1 && !halo_fits<T>(1, H->h_max) && halo_fits<T>(2, H->h_max)) lanes = 2;
   }
   int rc;
   if constexpr (sizeof(T) == sizeof(float))  // the compensated state is FP32

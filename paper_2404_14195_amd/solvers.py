@@ -115,15 +115,19 @@ class ACMSolver:
     def staged_now(self) -> bool:
         """Whether run() takes the LDS-staged gather: a tile plan, one or two
         lanes per node (as the library picks them: 2 above 12k interior
-        nodes, 1 above 50k, and 2 again above 500k for an FP64 state) and a
-        block's halos within 64 KiB."""
+        nodes, 1 above 50k, and 2 again above 500k for an FP64 state or where
+        the halos fit LDS at two lanes but not at one) and a block's halos
+        within 64 KiB."""
+        if not self.staged:
+            return False
         n_int, fp64 = self.d.n_int, self.precision in (MPF_F64, MPF_MIXED)
+        rec, val = (32, 8) if fp64 else (16, 4)
+        fits = lambda lanes: lanes <= 2 and (256 // (64 * lanes)) * self.d.tiles.h_max * (rec + val) <= 64 * 1024
         lanes = self.prm.lanes or (8 if n_int <= 12000 else 2 if n_int <= 50000 else
                                    2 if fp64 and n_int > 500000 else 1)
-        if not self.staged or lanes > 2:
-            return False
-        rec, val = (32, 8) if fp64 else (16, 4)
-        return (256 // (64 * lanes)) * self.d.tiles.h_max * (rec + val) <= 64 * 1024
+        if not self.prm.lanes and lanes == 1 and not fits(1) and fits(2):
+            lanes = 2
+        return fits(lanes)
 
     def clear_compensation(self):
         """After the state was set from outside (a warm start): the FP32
