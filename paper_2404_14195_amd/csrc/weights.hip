@@ -278,8 +278,9 @@ __device__ __forceinline__ void solve_row_gj(const double* __restrict__ pos, int
   for (int c = 0; c < N; ++c) {
     const unsigned key = (pcol > c) ? (unsigned)__double2hiint(fabs(a[c])) : 0u;
     const int p = pivot_lane(key);
+    if (p < 0) { bad = c + 1; break; }
     const double piv = bcast(a[c], p);
-    if (p < 0 || !(fabs(piv) > 0.0)) { bad = c + 1; break; }
+    if (!(fabs(piv) > 0.0)) { bad = c + 1; break; }
     const double inv = recip(piv);
     if (lane == p) { pcol = c; dinv = inv; }
     // every row but the pivot's; a zero multiplier leaves a row as it is

@@ -99,3 +99,43 @@ def test_staged_acm_fp32_against_the_oracle(disc):
     k = g.permeability()
     print(f"[acm staged fp32] k={k:.9e} k64={q_o:.9e} rel={abs(k / q_o - 1):.3e}", flush=True)
     assert k == pytest.approx(q_o, rel=1e-4)
+
+
+@pytest.fixture(scope="module")
+def mid_disc():
+    """The 71k-node cell (55,662 interior nodes: one lane per node by default
+    for an FP32 state)."""
+    from paper_2404_14195_amd.solvers import Discretization
+    return Discretization(nc.config_cloud("lbm_mid"), nl=30, M=16)
+
+
+def test_acm_takes_two_lanes_when_one_lane_halos_do_not_fit(mid_disc):
+    """With the lanes left to the library, a tile plan whose halos fit LDS at
+    two lanes per node but not at one (here the real plan with its h_max
+    raised to 900 > 819: the staged passes size LDS by h_max and copy only
+    each tile's own count) runs the two-lane staged passes: the same fields
+    bit for bit as lanes = 2 with the plan as built."""
+    from types import SimpleNamespace
+
+    from paper_2404_14195_amd import MPF_F32
+    from paper_2404_14195_amd._lib import Tiles
+    from paper_2404_14195_amd.solvers import ACMSolver
+    d = mid_disc
+    plan = d.tiles
+    assert plan.h_max <= 819 < 900 <= plan.h_cap
+    big = SimpleNamespace(rec=Tiles(count=plan.rec.count, halo=plan.rec.halo, lidx=plan.rec.lidx,
+                                    h_cap=plan.h_cap, h_max=900), h_max=900, h_cap=plan.h_cap)
+    a = ACMSolver(d, precision=MPF_F32)  # lanes from the library
+    b = ACMSolver(d, precision=MPF_F32, lanes=2)
+    one = ACMSolver(d, precision=MPF_F32, lanes=1)
+    try:
+        d._tiles = big
+        assert a.staged_now()
+        a.run(40)
+    finally:
+        d._tiles = plan
+    b.run(40)
+    one.run(40)
+    assert torch.equal(a.v, b.v) and torch.equal(a.p, b.p) and torch.equal(a.vmax, b.vmax)
+    # one lane per node sums in another order: equal to rounding only
+    assert torch.allclose(one.v, b.v, rtol=1e-4, atol=1e-9)
