@@ -1221,14 +1221,17 @@ def acm_bytes_per_node_step(nl, s_w, s_f, n_p=3, s_i=4, edac=False, halo=0.0):
             + n_p * ((3 * s_w + s_i) * nl + 7 * s_f) + (1 + 2 * n_p) * halo)
 
 
-def acm_bytes_per_step(disc, s_w, s_f, n_p=3, staged=False, edac=False):
+def acm_bytes_per_step(disc, s_w, s_f, n_p=3, staged=False, edac=False, plan=None):
     """Algorithmic bytes of one ACM step of a discretisation: the interior
     passes for its n_int interior nodes, and n_p Neumann passes over its nb
-    boundary nodes (their weight rows and 4-byte indices, p_b written)."""
+    boundary nodes (their weight rows and 4-byte indices, p_b written).
+    plan: the tile plan the staged passes use (default the 64-node one)."""
     halo = 0.0
     if staged:
-        t_int = (disc.n_int + 63) // 64
-        halo = 4.0 * int(disc.tiles.count[:t_int].sum().item()) / disc.n_int
+        plan = disc.tiles if plan is None else plan
+        ts = getattr(plan, "tile", 64)
+        t_int = (disc.n_int + ts - 1) // ts
+        halo = 4.0 * int(plan.count[:t_int].sum().item()) / disc.n_int
     inner = acm_bytes_per_node_step(disc.nl, s_w, s_f, n_p, s_i=2 if staged else 4, edac=edac, halo=halo)
     return disc.n_int * inner + disc.nb * n_p * ((s_w + 4) * disc.nl + s_f)
 
@@ -1274,8 +1277,9 @@ def acm_and_weights(torch, nc, api):
             torch.cuda.synchronize()
             ms = ev0.elapsed_time(ev1)
             sz = 8 if prec == MPF_F64 else 4
-            # FP32 on the large cell runs the staged gather (one lane per node)
-            bps = acm_bytes_per_step(disc, sz, sz, staged=s2.staged_now())
+            # the large cell runs the staged gather (one tile of 256 nodes per block
+            # at one lane per node, of 128 at two)
+            bps = acm_bytes_per_step(disc, sz, sz, staged=s2.staged_now(), plan=disc.tiles_of(s2.tile))
             rec[pname] = {"us_per_step": ms * 1e3 / steps, "node_steps_per_s": cloud.n * steps / (ms * 1e-3),
                           "k_after": s2.permeability(), "bytes_per_step": bps,
                           "hbm_frac": bps / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, "weights_ms": w_ms,
@@ -1297,7 +1301,7 @@ def acm_and_weights(torch, nc, api):
                 torch.cuda.synchronize()
                 ms = ev0.elapsed_time(ev1)
                 sz = 8 if prec == MPF_F64 else 4
-                bps = acm_bytes_per_step(disc, sz, sz, staged=s.staged_now(), edac=True)
+                bps = acm_bytes_per_step(disc, sz, sz, staged=s.staged_now(), edac=True, plan=disc.tiles_of(s.tile))
                 rec[pname] = {"us_per_step": ms * 1e3 / steps, "node_steps_per_s": cloud.n * steps / (ms * 1e-3),
                               "bytes_per_step": bps, "staged": s.staged_now(),
                               "hbm_frac": bps / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS}
@@ -1406,6 +1410,8 @@ def main():
     ap.add_argument("--lbm-large-steps", type=int, default=300)
     ap.add_argument("--weights-batch", action="store_true",
                     help="only measure the batched weight solve of 8 cells (about 18M rows) and exit")
+    ap.add_argument("--acm-tile", type=int, default=0, choices=[0, 64, 128, 256],
+                    help="nodes per tile of the ACM's staged passes (0: one tile per block)")
     ap.add_argument("--acm-profile", default=None, choices=["f32", "f32_kahan", "mixed", "f64"],
                     help="only the ACM steps of one precision on the 1.83M-node cell, --steps steps (counter runs)")
     ap.add_argument("--profile-kernel", default=None, choices=["f32", "f32_kahan", "mixed", "f64"],
@@ -1522,7 +1528,7 @@ def main():
         prec = {"f32": MPF_F32, "f32_kahan": MPF_F32_KAHAN, "mixed": MPF_MIXED, "f64": MPF_F64}[args.acm_profile]
         cloud = nc.config_cloud("acm_large")
         disc = Discretization(cloud, nl=30, M=64)
-        s = ACMSolver(disc, precision=prec, check=False)
+        s = ACMSolver(disc, precision=prec, check=False, tile=args.acm_tile)
         s.run(5)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -1530,9 +1536,12 @@ def main():
         s.run(args.steps)
         ev1.record()
         torch.cuda.synchronize()
+        sz = 8 if prec in (MPF_F64,) else 4
         print(json.dumps({"acm_profile": args.acm_profile, "n_nodes": disc.n, "n_interior": disc.n_int,
                           "steps": args.steps, "us_per_step": ev0.elapsed_time(ev1) * 1e3 / args.steps,
-                          "k": s.permeability()}))
+                          "k": s.permeability(), "tile": s.tile, "staged": s.staged_now(),
+                          "bytes_per_step": acm_bytes_per_step(disc, sz, 8 if prec in (MPF_F64, MPF_MIXED) else 4,
+                                                               staged=s.staged_now(), plan=disc.tiles_of(s.tile))}))
         return
     if args.lbm_large:
         print(json.dumps({"lbm_large": lbm_large(torch, nc, steps=args.lbm_large_steps)}))

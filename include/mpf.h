@@ -243,31 +243,37 @@ int mpf_rbffd_weights_batched(mpf_ctx* ctx, int n_geoms, const mpf_wgeom* geoms_
 int mpf_weights_autotune(mpf_ctx* ctx, int nl, int n_ops, const mpf_op* ops, int solve, const mpf_wgeom* sample,
                          int64_t sample_rows, mpf_wtune* out, void* ws, size_t ws_bytes);
 
-/* Tile plan of the LDS-staged stencil gather.  The MLBM step and the ACM
- * passes work on tiles of 64 consecutive nodes; a tile's stencils (Sec. 2.1) name few distinct
- * nodes (about 350 for 64 x 30 entries on the refined clouds here).  The
- * plan lists each tile's distinct stencil nodes in ascending order (its
- * halo) and every stencil entry as its 16-bit position in that list, so a
- * step copies the halo's records into LDS with contiguous loads and gathers
- * from LDS.  Built once per stencil set:
- *   count dev int32 [G + 1], G = mpf_tile_count(n): halo sizes, and in
- *         count[G] the largest (also returned in *h_max_host)
+/* Tile plan of the LDS-staged stencil gather.  The MLBM step works on tiles
+ * of 64 consecutive nodes, the ACM passes on tiles of 64, 128 or 256; a
+ * tile's stencils (Sec. 2.1) name few distinct nodes (about 350 for 64 x 30
+ * entries on the refined clouds here, 940 for 256 x 30).  The plan lists
+ * each tile's distinct stencil nodes in ascending order (its halo) and every
+ * stencil entry as its 16-bit position in that list, so a step copies the
+ * halo's records into LDS with contiguous loads and gathers from LDS.  Built
+ * once per stencil set and tile size:
+ *   count dev int32 [G + 1], G = mpf_tile_count_sized(n, tile): halo sizes,
+ *         and in count[G] the largest (also returned in *h_max_host)
  *   halo  dev int32 [G][h_cap]: the halo of tile t in halo[t][0, count[t])
- *   lidx  dev uint16 [nl][n]: sten[j][i] == halo[i / 64][lidx[j][i]]
- * sten dev [nl][n]; 1 <= nl <= 64; 64 <= h_cap <= 4096.  The call waits for
- * the stream (it reads back the largest halo) and returns
- * MPF_ERR_UNSUPPORTED if a tile's halo exceeds h_cap (the plan is then
- * incomplete and must not be used). */
+ *   lidx  dev uint16 [nl][n]: sten[j][i] == halo[i / tile][lidx[j][i]]
+ * sten dev [nl][n]; 1 <= nl <= 64; tile 64, 128 or 256;
+ * 64 <= h_cap <= 64 tile.  The call waits for the stream (it reads back the
+ * largest halo) and returns MPF_ERR_UNSUPPORTED if a tile's halo exceeds
+ * h_cap (the plan is then incomplete and must not be used).
+ * mpf_tile_plan and mpf_tile_count are the same with tile = 64. */
 typedef struct {
   const int32_t* count;
   const int32_t* halo;
   const uint16_t* lidx;
   int32_t h_cap; /* row length of halo */
   int32_t h_max; /* the largest halo, as mpf_tile_plan returned it */
+  int32_t tile;  /* nodes per tile (0 is read as 64) */
 } mpf_tiles;
 int64_t mpf_tile_count(int64_t n);
+int64_t mpf_tile_count_sized(int64_t n, int tile);
 int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* count, int32_t* halo, uint16_t* lidx,
                   int32_t* h_max_host, void* stream);
+int mpf_tile_plan_sized(int64_t n, int nl, const int32_t* sten, int tile, int h_cap, int32_t* count, int32_t* halo,
+                        uint16_t* lidx, int32_t* h_max_host, void* stream);
 
 /* ------------------------------------------------------------- ACM step
  * Explicit artificial-compressibility Navier-Stokes steps (Sec. 2.3, Eqs.
@@ -289,13 +295,15 @@ int mpf_tile_plan(int64_t n, int nl, const int32_t* sten, int h_cap, int32_t* co
  *       (rows of boundary nodes are not read)
  * sten  dev [nl][n]
  * sn    dev [nl][nb]; wn dev [nl][nb] normal-derivative weights on sn
- * tiles the tile plan of sten (mpf_tile_plan) or NULL: with one or two
- *       lanes per node the interior passes then copy each 64-node tile's
- *       halo values into LDS and gather from there, when a block's halos fit
- *       64 KiB (h_max <= 819 for FP32 at one lane and for an FP64 state at
- *       two, 1638 for FP32 at two, 409 for an FP64 state at one); otherwise,
- *       and for NULL, they gather through the caches.  Results are the same
- *       bit for bit either way.
+ * tiles the tile plan of sten (mpf_tile_plan_sized) or NULL: with one or
+ *       two lanes per node the interior passes then copy each tile's halo
+ *       values into LDS and gather from there, when a block of 256 lanes
+ *       holds whole tiles (tile x lanes <= 256) and its halos fit 64 KiB
+ *       (64-node tiles: h_max <= 819 for FP32 at one lane and for an FP64
+ *       state at two, 1638 for FP32 at two, 409 for an FP64 state at one;
+ *       one 256-node tile at one lane or one 128-node tile at two: 3276 FP32,
+ *       1638 FP64); otherwise, and for NULL, they gather through the caches.
+ *       Results are the same bit for bit either way.
  * v     dev [3][n], p dev [n]: state, updated in place (v stays 0 on the
  *       boundary)
  * comp  dev float [4][n] for MPF_F32_KAHAN (NULL otherwise): the
@@ -373,11 +381,12 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  * flags dev uint32 [1] or NULL: bit 0 when a collided node has a non-finite
  *       density or velocity, bit 1 when |u|^2 >= 1/3 there (see the flags
  *       word above; MPF_ERR_DIVERGED when set at the end of the call)
- * tiles host pointer to the tile plan of sten (mpf_tile_plan), or NULL: the
- *       step then stages each tile's halo records in LDS and gathers from
- *       there when the largest halo's records fit 64 KiB, and reads the
- *       neighbours' records through the caches otherwise (and without a
- *       plan).  Results are the same bit for bit either way.
+ * tiles host pointer to the tile plan of sten with 64-node tiles
+ *       (mpf_tile_plan), or NULL: the step then stages each tile's halo
+ *       records in LDS and gathers from there when the largest halo's
+ *       records fit 64 KiB, and reads the neighbours' records through the
+ *       caches otherwise (and without a plan).  Results are the same bit for
+ *       bit either way.  A plan of another tile size is MPF_ERR_ARG.
  * q is 15 or 19.  A W larger than 512 MiB (twice the Infinity Cache) is read
  * with non-temporal loads so that it does not evict the gathered population
  * records; the results are the same bit for bit either way. */

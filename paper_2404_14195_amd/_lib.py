@@ -88,7 +88,7 @@ class LbmParams(ctypes.Structure):
 
 class Tiles(ctypes.Structure):
     _fields_ = [("count", ctypes.c_void_p), ("halo", ctypes.c_void_p), ("lidx", ctypes.c_void_p),
-                ("h_cap", ctypes.c_int32), ("h_max", ctypes.c_int32)]
+                ("h_cap", ctypes.c_int32), ("h_max", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class LbmUnits(ctypes.Structure):
@@ -120,6 +120,8 @@ def _load():
         "mpf_lbm_run": (i32, [vp, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
         "mpf_tile_count": (i64, [i64]),
         "mpf_tile_plan": (i32, [i64, i32, vp, i32, vp, vp, vp, vp, vp]),
+        "mpf_tile_count_sized": (i64, [i64, i32]),
+        "mpf_tile_plan_sized": (i32, [i64, i32, vp, i32, i32, vp, vp, vp, vp, vp]),
         "mpf_lbm_units_of": (i32, [dbl, dbl, dbl, dbl, vp, vp]),
         "mpf_permeability": (i32, [dbl, dbl, vp, dbl, vp]),
         "mpf_drag_coefficient": (i32, [dbl, dbl, dbl, dbl, dbl, vp]),
@@ -177,7 +179,7 @@ def lib():
 
 EXPORTED = ["mpf_strerror", "mpf_version", "mpf_create", "mpf_destroy", "mpf_acm_dt", "mpf_lbm_units_of",
             "mpf_permeability", "mpf_drag_coefficient", "mpf_residual", "mpf_flux_planes_noalloc", "mpf_pointwise",
-            "mpf_tile_count", "mpf_tile_plan",
+            "mpf_tile_count", "mpf_tile_plan", "mpf_tile_count_sized", "mpf_tile_plan_sized",
             "mpf_flux_planes_noalloc_max",
             "mpf_sc_cell", "mpf_weights_workspace", "mpf_rbffd_weights",
             "mpf_rbffd_weights_batched", "mpf_weights_autotune", "mpf_acm_workspace", "mpf_acm_run",

@@ -230,22 +230,22 @@ def lbm_units(h_min: float, nu: float, tau_plus: float, g, magic: float) -> dict
 
 
 class TilePlan:
-    """The tile plan of a stencil set (mpf_tile_plan): device arrays and the
-    mpf_tiles record that points at them."""
+    """The tile plan of a stencil set (mpf_tile_plan_sized; tile 64, 128 or
+    256 nodes): device arrays and the mpf_tiles record that points at them."""
 
-    def __init__(self, sten, h_cap: int = 1024):
+    def __init__(self, sten, h_cap: int = 1024, tile: int = 64):
         nl, n = sten.shape
         _need(sten, torch.int32, name="sten")
-        G = int(lib().mpf_tile_count(n))
+        G = int(lib().mpf_tile_count_sized(n, int(tile)))
         self.count = torch.empty(G + 1, dtype=torch.int32, device=sten.device)
         self.halo = torch.empty((G, h_cap), dtype=torch.int32, device=sten.device)
         self.lidx = torch.empty((nl, n), dtype=torch.int16, device=sten.device)  # the uint16 pattern
         hmax = ctypes.c_int32()
-        check(lib().mpf_tile_plan(n, nl, _p(sten), int(h_cap), _p(self.count), _p(self.halo), _p(self.lidx),
-                                  ctypes.byref(hmax), _stream()), "mpf_tile_plan")
-        self.h_cap, self.h_max = int(h_cap), hmax.value
+        check(lib().mpf_tile_plan_sized(n, nl, _p(sten), int(tile), int(h_cap), _p(self.count), _p(self.halo),
+                                        _p(self.lidx), ctypes.byref(hmax), _stream()), "mpf_tile_plan_sized")
+        self.h_cap, self.h_max, self.tile = int(h_cap), hmax.value, int(tile)
         self.rec = Tiles(count=_p(self.count), halo=_p(self.halo), lidx=_p(self.lidx), h_cap=self.h_cap,
-                         h_max=self.h_max)
+                         h_max=self.h_max, tile=self.tile)
 
 
 def lbm_run(prm: LbmParams, n_int: int, sten, W, unknown, f, f_tmp, n_steps: int, comp=None, flags=None,

@@ -40,7 +40,7 @@ namespace mpf {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kTile = 64;  // nodes per tile of the tile plan (mpf_tile_plan)
+constexpr int kTile = 64;  // nodes per tile of a plan that does not say (mpf_tile_plan)
 
 template <int LPN, typename T>
 __device__ __forceinline__ T group_sum(T x) {
@@ -403,18 +403,20 @@ struct Halo {
   const uint16_t* lidx;
   int h_cap;
   int h_max;
+  int tile;  // nodes per tile: 64, 128 or 256
 };
 
 // the tile's halo values of src into dst (this tile's LDS), four entries per
-// thread in flight; the tile's GT threads share the copy (entries past the
+// thread in flight; the tile's gt threads share the copy (entries past the
 // halo load a valid one and are not stored; named temporaries, so that
 // nothing is placed in scratch)
-template <int GT, typename R>
-__device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R* __restrict__ src, R* dst, int t) {
+template <typename R>
+__device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R* __restrict__ src, R* dst, int t,
+                                           int gt) {
   const int cnt = H.count[tile];
   const int32_t* hl = H.halo + tile * H.h_cap;
-  for (int c0 = t; c0 < cnt; c0 += 4 * GT) {
-    const int c1 = c0 + GT, c2 = c0 + 2 * GT, c3 = c0 + 3 * GT;
+  for (int c0 = t; c0 < cnt; c0 += 4 * gt) {
+    const int c1 = c0 + gt, c2 = c0 + 2 * gt, c3 = c0 + 3 * gt;
     const int i0 = hl[c0];
     const int i1 = hl[c1 < cnt ? c1 : c0];
     const int i2 = hl[c2 < cnt ? c2 : c0];
@@ -427,21 +429,22 @@ __device__ __forceinline__ void stage_halo(const Halo& H, int64_t tile, const R*
   }
 }
 
-// Thread layout of a staged pass with LPN lanes per node: a tile of 64 nodes
-// is 64 LPN consecutive threads (one wave at LPN = 1, two at LPN = 2); a block
-// holds kBlock / (64 LPN) tiles, each with h_max halo values in LDS.
+// Thread layout of a staged pass with LPN lanes per node: a tile of ts nodes
+// (64, 128 or 256, ts LPN <= kBlock) is gt = ts LPN consecutive threads; a
+// block holds kBlock / gt tiles, each with h_max halo values in LDS.
 template <int LPN>
 struct StagedIdx {
-  static constexpr int GT = kTile * LPN;  // threads per tile
   int64_t g, i, tile;
-  int sl, t, slot;
-  __device__ StagedIdx() {
+  int sl, t, slot, gt;
+  __device__ explicit StagedIdx(int ts) {
+    const int lg = __builtin_ctz((unsigned)ts);  // ts is a power of two
+    gt = ts * LPN;
     g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     i = g / LPN;
     sl = (int)(g % LPN);
-    tile = i / kTile;
-    t = threadIdx.x % GT;
-    slot = threadIdx.x / GT;
+    tile = i >> lg;
+    t = threadIdx.x & (gt - 1);
+    slot = threadIdx.x >> (lg + (LPN == 2 ? 1 : 0));
   }
 };
 
@@ -449,9 +452,9 @@ template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_predictor_st(Fields<T, TW> F, Halo H) {
   using R = typename Rec<T>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const StagedIdx<LPN> x;
+  const StagedIdx<LPN> x(H.tile);
   R* hv = reinterpret_cast<R*>(lds_raw) + x.slot * H.h_max;
-  if (x.tile * kTile < F.n_int) stage_halo<StagedIdx<LPN>::GT>(H, x.tile, reinterpret_cast<const R*>(F.V), hv, x.t);
+  if (x.tile * H.tile < F.n_int) stage_halo(H, x.tile, reinterpret_cast<const R*>(F.V), hv, x.t, x.gt);
   __syncthreads();
   if (x.i >= F.n_int) return;
   predictor_node<T, TW, LPN, NLC, KAHAN>(F, x.i, x.sl, [&](int64_t at) { return hv[H.lidx[at]]; });
@@ -462,9 +465,9 @@ __global__ __launch_bounds__(kBlock) void k_pressure_st(Fields<T, TW> F, const T
   using R = typename Rec<T>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const T coef = coupling_coef(F);
-  const StagedIdx<LPN> x;
+  const StagedIdx<LPN> x(H.tile);
   R* hv = reinterpret_cast<R*>(lds_raw) + x.slot * H.h_max;
-  if (x.tile * kTile < F.n_int) stage_halo<StagedIdx<LPN>::GT>(H, x.tile, reinterpret_cast<const R*>(vsrc), hv, x.t);
+  if (x.tile * H.tile < F.n_int) stage_halo(H, x.tile, reinterpret_cast<const R*>(vsrc), hv, x.t, x.gt);
   __syncthreads();
   if (x.i >= F.n_int) return;
   pressure_node<T, TW, LPN, NLC, KAHAN>(F, P, P, coef, x.i, x.sl, [&](int64_t at) { return hv[H.lidx[at]]; });
@@ -477,13 +480,13 @@ __global__ __launch_bounds__(kBlock) void k_pressure_edac_st(Fields<T, TW> F, co
   using R = typename Rec<T>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const T coef = coupling_coef(F);
-  const StagedIdx<LPN> x;
-  constexpr int tiles = kBlock / StagedIdx<LPN>::GT;
+  const StagedIdx<LPN> x(H.tile);
+  const int tiles = kBlock / x.gt;
   R* hv = reinterpret_cast<R*>(lds_raw) + x.slot * H.h_max;
   T* hp = reinterpret_cast<T*>(reinterpret_cast<R*>(lds_raw) + tiles * H.h_max) + x.slot * H.h_max;
-  if (x.tile * kTile < F.n_int) {
-    stage_halo<StagedIdx<LPN>::GT>(H, x.tile, reinterpret_cast<const R*>(vsrc), hv, x.t);
-    stage_halo<StagedIdx<LPN>::GT>(H, x.tile, pin, hp, x.t);
+  if (x.tile * H.tile < F.n_int) {
+    stage_halo(H, x.tile, reinterpret_cast<const R*>(vsrc), hv, x.t, x.gt);
+    stage_halo(H, x.tile, pin, hp, x.t, x.gt);
   }
   __syncthreads();
   if (x.i >= F.n_int) return;
@@ -496,9 +499,9 @@ template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_velocity_st(Fields<T, TW> F, const T* __restrict__ P, Halo H) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double red[kBlock / kWave];
-  const StagedIdx<LPN> x;
+  const StagedIdx<LPN> x(H.tile);
   T* hp = reinterpret_cast<T*>(lds_raw) + x.slot * H.h_max;
-  if (x.tile * kTile < F.n_int) stage_halo<StagedIdx<LPN>::GT>(H, x.tile, P, hp, x.t);
+  if (x.tile * H.tile < F.n_int) stage_halo(H, x.tile, P, hp, x.t, x.gt);
   __syncthreads();
   double mag = 0.0;
   if (x.i < F.n_int)
@@ -541,7 +544,7 @@ template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 int run_staged(Fields<T, TW>& F, const Halo& H, int n_steps, int n_p, bool edac, hipStream_t st) {
   using R = typename Rec<T>::type;
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
-  const size_t tiles = kBlock / (kTile * LPN);
+  const size_t tiles = kBlock / (H.tile * LPN);
   const size_t lv = tiles * H.h_max * sizeof(R), lp = tiles * H.h_max * sizeof(T);
   T* cur = F.p;
   for (int s = 0; s < n_steps; ++s) {
@@ -576,16 +579,17 @@ int run_staged(Fields<T, TW>& F, const Halo& H, int n_steps, int n_p, bool edac,
 constexpr size_t kAcmHaloLds = 64 * 1024;
 
 template <typename T>
-bool halo_fits(int lanes, int h_max) {
+bool halo_fits(int lanes, int h_max, int tile) {
   using R = typename Rec<T>::type;
-  return (lanes == 1 || lanes == 2) &&
-         (size_t)(kBlock / (kTile * lanes)) * (size_t)h_max * (sizeof(R) + sizeof(T)) <= kAcmHaloLds;
+  return (lanes == 1 || lanes == 2) && tile * lanes <= kBlock &&
+         (size_t)(kBlock / (tile * lanes)) * (size_t)h_max * (sizeof(R) + sizeof(T)) <= kAcmHaloLds;
 }
 
 template <typename T, typename TW, int LPN, int NLC, bool KAHAN>
 int run_launches(Fields<T, TW>& F, const Halo* H, int n_steps, int n_p, bool edac, hipStream_t st) {
   if constexpr (LPN <= 2) {
-    if (H && halo_fits<T>(LPN, H->h_max)) return run_staged<T, TW, LPN, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
+    if (H && halo_fits<T>(LPN, H->h_max, H->tile))
+      return run_staged<T, TW, LPN, NLC, KAHAN>(F, *H, n_steps, n_p, edac, st);
   }
   const unsigned gi = grid_for(F.n_int * LPN, kBlock), gb = grid_for(F.nb * LPN, kBlock);
   T* cur = F.p;  // the pressure of the current iteration (alternates with F.P1 when damped)
@@ -666,7 +670,7 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   Halo hd{};
   const Halo* H = nullptr;
   if (tiles) {
-    hd = Halo{tiles->count, tiles->halo, tiles->lidx, tiles->h_cap, tiles->h_max};
+    hd = Halo{tiles->count, tiles->halo, tiles->lidx, tiles->h_cap, tiles->h_max, tiles->tile ? tiles->tile : kTile};
     H = &hd;
   }
   int lanes = prm->lanes;
@@ -674,7 +678,7 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
     lanes = default_lanes<T>(n_int);
     // a one-lane pass whose halos do not fit LDS gathers through the caches;
     // two lanes per node halve the tiles per block, and staged they beat it
-    if (H && lanes == 1 && !halo_fits<T>(1, H->h_max) && halo_fits<T>(2, H->h_max)) lanes = 2;
+    if (H && lanes == 1 && !halo_fits<T>(1, H->h_max, H->tile) && halo_fits<T>(2, H->h_max, H->tile)) lanes = 2;
   }
   int rc;
   if constexpr (sizeof(T) == sizeof(float))  // the compensated state is FP32
@@ -724,7 +728,8 @@ extern "C" int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, 
       prm->lanes != 16)
     return MPF_ERR_ARG;
   if (tiles && (!tiles->count || !tiles->halo || !tiles->lidx || tiles->h_cap < 64 || tiles->h_max < 1 ||
-                tiles->h_max > tiles->h_cap))
+                tiles->h_max > tiles->h_cap ||
+                (tiles->tile != 0 && tiles->tile != 64 && tiles->tile != 128 && tiles->tile != 256)))
     return MPF_ERR_ARG;
   if (!ws || ws_bytes < mpf_acm_workspace(n, prec)) return MPF_ERR_WORKSPACE;
   if (n_steps == 0) return MPF_OK;

@@ -605,7 +605,7 @@ extern "C" int mpf_lbm_run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, 
   if (!precision_ok(prm->precision)) return MPF_ERR_ARG;
   if ((prm->precision == MPF_F32_KAHAN) != (comp != nullptr)) return MPF_ERR_ARG;
   if (tiles && (!tiles->count || !tiles->halo || !tiles->lidx || tiles->h_cap < 64 || tiles->h_max < 1 ||
-                tiles->h_max > tiles->h_cap))
+                tiles->h_max > tiles->h_cap || (tiles->tile != 0 && tiles->tile != kTile)))
     return MPF_ERR_ARG;
   if (n_steps == 0) return MPF_OK;
   hipStream_t st = as_stream(stream);

@@ -38,6 +38,7 @@ class Discretization:
         self.sten = api.solver_stencils(self.pos, self.n_int, nl)
         self._sten_host = None
         self._tiles = None
+        self._plans = {}
         self.nrm = t(cloud.nrm.T, torch.float64) if self.nb else torch.zeros((3, 0), dtype=torch.float64,
                                                                                device=self.device)
         # the Neumann rows and the drag's gradient rows use the surface stencils
@@ -55,14 +56,26 @@ class Discretization:
 
     @property
     def tiles(self):
-        """The tile plan of the stencils for the LDS-staged gather (built on
-        first use, once per discretization)."""
+        """The tile plan (64-node tiles) of the stencils for the LDS-staged
+        gather (built on first use, once per discretization)."""
         if self._tiles is None:
             try:
                 self._tiles = api.TilePlan(self.sten)
             except MPFError:  # a halo over the default capacity: the largest the plan takes
                 self._tiles = api.TilePlan(self.sten, h_cap=4096)
         return self._tiles
+
+    def tiles_of(self, tile: int):
+        """The tile plan with tiles of 64, 128 or 256 nodes (built on first
+        use, once per discretization and size)."""
+        if tile == 64:
+            return self.tiles
+        if tile not in self._plans:
+            try:
+                self._plans[tile] = api.TilePlan(self.sten, h_cap=16 * tile, tile=tile)
+            except MPFError:
+                self._plans[tile] = api.TilePlan(self.sten, h_cap=64 * tile, tile=tile)
+        return self._plans[tile]
 
     @property
     def sten_host(self):
@@ -78,8 +91,11 @@ class ACMSolver:
 
     def __init__(self, disc: Discretization, precision: int = MPF_F64, nu=1.0, rho=1.0, dt=None, beta=10.0,
                  v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False, check: bool = True,
-                 staged: bool = True):
+                 staged: bool = True, tile: int = 0):
         self.d, self.precision, self.check, self.staged = disc, precision, check, staged
+        # the staged passes' tile: one tile per block of 256 lanes (256 nodes at
+        # one lane per node, 128 at two) unless given
+        self.tile = tile or {1: 256, 2: 128}.get(lanes or self._default_lanes(disc.n_int, precision), 64)
         dt = api.acm_dt(disc.cloud.h_min, nu) if dt is None else dt
         self.prm = AcmParams(nu=nu, rho=rho, dt=dt, beta=beta, v_ref=v_ref, g=(ctypesarr(g)), n_p=n_p,
                              precision=precision, lanes=lanes, edac=int(bool(edac)), h_min=disc.cloud.h_min)
@@ -104,10 +120,18 @@ class ACMSolver:
         self.ws = api.acm_workspace(disc.n, precision, disc.device)
         self.steps = 0
 
+    @staticmethod
+    def _default_lanes(n_int: int, precision: int) -> int:
+        """The library's lanes per node when left to it (before the tile plan
+        is considered): 8 up to 12k interior nodes, 2 up to 50k, then 1, and
+        2 again above 500k for an FP64 state."""
+        fp64 = precision in (MPF_F64, MPF_MIXED)
+        return 8 if n_int <= 12000 else 2 if n_int <= 50000 else 2 if fp64 and n_int > 500000 else 1
+
     def run(self, n_steps: int):
-        # the tile plan is built once per discretization; the library stages
-        # where the lanes per node and the halos allow it
-        tiles = self.d.tiles if self.staged else None
+        # the tile plan is built once per discretization and tile size; the
+        # library stages where the lanes per node and the halos allow it
+        tiles = self.d.tiles_of(self.tile) if self.staged else None
         api.acm_run(self.prm, self.d.n_int, self.d.sten, self.w, self.d.sn, self.wn, self.v, self.p, self.vmax,
                     n_steps, self.ws, comp=self.comp, flags=self.flags if self.check else None, tiles=tiles)
         self.steps += n_steps
@@ -120,11 +144,13 @@ class ACMSolver:
         within 64 KiB."""
         if not self.staged:
             return False
-        n_int, fp64 = self.d.n_int, self.precision in (MPF_F64, MPF_MIXED)
+        fp64 = self.precision in (MPF_F64, MPF_MIXED)
         rec, val = (32, 8) if fp64 else (16, 4)
-        fits = lambda lanes: lanes <= 2 and (256 // (64 * lanes)) * self.d.tiles.h_max * (rec + val) <= 64 * 1024
-        lanes = self.prm.lanes or (8 if n_int <= 12000 else 2 if n_int <= 50000 else
-                                   2 if fp64 and n_int > 500000 else 1)
+        plan = self.d.tiles_of(self.tile)
+        ts = getattr(plan, "tile", 64)
+        fits = lambda lanes: (lanes <= 2 and ts * lanes <= 256 and
+                              (256 // (ts * lanes)) * plan.h_max * (rec + val) <= 64 * 1024)
+        lanes = self.prm.lanes or self._default_lanes(self.d.n_int, self.precision)
         if not self.prm.lanes and lanes == 1 and not fits(1) and fits(2):
             lanes = 2
         return fits(lanes)

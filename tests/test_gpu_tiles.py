@@ -30,14 +30,16 @@ def disc(small_cloud):
     return Discretization(small_cloud, nl=30, M=32)
 
 
-@pytest.mark.parametrize("nl", [30, 25, 50])
-def test_tile_plan_equals_the_definition(small_cloud, nl):
+@pytest.mark.parametrize("nl, tile", [(30, 64), (25, 64), (50, 64), (30, 128), (30, 256), (50, 256)])
+def test_tile_plan_equals_the_definition(small_cloud, nl, tile):
     """Halo lists and 16-bit positions equal the oracle's, on the 8k-node
-    cell (ragged last tile) and for the host fixture's stencils."""
+    cell (ragged last tile) and for the host fixture's stencils, for tiles of
+    64, 128 and 256 nodes."""
     from paper_2404_14195_amd import api
     S = nc.solver_stencils(small_cloud, nl)
-    plan = api.TilePlan(torch.as_tensor(np.ascontiguousarray(S.T), dtype=torch.int32, device="cuda"))
-    halos, lidx = O.tile_plan(S, 64)
+    plan = api.TilePlan(torch.as_tensor(np.ascontiguousarray(S.T), dtype=torch.int32, device="cuda"),
+                        h_cap=16 * tile, tile=tile)
+    halos, lidx = O.tile_plan(S, tile)
     count = plan.count.cpu().numpy()
     assert len(count) == len(halos) + 1 and count[-1] == max(len(h) for h in halos) == plan.h_max
     halo = plan.halo.cpu().numpy()
@@ -67,16 +69,19 @@ def test_staged_step_equals_cached_gather(disc, precision, q):
 
 @pytest.mark.parametrize("precision, lanes", [(1, 1), (1, 2), (3, 1), (3, 2), (0, 2), (2, 2)])
 @pytest.mark.parametrize("edac", [False, True])
-def test_staged_acm_equals_cached_gather(disc, precision, lanes, edac):
+@pytest.mark.parametrize("tile", [64, 0])
+def test_staged_acm_equals_cached_gather(disc, precision, lanes, edac, tile):
     """The ACM passes at one and two lanes per node, in every precision (FP32
     and compensated FP32 at both; FP64 and mixed, whose 40-byte halo entries
     fit four 64-node tiles only up to 409 entries, at two), with and without
-    the damped pressure equation: staged and cached gathers give the same
-    fields bit for bit (same values, same summation order), including the
-    running max |v|."""
+    the damped pressure equation, on 64-node tiles and on one tile per block
+    (256 nodes at one lane, 128 at two): staged and cached gathers give the
+    same fields bit for bit (same values, same summation order), including
+    the running max |v|."""
     from paper_2404_14195_amd.solvers import ACMSolver
-    a = ACMSolver(disc, precision=precision, lanes=lanes, edac=edac, staged=True)
+    a = ACMSolver(disc, precision=precision, lanes=lanes, edac=edac, staged=True, tile=tile)
     b = ACMSolver(disc, precision=precision, lanes=lanes, edac=edac, staged=False)
+    assert a.tile == (tile or 256 // lanes)
     assert a.staged_now()  # the halo fits: the staged passes run
     for s in (a, b):
         s.run(60)
@@ -125,9 +130,9 @@ def test_acm_takes_two_lanes_when_one_lane_halos_do_not_fit(mid_disc):
     assert plan.h_max <= 819 < 900 <= plan.h_cap
     big = SimpleNamespace(rec=Tiles(count=plan.rec.count, halo=plan.rec.halo, lidx=plan.rec.lidx,
                                     h_cap=plan.h_cap, h_max=900), h_max=900, h_cap=plan.h_cap)
-    a = ACMSolver(d, precision=MPF_F32)  # lanes from the library
-    b = ACMSolver(d, precision=MPF_F32, lanes=2)
-    one = ACMSolver(d, precision=MPF_F32, lanes=1)
+    a = ACMSolver(d, precision=MPF_F32, tile=64)  # lanes from the library
+    b = ACMSolver(d, precision=MPF_F32, lanes=2, tile=64)
+    one = ACMSolver(d, precision=MPF_F32, lanes=1, tile=64)
     try:
         d._tiles = big
         assert a.staged_now()
