@@ -144,3 +144,22 @@ def test_acm_takes_two_lanes_when_one_lane_halos_do_not_fit(mid_disc):
     assert torch.equal(a.v, b.v) and torch.equal(a.p, b.p) and torch.equal(a.vmax, b.vmax)
     # one lane per node sums in another order: equal to rounding only
     assert torch.allclose(one.v, b.v, rtol=1e-4, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision, lanes, tile, staged", [(1, 1, 128, True), (3, 1, 128, True), (0, 1, 128, False),
+                                                             (1, 2, 256, False), (0, 2, 256, False)])
+def test_staged_acm_other_tile_sizes(disc, precision, lanes, tile, staged):
+    """Two 128-node tiles per block at one lane per node run staged for an
+    FP32 state; for an FP64 state their two halos (over 819 entries each on
+    this cell) exceed 64 KiB, and a 256-node tile at two lanes (512 lanes,
+    more than a block) is no block's tile: both fall back to the cached
+    gather.  Either way the fields equal the cached gather's bit for bit."""
+    from paper_2404_14195_amd.solvers import ACMSolver
+    a = ACMSolver(disc, precision=precision, lanes=lanes, staged=True, tile=tile)
+    b = ACMSolver(disc, precision=precision, lanes=lanes, staged=False)
+    if precision == 0 and lanes == 1:
+        assert disc.tiles_of(128).h_max > 819
+    assert a.staged_now() == staged
+    for s in (a, b):
+        s.run(60)
+    assert torch.equal(a.v, b.v) and torch.equal(a.p, b.p) and torch.equal(a.vmax, b.vmax)
