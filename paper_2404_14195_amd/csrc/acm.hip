@@ -35,12 +35,17 @@
 // passes and a replayed HIP graph were both slower than plain launches once
 // the gather chain was split 8 ways (126 -> 50 us per step).
 #include "common.hpp"
+#include "graph.hpp"
 
 namespace mpf {
 namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 64;  // nodes per tile of a plan that does not say (mpf_tile_plan)
+// cells whose long runs replay a captured graph: on the 8k-node cell the
+// step drops 8 % (41.0 -> 37.8 us FP32), on the 71k-node one it is 1 % slower
+constexpr int64_t kGraphNodes = 50000;
+constexpr int kGraphSteps = 16;
 
 template <int LPN, typename T>
 __device__ __forceinline__ T group_sum(T x) {
@@ -680,12 +685,17 @@ int run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, const int32
     // two lanes per node halve the tiles per block, and staged they beat it
     if (H && lanes == 1 && !halo_fits<T>(1, H->h_max, H->tile) && halo_fits<T>(2, H->h_max, H->tile)) lanes = 2;
   }
-  int rc;
-  if constexpr (sizeof(T) == sizeof(float))  // the compensated state is FP32
-    rc = comp ? launch_lanes<T, TW, true>(F, H, lanes, n_steps, prm->n_p, edac, st)
-              : launch_lanes<T, TW, false>(F, H, lanes, n_steps, prm->n_p, edac, st);
-  else
-    rc = launch_lanes<T, TW, false>(F, H, lanes, n_steps, prm->n_p, edac, st);
+  // a step is 1 + 3 n_p launches; on cells of up to kGraphNodes nodes their
+  // launch overhead is a large part of the step, and long runs replay a
+  // captured graph of kGraphSteps steps
+  auto steps = [&](int k, hipStream_t s) {
+    if constexpr (sizeof(T) == sizeof(float))  // the compensated state is FP32
+      return comp ? launch_lanes<T, TW, true>(F, H, lanes, k, prm->n_p, edac, s)
+                  : launch_lanes<T, TW, false>(F, H, lanes, k, prm->n_p, edac, s);
+    else
+      return launch_lanes<T, TW, false>(F, H, lanes, k, prm->n_p, edac, s);
+  };
+  const int rc = run_steps(n_steps, n <= kGraphNodes ? kGraphSteps : 0, steps, st);
   if (rc) return rc;
   hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.V, v);
   if (comp) hipLaunchKernelGGL(from_records<T>, dim3(gn), dim3(kBlock), 0, st, n, (const T*)F.VL, comp);

@@ -1,0 +1,65 @@
+// Replaying a captured HIP graph for long runs of launch-bound steps.
+#pragma once
+#include <map>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace mpf {
+
+// A stream per device for stream capture (created once, default priority,
+// not synchronising with the null stream: capture executes nothing).
+inline int capture_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  MPF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t s = nullptr;
+    MPF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    it = streams.emplace(dev, s).first;
+  }
+  *out = it->second;
+  return MPF_OK;
+}
+
+// Runs launch(k, stream), which enqueues k steps on stream, for n_steps steps
+// on st.  With at least two graphs' worth of steps, graph_steps steps are
+// captured once into a graph that is then launched n_steps / graph_steps
+// times, and the rest is enqueued directly: the same kernels with the same
+// arguments in the same order, so the results are the same bit for bit; what
+// changes is the host's launch overhead, which bounds the steps of small
+// cells.  The call then waits for st before it frees the graph.
+template <typename L>
+int run_steps(int n_steps, int graph_steps, L&& launch, hipStream_t st) {
+  if (graph_steps < 1 || n_steps < 2 * graph_steps) return launch(n_steps, st);
+  hipStream_t cs = nullptr;
+  int rc = capture_stream(&cs);
+  if (rc) return rc;
+  MPF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  rc = launch(graph_steps, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  if (rc || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : MPF_ERR_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return MPF_ERR_HIP;
+  }
+  const int reps = n_steps / graph_steps;
+  for (int r = 0; r < reps && rc == MPF_OK; ++r)
+    if (hipGraphLaunch(ex, st) != hipSuccess) rc = MPF_ERR_HIP;
+  if (rc == MPF_OK && n_steps > reps * graph_steps) rc = launch(n_steps - reps * graph_steps, st);
+  const hipError_t es = hipStreamSynchronize(st);
+  (void)hipGraphExecDestroy(ex);
+  (void)hipGraphDestroy(g);
+  if (rc == MPF_OK && es != hipSuccess) rc = MPF_ERR_HIP;
+  return rc;
+}
+
+}  // namespace mpf
