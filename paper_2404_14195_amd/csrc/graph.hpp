@@ -31,25 +31,27 @@ inline int capture_stream(hipStream_t* out) {
 // times, and the rest is enqueued directly: the same kernels with the same
 // arguments in the same order, so the results are the same bit for bit; what
 // changes is the host's launch overhead, which bounds the steps of small
-// cells.  The call then waits for st before it frees the graph.
+// cells.  The call then waits for st before it frees the graph.  A caller's
+// stream that is itself being captured gets direct launches (no nested
+// capture, no wait), and so does any run whose capture cannot be set up
+// (nothing has been enqueued on st at that point).
 template <typename L>
 int run_steps(int n_steps, int graph_steps, L&& launch, hipStream_t st) {
   if (graph_steps < 1 || n_steps < 2 * graph_steps) return launch(n_steps, st);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return launch(n_steps, st);
   hipStream_t cs = nullptr;
-  int rc = capture_stream(&cs);
-  if (rc) return rc;
-  MPF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  rc = launch(graph_steps, cs);
+  if (capture_stream(&cs) != MPF_OK) return launch(n_steps, st);
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return launch(n_steps, st);
+  int rc = launch(graph_steps, cs);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &g);
-  if (rc || ec != hipSuccess || !g) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc ? rc : MPF_ERR_HIP;
-  }
   hipGraphExec_t ex = nullptr;
-  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    return MPF_ERR_HIP;
+  if (rc || ec != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();  // a failed capture leaves no work behind: launch directly
+    return launch(n_steps, st);
   }
   const int reps = n_steps / graph_steps;
   for (int r = 0; r < reps && rc == MPF_OK; ++r)

@@ -57,3 +57,29 @@ def test_acm_graph_run_reports_divergence(disc):
     s.v[0, 7] = float("nan")
     with pytest.raises(MPFDiverged):
         s.run(64)
+
+
+def test_acm_run_inside_a_callers_graph_capture(disc):
+    """Called on a stream that the caller is capturing (no flags word, so no
+    wait inside the call), the run enqueues its kernels directly into the
+    caller's graph; three replays, with eager work between them, equal three
+    eager runs of the same length bit for bit."""
+    from paper_2404_14195_amd.solvers import ACMSolver
+    a = ACMSolver(disc, precision=1, check=False)
+    b = ACMSolver(disc, precision=1, check=False)
+    a.run(10)
+    b.run(10)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            a.run(40)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        b.run(40)
+        torch.cuda.synchronize()
+        assert a.permeability() == b.permeability()  # eager work between the replays
+        assert torch.equal(a.v, b.v) and torch.equal(a.p, b.p) and torch.equal(a.vmax, b.vmax)
