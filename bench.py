@@ -1420,7 +1420,7 @@ def main():
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
                                    "note only)"}))
         sys.exit(2)
 
