@@ -1357,6 +1357,8 @@ def main():
     ap.add_argument("--no-steady", action="store_true", help="skip the time-to-steady measurement")
     ap.add_argument("--no-warm", action="store_true", help="time-to-steady without the learned warm start")
     ap.add_argument("--mlp", action="store_true", help="only the warm-start network's training throughput")
+    ap.add_argument("--mlp-batches", type=int, nargs="+", default=None,
+                    help="with --mlp: the fused training step at these batch sizes only")
     ap.add_argument("--c5", choices=["train", "eval"], default=None,
                     help="the learned warm start at its benchmark scale: train (64 cells of ~200k nodes) or eval "
                          "(held-out radii, warm vs cold vs the no-network ablation)")
@@ -1509,6 +1511,10 @@ def main():
         return
     if args.mlp:
         torch.cuda.set_device(0)
+        if args.mlp_batches:  # the fused step's cost against the batch (tiles per block)
+            print(json.dumps({"mlp_training_batches": [mlp_training_throughput(torch, api, batch=b, variants=("fused",))
+                                                       for b in args.mlp_batches]}))
+            return
         print(json.dumps({"mlp_training": mlp_training_throughput(torch, api)}))
         return
     if args.weights_batch:
