@@ -1317,14 +1317,19 @@ def acm_and_weights(torch, nc, api):
 def lbm_large(torch, nc, steps=300):
     """The MLBM step on a cell whose weights (2.8 GB FP32) cannot sit in the
     256 MB Infinity Cache: r = 0.3, h(d) = min(0.003 + 0.16 d, 0.015), seed 2."""
-    from paper_2404_14195_amd import MPF_F32, MPF_F64, MPF_MIXED
+    from paper_2404_14195_amd import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED
     from paper_2404_14195_amd.solvers import Discretization, MLBMSolver
     t0 = time.perf_counter()
     cloud = nc.sphere_cloud(0.3, 0.003, 0.16, 0.015, seed=2)
     disc = Discretization(cloud, nl=30, M=64)
     print(f"[bench] lbm_large: {cloud.n} nodes, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     rec = {"n_nodes": cloud.n, "n_boundary": cloud.n_bnd, "steps": steps}
-    for name, prec, sw, sf in (("fp32", MPF_F32, 4, 4), ("mixed", MPF_MIXED, 4, 8), ("fp64", MPF_F64, 8, 8)):
+    # the FP32 states stage their tiles' halo records (80-byte records, when a
+    # tile's fit 64 KiB): 2-byte stencil positions plus the halo lists
+    staged32 = disc.tiles.h_max * 80 <= 64 * 1024
+    halo_b = 4.0 * int(disc.tiles.count[:-1].sum().item()) / disc.n if staged32 else 0.0
+    for name, prec, sw, sf, sc in (("fp32", MPF_F32, 4, 4, 0), ("fp32_kahan", MPF_F32_KAHAN, 4, 4, 4),
+                                   ("mixed", MPF_MIXED, 4, 8, 0), ("fp64", MPF_F64, 8, 8, 0)):
         s = MLBMSolver(disc, q=19, precision=prec)
         s.run(20)
         torch.cuda.synchronize()
@@ -1335,8 +1340,10 @@ def lbm_large(torch, nc, steps=300):
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
-        bpn = bytes_per_node_step(19, 30, sw, sf)
-        rec[name] = {"us_per_step": ms * 1e3, "node_steps_per_s": cloud.n / (ms * 1e-3),
+        staged = staged32 and sf == 4
+        bpn = bytes_per_node_step(19, 30, sw, sf, s_i=2 if staged else 4, s_comp=sc, halo=halo_b if staged else 0.0)
+        rec[name] = {"us_per_step": ms * 1e3, "node_steps_per_s": cloud.n / (ms * 1e-3), "staged": staged,
+                     "bytes_per_node_step": bpn,
                      "hbm_frac": bpn * cloud.n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "k": s.permeability()}
         print(f"[bench] lbm_large {name}: {ms * 1e3:.1f} us/step, {rec[name]['node_steps_per_s']:.3e} node-steps/s, "
               f"{rec[name]['hbm_frac']:.2f} of HBM", file=sys.stderr, flush=True)
