@@ -388,9 +388,10 @@ int mpf_acm_run(const mpf_acm_params* prm, int64_t n, int64_t n_int, int nl, con
  * tiles host pointer to the tile plan of sten with 64-node tiles
  *       (mpf_tile_plan), or NULL: the step then stages each tile's halo
  *       records in LDS and gathers from there when the largest halo's
- *       records fit 64 KiB, and reads the neighbours' records through the
- *       caches otherwise (and without a plan).  Results are the same bit for
- *       bit either way.  A plan of another tile size is MPF_ERR_ARG.
+ *       records fit 64 KiB (80 KiB for MPF_F64), and reads the neighbours'
+ *       records through the caches otherwise (and without a plan).  Results
+ *       are the same bit for bit either way.  A plan of another tile size is
+ *       MPF_ERR_ARG.
  * q is 15 or 19.  A W larger than 512 MiB (twice the Infinity Cache) is read
  * with non-temporal loads so that it does not evict the gathered population
  * records; the results are the same bit for bit either way. */

@@ -248,10 +248,13 @@ constexpr size_t step_part_bytes() { return sizeof(T) * step_waves<TW, T>() * (Q
 
 // The compensated state's FP64 epilogue would take 94 VGPRs (two 8-wave
 // blocks per CU); capped at 80 (three blocks, a few values spilled in the
-// epilogue) the step is 6-7 % faster on the 71k and 581k-node cells.
+// epilogue) the step is 6-7 % faster on the 71k and 581k-node cells.  The
+// staged FP64 kernel is bounded the other way (at most four waves per SIMD):
+// with its LDS sized at launch the compiler would otherwise aim at an
+// occupancy that its two blocks per CU never reach and cut its registers.
 template <typename TW, typename T, int Q, bool COLLIDE, bool STREAM_W, bool KAHAN, bool HALO>
 __global__ __launch_bounds__((step_waves<TW, T>() * kWave))
-__attribute__((amdgpu_waves_per_eu(KAHAN ? 6 : 1))) void lbm_step(
+__attribute__((amdgpu_waves_per_eu(KAHAN ? 6 : 1, (sizeof(TW) == 8 && HALO) ? 4 : 8))) void lbm_step(
     int64_t n, int64_t n_int, int nl, const int32_t* __restrict__ sten, const TW* __restrict__ W,
     const uint32_t* __restrict__ unknown, const T* __restrict__ src, T* __restrict__ dst, T* __restrict__ comp,
     Prm<typename Compute<T, KAHAN>::type> pr, uint32_t* __restrict__ flags, TileArg tp) {
@@ -480,10 +483,15 @@ __global__ __launch_bounds__(kBlock) void lbm_unknown(int64_t nb, int64_t n, int
 constexpr double kStreamWeightsBytes = 512.0 * 1024 * 1024;
 
 // LDS staging is used when the largest halo fits this many bytes of
-// records: 64 KiB keeps three 8-wave FP32 blocks per CU at the step kernel's
-// register use, and holds halos of up to 819 FP32 or 409 FP64 records
-// (the refined clouds here: about 350 on average, 500 at most).
-constexpr size_t kHaloLdsBytes = 64 * 1024;
+// records: 64 KiB for FP32 records keeps three 8-wave blocks per CU at the
+// step kernel's register use (halos of up to 819 records); the FP64 kernel
+// holds two blocks per CU at its register use anyway, so 80 KiB (512 records)
+// costs it no occupancy (the refined clouds here: about 350 on average, 500
+// at most; on the 71k-node cell its step drops from 88.9 to 74.8 us).  The
+// mixed kernel (FP32 weights, FP64 state) keeps 64 KiB: staged at 80 KiB it
+// was slower (50.2 -> 55.4 us).
+template <typename TW, typename T>
+constexpr size_t halo_lds_bytes() { return sizeof(T) == 8 && sizeof(TW) == 8 ? 80 * 1024 : 64 * 1024; }
 
 template <typename TW, typename T, int Q, bool STREAM_W, bool KAHAN, bool HALO>
 void launch_steps(int64_t n, int64_t n_int, int nl, const int32_t* sten, const TW* W, const uint32_t* unknown,
@@ -516,7 +524,7 @@ int run(const mpf_lbm_params* prm, int64_t n, int64_t n_int, int nl, const int32
   constexpr int QP = Pad<Q>::QP;
   const size_t part = step_part_bytes<TW, T, Q>();
   const size_t halo_bytes = tiles ? (size_t)tiles->h_max * QP * sizeof(T) : 0;
-  const bool halo = tiles && halo_bytes <= kHaloLdsBytes;
+  const bool halo = tiles && halo_bytes <= halo_lds_bytes<TW, T>();
   const TileArg tp{tiles ? tiles->count : nullptr, tiles ? tiles->halo : nullptr, tiles ? tiles->lidx : nullptr,
                    tiles ? tiles->h_cap : 0};
   const size_t lds = halo ? (halo_bytes > part ? halo_bytes : part) : 0;  // else static
