@@ -93,9 +93,7 @@ class ACMSolver:
                  v_ref=1e-3, g=(1.0, 0.0, 0.0), n_p=3, lanes: int = 0, edac: bool = False, check: bool = True,
                  staged: bool = True, tile: int = 0):
         self.d, self.precision, self.check, self.staged = disc, precision, check, staged
-        # the staged passes' tile: one tile per block of 256 lanes (256 nodes at
-        # one lane per node, 128 at two) unless given
-        self.tile = tile or {1: 256, 2: 128}.get(lanes or self._default_lanes(disc.n_int, precision), 64)
+        self.tile = tile or self._block_tile(lanes or self._default_lanes(disc.n_int, precision))
         dt = api.acm_dt(disc.cloud.h_min, nu) if dt is None else dt
         self.prm = AcmParams(nu=nu, rho=rho, dt=dt, beta=beta, v_ref=v_ref, g=(ctypesarr(g)), n_p=n_p,
                              precision=precision, lanes=lanes, edac=int(bool(edac)), h_min=disc.cloud.h_min)
@@ -119,6 +117,12 @@ class ACMSolver:
         self.flags = torch.zeros(1, dtype=torch.int32, device=disc.device)
         self.ws = api.acm_workspace(disc.n, precision, disc.device)
         self.steps = 0
+
+    @staticmethod
+    def _block_tile(lanes: int) -> int:
+        """The staged passes' tile: one tile per block of 256 lanes (256 nodes
+        at one lane per node, 128 at two); 64 where the passes do not stage."""
+        return {1: 256, 2: 128}.get(lanes, 64)
 
     @staticmethod
     def _default_lanes(n_int: int, precision: int) -> int:

@@ -1,6 +1,6 @@
-"""Host-side stop control of the solvers (no GPU): the paper's stopping
-criterion, Eq. stopCrit, on stand-in solvers whose permeability history is
-known exactly."""
+"""Host-side logic of the solvers (no GPU): the paper's stopping criterion,
+Eq. stopCrit, on stand-in solvers whose permeability history is known
+exactly, and the ACM's lane and tile choice."""
 import math
 
 import pytest
@@ -60,3 +60,20 @@ def test_running_out_of_steps_and_bad_input():
         run_to_paper_criterion(History(lambda t: t, 1.0), every=0)
     with pytest.raises(ValueError):
         run_to_paper_criterion(History(lambda t: t, 1.0), tol=0.0)
+
+
+def test_acm_lane_and_tile_choice():
+    """The host mirror of the library's lane rule (8 lanes per node up to
+    12,000 interior nodes, 2 up to 50,000, then 1, and 2 again above 500,000
+    for an FP64 state) and the staged passes' tile (one per block of 256
+    lanes)."""
+    from paper_2404_14195_amd import MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED
+    from paper_2404_14195_amd.solvers import ACMSolver
+    L = ACMSolver._default_lanes
+    for prec in (MPF_F32, MPF_F32_KAHAN, MPF_F64, MPF_MIXED):
+        assert L(8000, prec) == 8 and L(12000, prec) == 8 and L(12001, prec) == 2 and L(50000, prec) == 2
+        assert L(50001, prec) == 1 and L(500000, prec) == 1
+    assert L(500001, MPF_F32) == 1 and L(500001, MPF_F32_KAHAN) == 1
+    assert L(500001, MPF_F64) == 2 and L(500001, MPF_MIXED) == 2
+    T = ACMSolver._block_tile
+    assert (T(1), T(2), T(4), T(8), T(16)) == (256, 128, 64, 64, 64)
